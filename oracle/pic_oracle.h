@@ -1,0 +1,54 @@
+/*
+ * pic_oracle.h -- declarations of the double-precision CPU reference of the
+ * charge-conserving PIC step (arXiv:1101.0809).  TEST INFRASTRUCTURE: only the
+ * test suite, the smoke check and the benchmark's CPU baseline use it.  See
+ * pic_oracle.c for the conventions (cell units, storage order, staggering).
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+
+#include <stdint.h>
+
+typedef struct orc_grid {
+    int64_t nx, ny, nz;  /* cells per axis, periodic */
+    double dx, dy, dz;   /* cell sizes */
+    double dt;           /* time step */
+    double c;            /* speed of light */
+    double bext[3];      /* uniform external B added at the gather */
+} orc_grid;
+
+typedef struct orc_species {
+    int64_t n;             /* particle count */
+    double q;              /* charge per unit weight */
+    double m;              /* mass per unit weight */
+    int32_t mobile;        /* 0: immobile (charge only) */
+    int32_t deposit;       /* 0: test particles, no current */
+    double* x;             /* [3][n] positions in cell units, in [0, N) */
+    double* w;             /* [3][n] momentum over mass, w^{n-1/2} */
+    const double* weight;  /* [n] macro-particle weight */
+} orc_species;
+
+double orc_shape(int l, double r);
+double orc_cumulative1(double s);
+void orc_gather(const orc_grid* g, const double* fields, const double xp[3], double Ep[3],
+                double Bp[3]);
+void orc_push(double q_over_m, double dt, double c, const double Ep[3], const double Bp[3],
+              double w[3]);
+void orc_displacement(const orc_grid* g, const double w[3], double dxp[3]);
+void orc_deposit(const orc_grid* g, const double x0[3], const double x1[3], double charge,
+                 double* J);
+void orc_deposit_quarter(const orc_grid* g, const double x0[3], const double x1[3],
+                         double charge, double* J);
+void orc_rho_add(const orc_grid* g, const double xp[3], double charge, double* rho);
+void orc_rho(const orc_grid* g, int nsp, const orc_species* sp, double* rho);
+void orc_half_b(const orc_grid* g, double* fields);
+void orc_update_e(const orc_grid* g, double* fields);
+void orc_particle_step(const orc_grid* g, const double* fields, const orc_species* s,
+                       double* J);
+void orc_step(const orc_grid* g, double* fields, int nsp, const orc_species* sp, int nsteps);
+void orc_gauss_residual(const orc_grid* g, const double* fields, const double* rho, double* R);
+void orc_div_b(const orc_grid* g, const double* fields, double* D);
+void orc_energies(const orc_grid* g, const double* fields, int nsp, const orc_species* sp,
+                  double out[4]);
+
+#endif

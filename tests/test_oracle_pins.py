@@ -1,0 +1,477 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numerical
+integration of the definitions, exact identities stated in the paper, closed
+forms (gyration, cold plasma oscillation, vacuum dispersion, self-force) or
+values printed in the paper (tests/golden/paper_values.json).  Section and
+equation names refer to arXiv:1101.0809.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import picgen
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+RNG = np.random.Generator(np.random.PCG64(20110105))
+
+
+# --------------------------------------------------------------------------
+# Q1  form factors (Section 3.1, Section 4.5)
+# --------------------------------------------------------------------------
+
+def _cap(r):
+    return 1.0 if abs(r) <= 0.5 else 0.0
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_form_factor_is_recursive_integral(l):
+    """f^(l)(r) equals the integral of f^(l-1) over [r-1/2, r+1/2] (Section 3.1);
+    the order-0 base is the unit cap."""
+    lower = _cap if l == 1 else (lambda t: oracle.shape(l - 1, t))
+    knots = [k * 0.5 for k in range(-6, 7)]
+    for r in np.concatenate([RNG.uniform(-2.5, 2.5, 40), [0.0, 0.5, 1.0, 1.5, -0.25]]):
+        pts = [p for p in knots if r - 0.5 < p < r + 0.5]
+        ref, _ = integrate.quad(lower, r - 0.5, r + 0.5, points=pts or None, epsabs=1e-14,
+                                epsrel=1e-13)
+        assert oracle.shape(l, r) == pytest.approx(ref, abs=1e-12)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_form_factor_symmetry_support_partition(l):
+    """Symmetric in r, zero for |r| > (l+1)/2, and sum_i f(x+i) = 1 (Eq. sum1)."""
+    for r in RNG.uniform(0, 3, 30):
+        assert oracle.shape(l, r) == oracle.shape(l, -r)
+        if r > (l + 1) / 2:
+            assert oracle.shape(l, r) == 0.0
+    for x in RNG.uniform(-0.5, 0.5, 30):
+        s = sum(oracle.shape(l, x + i) for i in range(-4, 5))
+        assert s == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_form_factor_derivative_identity(l):
+    """d f^(l)/dr = f^(l-1)(r + 1/2) - f^(l-1)(r - 1/2) (Section 3.1, property 3)."""
+    lower = _cap if l == 1 else (lambda t: oracle.shape(l - 1, t))
+    h = 1e-7
+    for r in RNG.uniform(-2.2, 2.2, 30):
+        if min(abs(r - k * 0.5) for k in range(-6, 7)) < 1e-4:
+            continue
+        fd = (oracle.shape(l, r + h) - oracle.shape(l, r - h)) / (2 * h)
+        assert fd == pytest.approx(lower(r + 0.5) - lower(r - 0.5), abs=1e-6)
+
+
+def test_cumulative_is_integral_of_hat():
+    """F_i(x_p) = integral of f^(1) up to the node (Section 3.1)."""
+    for s in np.concatenate([RNG.uniform(-1.5, 1.5, 40), [-1.0, 0.0, 1.0]]):
+        ref, _ = integrate.quad(lambda t: oracle.shape(1, t), -2.0, s, points=[-1, 0, 1],
+                                epsabs=1e-14)
+        assert oracle.cumulative1(s) == pytest.approx(ref, abs=1e-13)
+
+
+def test_alternating_order_table_1p5():
+    """Oracle point and cell weights equal the printed order-1 1/2 table (Section 4.5)."""
+    for xp in RNG.uniform(0, 10, 40):
+        i = math.floor(xp)
+        d = xp - i
+        assert oracle.shape(1, i - xp) == pytest.approx(1 - d, abs=1e-15)
+        assert oracle.shape(1, i + 1 - xp) == pytest.approx(d, abs=1e-15)
+        table = [(1 - d) ** 2 / 2, 0.75 - (0.5 - d) ** 2, d ** 2 / 2]
+        for o, ref in zip((-1, 0, 1), table):
+            assert oracle.shape(2, (i + o) + 0.5 - xp) == pytest.approx(ref, abs=1e-15)
+
+
+def test_alternating_order_table_2p5():
+    """The order-2 1/2 table of Section 4.5 equals f^(2) at nodes and f^(3) at
+    cell centres (the oracle's shape functions one order up)."""
+    for xp in RNG.uniform(0, 10, 40):
+        i = math.floor(xp + 0.5)
+        d = xp + 0.5 - i
+        fnode = [(1 - d) ** 2 / 2, 0.75 - (0.5 - d) ** 2, d ** 2 / 2]
+        for o, ref in zip((-1, 0, 1), fnode):
+            assert oracle.shape(2, (i + o) - xp) == pytest.approx(ref, abs=1e-14)
+        fcell = [(1 - d) ** 3 / 6, (2 - d) ** 3 / 6 - 2 * (1 - d) ** 3 / 3,
+                 (1 + d) ** 3 / 6 - 2 * d ** 3 / 3, d ** 3 / 6]
+        for o, ref in zip((-2, -1, 0, 1), fcell):
+            assert oracle.shape(3, (i + o) + 0.5 - xp) == pytest.approx(ref, abs=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Q2-Q4  current and charge (Section 3.2)
+# --------------------------------------------------------------------------
+
+def test_cumulative_sum_identity():
+    """sum_i [F_i(x) - F_i(x')] = x' - x (Eq. sumcurrent)."""
+    for _ in range(30):
+        x = RNG.uniform(3, 7)
+        xq = x + RNG.uniform(-1.5, 1.5)
+        s = sum(oracle.cumulative1(i - x) - oracle.cumulative1(i - xq) for i in range(-2, 14))
+        assert s == pytest.approx(xq - x, abs=1e-14)
+
+
+def _grid(n=8, dt=0.4, **kw):
+    return oracle.Grid(n, n, n, dt, **kw)
+
+
+def test_face_sum_equals_velocity():
+    """sum over faces of xi^x equals u^x (Section 3.2, exact relationship)."""
+    g = _grid(10, dt=0.37, dx=1.3, dy=0.8, dz=1.1)
+    V = g.dx * g.dy * g.dz
+    for _ in range(20):
+        x0 = RNG.uniform(2, 8, 3)
+        x1 = x0 + RNG.uniform(-0.95, 0.95, 3)
+        J = oracle.deposit(g, x0, x1, charge=1.0)
+        h = np.array([g.dx, g.dy, g.dz])
+        u = (x1 - x0) * h / g.dt
+        for a in range(3):
+            assert J[a].sum() * V == pytest.approx(u[a], abs=1e-14)
+
+
+def _box_path_current(x0, x1, n, dt, h):
+    """Mean over the six axis orderings of the box-path integrals of Eq. Jx
+    (Section 3.2).  F_i and Delta F are obtained by numerical integration of the
+    hat function (their definitions, Eq. intff), not from closed forms."""
+    hat = lambda t: max(0.0, 1.0 - abs(t))
+
+    def F(i, xp):  # cumulative form factor at node i
+        lo = min(i, xp - 1.0)
+        return integrate.quad(lambda t: hat(t - xp), lo - 1.0, i,
+                              points=[xp - 1, xp, xp + 1], epsabs=1e-15, limit=200)[0]
+
+    def dF(c, xp):  # integral over the cell [c, c+1]
+        return integrate.quad(lambda t: hat(t - xp), c, c + 1, points=[xp - 1, xp, xp + 1],
+                              epsabs=1e-15, limit=200)[0]
+
+    import itertools
+    J = np.zeros((3, n, n, n))
+    lo = np.floor(np.minimum(x0, x1)).astype(int) - 2
+    hi = np.floor(np.maximum(x0, x1)).astype(int) + 3
+    for order in itertools.permutations(range(3)):
+        p = np.array(x0, dtype=float)
+        for axis in order:
+            q = p.copy()
+            q[axis] = x1[axis]
+            t1, t2 = (axis + 1) % 3, (axis + 2) % 3
+            for a in range(lo[axis], hi[axis] + 1):
+                dfa = F(a, q[axis]) - F(a, p[axis])
+                if dfa == 0.0:
+                    continue
+                for b in range(lo[t1], hi[t1] + 1):
+                    for c in range(lo[t2], hi[t2] + 1):
+                        ijk = [0, 0, 0]
+                        ijk[axis], ijk[t1], ijk[t2] = a % n, b % n, c % n
+                        J[axis][ijk[2], ijk[1], ijk[0]] += (
+                            -(h[axis] / dt) * dfa * dF(b, p[t1]) * dF(c, p[t2]) / 6.0)
+            p = q
+    return J
+
+
+def test_current_equals_six_box_path_average():
+    """The one-sixth and one-quarter forms of Eq. current both equal the mean of
+    the six box-path integrals, computed here from the definitions."""
+    n, dt = 6, 0.45
+    h = np.array([1.0, 1.0, 1.0])
+    g = oracle.Grid(n, n, n, dt)
+    for x0, x1 in [(np.array([2.3, 2.7, 3.1]), np.array([2.9, 3.2, 2.6])),
+                   (np.array([3.05, 2.5, 2.95]), np.array([2.4, 2.5, 3.4])),
+                   (np.array([2.5, 2.5, 2.5]), np.array([2.5, 2.5, 2.5]) + 0.2)]:
+        ref = _box_path_current(x0, x1, n, dt, h)
+        six = oracle.deposit(g, x0, x1, charge=1.0, form="sixth")
+        quarter = oracle.deposit(g, x0, x1, charge=1.0, form="quarter")
+        assert np.max(np.abs(six - ref)) < 1e-12
+        assert np.max(np.abs(quarter - ref)) < 1e-12
+
+
+def _div_face(g, J):
+    return ((np.roll(J[0], -1, axis=2) - J[0]) / g.dx + (np.roll(J[1], -1, axis=1) - J[1]) / g.dy
+            + (np.roll(J[2], -1, axis=0) - J[2]) / g.dz)
+
+
+@pytest.mark.parametrize("form", ["sixth", "quarter"])
+def test_single_particle_continuity(form):
+    """(rho^{n+1} - rho^n)/dt + div J = 0 for one particle, any move of less
+    than a cell, including moves across the periodic boundary (Eq. chargelaw)."""
+    g = oracle.Grid(7, 6, 5, 0.41, dx=1.2, dy=0.9, dz=1.05)
+    x0s, x1s = picgen.random_moves(60, seed=7, box=(7, 6, 5), max_step=0.95)
+    for p in range(x0s.shape[1]):
+        x0, x1 = x0s[:, p], x1s[:, p]
+        q = 0.7
+        J = oracle.deposit(g, x0, x1, charge=q, form=form)
+        r0 = oracle.rho_of(g, x0, q)
+        r1 = oracle.rho_of(g, x1 % np.array([7, 6, 5]), q)
+        resid = (r1 - r0) / g.dt + _div_face(g, J)
+        assert np.max(np.abs(resid)) < 1e-13 * max(1.0, np.max(np.abs(r0)) / g.dt)
+
+
+# --------------------------------------------------------------------------
+# Q5  whole-run Gauss law and div B invariants (Section 2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(6, 5, 4), (8, 8, 1)])
+def test_gauss_and_divb_invariant(shape):
+    nx, ny, nz = shape
+    wl = picgen.Workload("pin", nx, ny, nz, 3 if nz > 1 else 2, 0.45, 4, (0.2,) * 3, 0.3, 20)
+    e = picgen.electrons(wl)
+    ions = picgen.ions_like(wl, e)
+    st = oracle.State(oracle.Grid(nx, ny, nz, wl.dt),
+                      [oracle.Species(e.x, e.w, e.weight, q=-1.0, m=1.0),
+                       oracle.Species(ions.x, ions.w, ions.weight, q=1.0, m=100.0, mobile=False)])
+    # start from a non-trivial field with zero divergence of B
+    st.fields[0:3] = RNG.normal(0, 1e-3, (3,) + st.grid.shape)
+    R0 = st.gauss_residual()
+    D0 = st.div_b()
+    rho_e0 = np.max(np.abs(4 * np.pi * st.rho(st.species[:1])))
+    st.step(20)
+    R = st.gauss_residual()
+    assert np.max(np.abs(R - R0)) / rho_e0 < 1e-12
+    assert np.max(np.abs(st.div_b() - D0)) < 1e-14
+    # positions stay in the box
+    for a, n in enumerate(shape):
+        assert np.all((st.species[0].x[a] >= 0) & (st.species[0].x[a] < n))
+
+
+# --------------------------------------------------------------------------
+# Q6  push: magnetic energy neutrality (Eq. p2), pure electric kick, partition
+# --------------------------------------------------------------------------
+
+def test_push_magnetic_neutrality():
+    for _ in range(50):
+        E = RNG.normal(0, 1, 3)
+        B = RNG.normal(0, 3, 3)
+        w = RNG.normal(0, 2, 3)
+        qm, dt, c = RNG.choice([-1.0, 1.0, 0.01]), 0.3, 1.0
+        w1 = oracle.push(qm, dt, c, E, B, w)
+        e = 0.5 * qm * dt * E
+        lhs = np.sum((w1 - e) ** 2)
+        rhs = np.sum((w + e) ** 2)
+        assert lhs == pytest.approx(rhs, rel=2e-15)
+
+
+def test_push_pure_electric_kick():
+    for _ in range(20):
+        E = RNG.normal(0, 1, 3)
+        w = RNG.normal(0, 1, 3)
+        w1 = oracle.push(-1.0, 0.25, 1.0, E, np.zeros(3), w)
+        assert np.allclose(w1, w - 0.25 * E, rtol=0, atol=1e-15)
+
+
+def test_gather_partition_of_unity():
+    """Uniform grid fields are reproduced exactly at any position (Eq. one)."""
+    g = oracle.Grid(5, 4, 6, 0.3)
+    vals = RNG.normal(0, 1, 6)
+    fields = np.zeros((9,) + g.shape)
+    for c in range(6):
+        fields[c] = vals[c]
+    for _ in range(20):
+        xp = RNG.uniform(0, 1, 3) * np.array([5, 4, 6])
+        E, B = oracle.gather(g, fields, xp)
+        assert np.allclose(np.concatenate([E, B]), vals, atol=1e-14, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# Q7  closed-form gyration of a test particle (Section 5, gyration test)
+# --------------------------------------------------------------------------
+
+def test_gyration_closed_form():
+    gy = GOLDEN["gyration"]
+    dt = gy["omega_B_dt"] / gy["omega_B"]
+    dx = 1.0 * dt / gy["c_dt_over_dx"]
+    n = 32
+    steps = int(round(gy["omega_B_t_end"] / gy["omega_B_dt"]))
+    g = oracle.Grid(n, n, n, dt, dx=dx, dy=dx, dz=dx, bext=(0.0, 0.0, gy["omega_B"]))
+    x = np.array([[n / 2], [n / 2], [n / 2]])
+    w = np.array([[gy["w_over_c"]], [0.0], [0.0]])
+    sp = oracle.Species(x, w, np.ones(1), q=-1.0, m=1.0, deposit=False)
+    st = oracle.State(g, [sp])
+    gam = math.sqrt(1 + gy["w_over_c"] ** 2)
+    theta = 2 * math.atan(gy["omega_B_dt"] / (2 * gam))
+    u = gy["w_over_c"] / gam
+    R = u * dt / (2 * math.sin(theta / 2)) / dx  # chord geometry, cell units
+    pts = [sp.x[:, 0].copy()]
+    for _ in range(steps):
+        st.step(1)
+        pts.append(sp.x[:, 0].copy())
+    pts = np.array(pts)
+    # the derived numbers quoted for this test
+    assert gam == pytest.approx(1.1180340, abs=1e-7)
+    assert theta == pytest.approx(0.2226820, abs=1e-7)
+    assert R == pytest.approx(1.0062306, abs=1e-7)
+    # circumcentre of the first three points; every point must lie on the circle
+    a, b, c = pts[0, :2], pts[1, :2], pts[2, :2]
+    d = 2 * (a[0] * (b[1] - c[1]) + b[0] * (c[1] - a[1]) + c[0] * (a[1] - b[1]))
+    ux = ((a @ a) * (b[1] - c[1]) + (b @ b) * (c[1] - a[1]) + (c @ c) * (a[1] - b[1])) / d
+    uy = ((a @ a) * (c[0] - b[0]) + (b @ b) * (a[0] - c[0]) + (c @ c) * (b[0] - a[0])) / d
+    r = np.hypot(pts[:, 0] - ux, pts[:, 1] - uy)
+    assert np.max(np.abs(r - R)) < 1e-11
+    ang = np.unwrap(np.arctan2(pts[:, 1] - uy, pts[:, 0] - ux))
+    assert np.allclose(np.abs(np.diff(ang)), theta, atol=1e-11)
+    assert np.all(pts[:, 2] == n / 2)
+    assert np.sum(sp.w[:, 0] ** 2) == pytest.approx(gy["w_over_c"] ** 2, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Q8  cold k=0 plasma oscillation: leapfrog recurrence
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_cold_plasma_oscillation(dims):
+    opdt = GOLDEN["thermal_test"]["omega_pe_dt"]
+    nz = 1 if dims == 2 else 4
+    wl = picgen.Workload("cold", 4, 4, nz, dims, 0.5, 4 if dims == 2 else 8, (0.0,) * 3,
+                         opdt / 0.5, 40)
+    e = picgen.lattice_electrons(wl, drift=(1e-5, 0.0, 0.0))
+    ions = picgen.Plasma(e.x.copy(), np.zeros_like(e.w), e.weight.copy(), q=1.0, m=1.0)
+    st = oracle.State(oracle.Grid(4, 4, nz, wl.dt),
+                      [oracle.Species(e.x, e.w, e.weight),
+                       oracle.Species(ions.x, ions.w, ions.weight, q=1.0, m=1.0, mobile=False)])
+    ex = []
+    for _ in range(40):
+        st.step(1)
+        # uniform up to the cancellation in F(x1) - F(x0) for a 5e-6 cell move
+        assert np.ptp(st.E[0]) < 1e-9 * max(1e-30, np.max(np.abs(st.E[0])))
+        ex.append(st.E[0].mean())
+    ex = np.array(ex)
+    ratio = (ex[2:] + ex[:-2]) / ex[1:-1]
+    ok = np.abs(ex[1:-1]) > 0.1 * np.max(np.abs(ex))
+    assert np.allclose(ratio[ok], 2 - opdt ** 2, rtol=0, atol=1e-8)
+    omega = 2 / wl.dt * math.asin(opdt / 2)
+    assert omega / wl.omega_pe == pytest.approx(1.0000260, abs=1e-7)
+
+
+# --------------------------------------------------------------------------
+# Q9  vacuum dispersion of the staggered leapfrog (Appendix field solver)
+# --------------------------------------------------------------------------
+
+def test_vacuum_dispersion():
+    n, dt = 16, 0.45
+    g = oracle.Grid(n, n, n, dt)
+    kx, ky = 2 * math.pi * 2 / n, 2 * math.pi * 3 / n
+    i = np.arange(n)
+    # E^z at (i+1/2, j+1/2, k): a transverse standing mode, B = 0
+    phase = kx * (i[None, :] + 0.5) + ky * (i[:, None] + 0.5)
+    fields = np.zeros((9, n, n, n))
+    fields[2] = np.cos(phase)[None, :, :]
+    amp = []
+    for _ in range(30):
+        oracle.half_b(g, fields)
+        oracle.half_b(g, fields)
+        oracle.update_e(g, fields)
+        amp.append(np.sum(fields[2] * np.cos(phase)[None]))
+    amp = np.array(amp)
+    cos_wdt = 1 - 2 * (dt ** 2) * (math.sin(kx / 2) ** 2 + math.sin(ky / 2) ** 2)
+    ratio = (amp[2:] + amp[:-2]) / amp[1:-1]
+    ok = np.abs(amp[1:-1]) > 0.1 * np.max(np.abs(amp))
+    assert np.allclose(ratio[ok], 2 * cos_wdt, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Q10, Q11  E = -grad_p Phi and B = curl_p A at the particle (Sections 4.2, 4.3)
+# --------------------------------------------------------------------------
+
+def _phi_at(g, phi, xp):
+    w = oracle.rho_of(g, xp, g.dx * g.dy * g.dz)  # the cell weights dF dF dF
+    return np.sum(w * phi)
+
+
+def test_electric_field_is_gradient_of_potential():
+    g = oracle.Grid(6, 5, 7, 0.3, dx=1.1, dy=0.9, dz=1.2)
+    phi = RNG.normal(0, 1, g.shape)
+    fields = np.zeros((9,) + g.shape)
+    fields[0] = (np.roll(phi, 1, axis=2) - phi) / g.dx   # (Phi_{i-1/2} - Phi_{i+1/2})/dx
+    fields[1] = (np.roll(phi, 1, axis=1) - phi) / g.dy
+    fields[2] = (np.roll(phi, 1, axis=0) - phi) / g.dz
+    h = 1e-6
+    hs = (g.dx, g.dy, g.dz)
+    for _ in range(20):
+        xp = RNG.uniform(0, 1, 3) * np.array([6, 5, 7])
+        if np.min(np.abs(xp - np.round(xp))) < 1e-3 or np.min(np.abs(xp - np.floor(xp) - 0.5)) < 1e-3:
+            continue
+        E, _ = oracle.gather(g, fields, xp)
+        for a in range(3):
+            dp = np.zeros(3)
+            dp[a] = h
+            grad = (_phi_at(g, phi, xp + dp) - _phi_at(g, phi, xp - dp)) / (2 * h) / hs[a]
+            assert E[a] == pytest.approx(-grad, abs=2e-8)
+
+
+def test_magnetic_field_is_curl_of_vector_potential():
+    g = oracle.Grid(6, 7, 5, 0.3, dx=1.0, dy=1.3, dz=0.8)
+    A = RNG.normal(0, 1, (3,) + g.shape)
+    Ax, Ay, Az = A
+    fields = np.zeros((9,) + g.shape)
+    fields[3] = (Az - np.roll(Az, 1, axis=1)) / g.dy - (Ay - np.roll(Ay, 1, axis=0)) / g.dz
+    fields[4] = (Ax - np.roll(Ax, 1, axis=0)) / g.dz - (Az - np.roll(Az, 1, axis=2)) / g.dx
+    fields[5] = (Ay - np.roll(Ay, 1, axis=2)) / g.dx - (Ax - np.roll(Ax, 1, axis=1)) / g.dy
+    afields = np.zeros((9,) + g.shape)
+    afields[0:3] = A
+    hs = (g.dx, g.dy, g.dz)
+    h = 1e-6
+
+    def A_at(xp):
+        return oracle.gather(g, afields, xp)[0]
+
+    for _ in range(20):
+        xp = RNG.uniform(0, 1, 3) * np.array([6, 7, 5])
+        if np.min(np.abs(xp - np.round(xp))) < 1e-3 or np.min(np.abs(xp - np.floor(xp) - 0.5)) < 1e-3:
+            continue
+        _, B = oracle.gather(g, fields, xp)
+        d = np.zeros((3, 3))  # d[a][b] = dA_b / dx_a (physical units)
+        for a in range(3):
+            dp = np.zeros(3)
+            dp[a] = h
+            d[a] = (A_at(xp + dp) - A_at(xp - dp)) / (2 * h) / hs[a]
+        curl = np.array([d[1][2] - d[2][1], d[2][0] - d[0][2], d[0][1] - d[1][0]])
+        assert np.allclose(B, curl, atol=2e-8, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# Q12  self-force of a lone 1D sheet (Section 4.4)
+# --------------------------------------------------------------------------
+
+def test_self_energy_closed_form():
+    se = GOLDEN["self_energy"]
+    vals = []
+    for d in np.linspace(0, 1, 41):
+        xp = 10.0 + d
+        nodes = range(6, 16)
+        tot = sum((oracle.cumulative1(i - xp) - 0.5) ** 2 / 2 for i in nodes)
+        tot -= (len(nodes) - 2) * 0.125  # nodes outside the support contribute (1/2)^2/2 each
+        assert tot == pytest.approx(0.125 + 0.25 * d * d * (1 - d) ** 2, abs=1e-15)
+        vals.append(tot)
+    assert min(vals) == pytest.approx(se["minimum"], abs=1e-15)
+    assert max(vals) - min(vals) == pytest.approx(se["variation"], abs=1e-15)
+
+
+def test_self_force_of_sheet():
+    """q sum_i f_i E_i with E_i = 4 pi q dx/V (F_i - 1/2) equals
+    -(4 pi q^2 dx / V) d(1-d)(1-2d)/2: zero at d = 0, 1/2 and zero on average."""
+    n, q = 32, 0.3
+    g = oracle.Grid(n, 1, 1, 0.2, dx=1.0, dy=1.0, dz=1.0)
+    forces = []
+    ds = np.linspace(0, 1, 201)[:-1]
+    for d in ds:
+        xp = np.array([16.0 + d, 0.5, 0.5])
+        fields = np.zeros((9, 1, 1, n))
+        fields[0, 0, 0, :] = [4 * math.pi * q * (oracle.cumulative1(i - xp[0]) - 0.5)
+                              for i in range(n)]
+        E, _ = oracle.gather(g, fields, xp)
+        F = q * E[0]
+        assert F == pytest.approx(-4 * math.pi * q * q * 0.5 * d * (1 - d) * (1 - 2 * d),
+                                  abs=1e-14)
+        forces.append(F)
+    assert abs(np.mean(forces)) < 1e-15
+    assert abs(forces[0]) < 1e-16 and abs(forces[100]) < 1e-16
+
+
+def test_lone_particle_with_ion_stays_at_rest():
+    g = oracle.Grid(8, 8, 8, 0.45)
+    x = np.array([[3.3], [4.6], [2.2]])
+    st = oracle.State(g, [oracle.Species(x, np.zeros((3, 1)), np.ones(1)),
+                          oracle.Species(x, np.zeros((3, 1)), np.ones(1), q=1.0, mobile=False)])
+    st.step(10)
+    assert np.all(st.species[0].x == x) and np.all(st.fields == 0.0)
