@@ -101,7 +101,12 @@ static size_t ncell(const orc_grid* g) { return (size_t)g->nx * g->ny * g->nz; }
  * The sums run over a box around the particle that contains the support of
  * every weight; weights outside the support are exactly zero.
  * ------------------------------------------------------------------------- */
-#define REACH 3 /* half-width of the summation box, larger than any support */
+/* Summation boxes: offsets -BOX_LO .. +BOX_HI from floor(x_p) contain every
+ * node with a non-zero f_i (offsets 0, 1) and every cell with a non-zero
+ * Delta F (offsets -1, 0, 1) of the order-1 1/2 form factor; the extra
+ * entries get exactly zero weight. */
+#define BOX_LO 2
+#define BOX_HI 2
 
 void orc_gather(const orc_grid* g, const double* fields, const double xp[3], double Ep[3],
                 double Bp[3])
@@ -112,20 +117,20 @@ void orc_gather(const orc_grid* g, const double* fields, const double xp[3], dou
     long base[3];
     for (int a = 0; a < 3; ++a) base[a] = (long)floor(xp[a]);
 
-    /* one-dimensional factors, indexed by offset o = index - base + REACH */
-    double nw[3][2 * REACH + 1], cw[3][2 * REACH + 1];
+    /* one-dimensional factors, indexed by offset o = index - base + BOX_LO */
+    double nw[3][BOX_LO + BOX_HI + 1], cw[3][BOX_LO + BOX_HI + 1];
     for (int a = 0; a < 3; ++a)
-        for (int o = 0; o <= 2 * REACH; ++o) {
-            long n = base[a] + o - REACH;
+        for (int o = 0; o <= BOX_LO + BOX_HI; ++o) {
+            long n = base[a] + o - BOX_LO;
             nw[a][o] = node_w(n, xp[a]);
             cw[a][o] = cell_w(n, xp[a]);
         }
 
     for (int c = 0; c < 3; ++c) Ep[c] = Bp[c] = 0.0;
-    for (int ok = 0; ok <= 2 * REACH; ++ok)
-        for (int oj = 0; oj <= 2 * REACH; ++oj)
-            for (int oi = 0; oi <= 2 * REACH; ++oi) {
-                long i = base[0] + oi - REACH, j = base[1] + oj - REACH, k = base[2] + ok - REACH;
+    for (int ok = 0; ok <= BOX_LO + BOX_HI; ++ok)
+        for (int oj = 0; oj <= BOX_LO + BOX_HI; ++oj)
+            for (int oi = 0; oi <= BOX_LO + BOX_HI; ++oi) {
+                long i = base[0] + oi - BOX_LO, j = base[1] + oj - BOX_LO, k = base[2] + ok - BOX_LO;
                 size_t p = idx(g, i, j, k);
                 double ax = nw[0][oi] * cw[1][oj] * cw[2][ok];
                 double ay = cw[0][oi] * nw[1][oj] * cw[2][ok];
@@ -197,8 +202,8 @@ void orc_deposit(const orc_grid* g, const double x0[3], const double x1[3], doub
     for (int a = 0; a < 3; ++a) {
         double m = x0[a] < x1[a] ? x0[a] : x1[a];
         double M = x0[a] < x1[a] ? x1[a] : x0[a];
-        lo[a] = (long)floor(m) - REACH;
-        hi[a] = (long)floor(M) + REACH;
+        lo[a] = (long)floor(m) - BOX_LO;
+        hi[a] = (long)floor(M) + BOX_HI;
     }
     for (int comp = 0; comp < 3; ++comp) {
         int t1 = (comp + 1) % 3, t2 = (comp + 2) % 3; /* transverse axes */
@@ -239,8 +244,8 @@ void orc_deposit_quarter(const orc_grid* g, const double x0[3], const double x1[
     for (int a = 0; a < 3; ++a) {
         double m = x0[a] < x1[a] ? x0[a] : x1[a];
         double M = x0[a] < x1[a] ? x1[a] : x0[a];
-        lo[a] = (long)floor(m) - REACH;
-        hi[a] = (long)floor(M) + REACH;
+        lo[a] = (long)floor(m) - BOX_LO;
+        hi[a] = (long)floor(M) + BOX_HI;
     }
     for (int comp = 0; comp < 3; ++comp) {
         int t1 = (comp + 1) % 3, t2 = (comp + 2) % 3;
@@ -275,13 +280,13 @@ void orc_rho_add(const orc_grid* g, const double xp[3], double charge, double* r
     const double V = g->dx * g->dy * g->dz;
     long base[3];
     for (int a = 0; a < 3; ++a) base[a] = (long)floor(xp[a]);
-    for (long k = base[2] - REACH; k <= base[2] + REACH; ++k) {
+    for (long k = base[2] - BOX_LO; k <= base[2] + BOX_HI; ++k) {
         double wk = cell_w(k, xp[2]);
         if (wk == 0.0) continue;
-        for (long j = base[1] - REACH; j <= base[1] + REACH; ++j) {
+        for (long j = base[1] - BOX_LO; j <= base[1] + BOX_HI; ++j) {
             double wj = cell_w(j, xp[1]);
             if (wj == 0.0) continue;
-            for (long i = base[0] - REACH; i <= base[0] + REACH; ++i) {
+            for (long i = base[0] - BOX_LO; i <= base[0] + BOX_HI; ++i) {
                 double wi = cell_w(i, xp[0]);
                 if (wi == 0.0) continue;
                 rho[idx(g, i, j, k)] += charge / V * wi * wj * wk;
