@@ -1,0 +1,214 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) library for the charge-conserving
+ * particle-in-cell step with alternating-order field interpolation
+ * (Sokolov, arXiv:1101.0809).
+ *
+ * One time step (paper Appendix) is: half step of B (Eq. updateB); for every
+ * particle, the order-1 1/2 alternating form factor at x^n (Section 4.5),
+ * gather of E with the alpha weights (Eq. alphax) and of B with the beta
+ * weights (Eq. betax), relativistic momentum advance of the equation of
+ * motion Eq. (1) as split in the Appendix (Eq. p2), position advance
+ * (Eq. coordscheme), charge-conserving current from the six-box-path
+ * average (Eq. current); second half step of B; E update (Eq. escheme).
+ *
+ * Conventions used by every call
+ *   - Units: Gaussian.  Positions are in cell units (x/dx, y/dy, z/dz) and lie
+ *     in [0, N) per axis; every axis is periodic.  Momenta are w = gamma v
+ *     (momentum over mass), in the same velocity units as c.
+ *   - Grid functions are FP64 arrays [k][j][i], i fastest, N = nx*ny*nz
+ *     points each, packed in one field buffer as 9 planes:
+ *       Ex Ey Ez  at the face centres (i, j+1/2, k+1/2), (i+1/2, j, k+1/2),
+ *                 (i+1/2, j+1/2, k)                       (paper Section 2)
+ *       Bx By Bz  at the edge midpoints (i+1/2, j, k), (i, j+1/2, k),
+ *                 (i, j, k+1/2)
+ *       Jx Jy Jz  located like E; J is the current density of Eq. xi.
+ *     Between steps the buffer holds E^n, B^{n-1/2} and J = 0.
+ *   - Memory: the caller owns every buffer (typically PyTorch tensors on the
+ *     GPU) and passes device pointers; sizes come from pic_query_sizes.  The
+ *     library keeps borrowed pointers until pic_destroy, never frees them and
+ *     performs no device allocation of its own.
+ *   - Streams: a stream argument is a hipStream_t passed as void*; NULL is
+ *     the null stream.  Calls are asynchronous on that stream unless stated
+ *     otherwise.  One context must not be used from two host threads at once.
+ *   - Errors: every int-returning call returns PIC_OK (0) or a negative
+ *     pic_status; the message is available from pic_last_error.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+enum pic_status {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,   /* bad argument (null pointer, size, unsupported option) */
+    PIC_ERANGE = -2,   /* particle position outside [0, N) or not finite */
+    PIC_ECFL = -3,     /* Courant condition of the staggered leapfrog violated */
+    PIC_EDEVICE = -4,  /* a HIP call failed; the HIP error text is in pic_last_error */
+    PIC_ESTATE = -5,   /* call not valid in the current state */
+    PIC_ESIZE = -6     /* a caller buffer is smaller than pic_query_sizes asks */
+};
+
+enum pic_precision {
+    PIC_FP64 = 0,  /* particles as FP64 absolute positions; all arithmetic FP64 */
+    PIC_FP32C = 1  /* particles as int cell + FP32 offset, FP32 push/deposit with
+                      two-sum compensated FP32 current sums; grid and reductions FP64 */
+};
+
+enum pic_field_op {
+    PIC_B_HALF = 1, /* B <- B - (1/2) curl_h E            (Eq. updateB)          */
+    PIC_E_FULL = 2  /* B <- B - (1/2) curl_h E; E <- E - 4 pi dt J + curl_h B; J <- 0
+                       (second half of Eq. updateB, then Eq. escheme)             */
+};
+
+/* Grid and run description (copied by pic_init_grid). */
+typedef struct pic_grid_desc {
+    int32_t dims;        /* 3, or 2 for 2D3V (requires nz == 1: nothing depends on z) */
+    int32_t nx, ny, nz;  /* cells per axis, >= 1 */
+    int32_t precision;   /* enum pic_precision */
+    int32_t order;       /* form-factor order: 1 selects l_a = 1 1/2 (the only value) */
+    int32_t sort_every;  /* re-sort particles by cell every this many steps (0: only
+                            when loaded) */
+    int32_t reserved;    /* must be 0 */
+    double dx, dy, dz;   /* cell sizes */
+    double dt;           /* time step */
+    double c;            /* speed of light */
+    double bext[3];      /* uniform external B, added to the gathered B; it is not
+                            stored in the field buffer and not in field energies */
+} pic_grid_desc;
+
+/* Particle species (copied by pic_add_species). */
+typedef struct pic_species_desc {
+    double q;            /* charge per unit weight (macro charge = q * weight) */
+    double m;            /* mass per unit weight */
+    int32_t mobile;      /* 0: immobile background charge, deposited once into a
+                            fixed density and never pushed; 1: pushed and deposited */
+    int32_t reserved;    /* must be 0 */
+    int64_t capacity;    /* maximum particle count of this species */
+} pic_species_desc;
+
+typedef struct pic_sizes {
+    size_t field_bytes;      /* field buffer: 9 * N FP64 */
+    size_t workspace_bytes;  /* grid workspace: background and reference charge,
+                                diagnostics, sort histogram */
+    size_t particle_bytes;   /* particle buffer for one species of the given capacity
+                                (two copies of the particle arrays for out-of-place sorting,
+                                sort keys, tile table) */
+} pic_sizes;
+
+/* Diagnostics of the state at a step boundary (paper Sections 2, 4.1). */
+typedef struct pic_diag {
+    int64_t step;            /* steps taken since pic_init_grid */
+    int64_t n_particles;     /* mobile particles */
+    double kinetic;          /* sum m_p c^2 (gamma^{n-1/2} - 1) over mobile particles */
+    double field_e;          /* V/(8 pi) sum E^2 */
+    double field_b;          /* V/(8 pi) sum (B^n)^2, B^n = B^{n-1/2} advanced a half
+                                step with E^n (external B excluded) */
+    double charge;           /* V * sum_cells (rho_mobile + rho_background) */
+    double gauss_abs;        /* max_cells |R^n - R^0|, R = div_h E - 4 pi rho */
+    double gauss_rel;        /* gauss_abs / max_cells |4 pi rho_mobile^n| */
+    double rho_mobile_max;   /* max_cells |4 pi rho_mobile^n| */
+    double divb_max;         /* max over nodes of |div_h B^{n-1/2}| */
+    int64_t nonfinite;       /* count of non-finite field values and particle momenta */
+} pic_diag;
+
+/* Buffer sizes for a grid and a particle capacity.  Any pointer in g may be
+ * NULL; only the numeric fields are read. */
+int pic_query_sizes(const pic_grid_desc* g, int64_t particle_capacity, pic_sizes* out);
+
+/* Validate the grid description and create a context bound to the caller's
+ * field buffer (field_bytes from pic_query_sizes; contents are used as the
+ * initial E^0, B^{-1/2}; J must be zero) and grid workspace.  Fails with
+ * PIC_ECFL unless sum_a (c dt / d_a)^2 < 1 over the axes that have more than one
+ * cell (the Courant limit of the staggered leapfrog, Appendix), with
+ * PIC_EINVAL for unsupported sizes (FP32 mode: nx, ny <= 2048, nz <= 1024). */
+int pic_init_grid(const pic_grid_desc* g, void* fields, size_t field_bytes, void* workspace,
+                  size_t workspace_bytes, pic_ctx** out);
+
+/* Register a species and bind its particle buffer (particle_bytes for its
+ * capacity; ignored for an immobile species, which may pass NULL and 0).
+ * Returns the species index in *species (0, 1, ...; at most 4 species). */
+int pic_add_species(pic_ctx* ctx, const pic_species_desc* s, void* buffer, size_t bytes,
+                    int* species);
+
+/* Append n particles to a species from device arrays: x [3][n] positions in
+ * cell units (the z row is ignored when dims == 2), w [3][n] momentum over
+ * mass at t = n - 1/2, weight [n] > 0.  Positions must lie in [0, N) and be
+ * finite (else PIC_ERANGE, nothing appended).  Immobile species add their
+ * charge density (Eq. rho) to the fixed background instead.  Synchronizes the
+ * stream (it checks the positions).  Particles get consecutive ids in load
+ * order.  Resets the Gauss reference R^0, which is recaptured before the next
+ * step or diagnostics. */
+int pic_load_particles(pic_ctx* ctx, int species, int64_t n, const double* x, const double* w,
+                       const double* weight, void* stream);
+
+/* Advance nsteps full time steps (Appendix order).  Asynchronous. */
+int pic_step(pic_ctx* ctx, int nsteps, void* stream);
+
+/* Current of n particles moving from x0 to x1 (device arrays [3][n] in cell
+ * units; x1 need not be wrapped but |x1 - x0| < 1 per axis is required) with
+ * macro charges charge[n], added into J_out (device, 3 * N FP64 in the Jx Jy Jz
+ * layout of the field buffer).  Uses the same per-particle deposit code as
+ * pic_step in the context's precision (FP32 mode converts the positions to
+ * cell + FP32 offset first); the sums go through global atomics.  Eq. current,
+ * Eq. xi.  Asynchronous. */
+int pic_deposit_J(pic_ctx* ctx, const double* x0, const double* x1, const double* charge,
+                  int64_t n, double* J_out, void* stream);
+
+/* One field operation on the bound fields (enum pic_field_op).  Asynchronous. */
+int pic_field_solve(pic_ctx* ctx, int what, void* stream);
+
+/* Compute pic_diag in FP64 on the GPU.  Synchronizes the stream. */
+int pic_diagnostics(pic_ctx* ctx, pic_diag* out, void* stream);
+
+/* Number of particles currently held by a species (host-side count). */
+int64_t pic_particle_count(const pic_ctx* ctx, int species);
+
+/* Copy a species out as FP64 device arrays (capacity >= count): x [3][n],
+ * w [3][n], weight [n], id [n] (any of them may be NULL).  The order is the
+ * library's current (cell-sorted) order; ids identify particles.
+ * Asynchronous. */
+int pic_get_particles(pic_ctx* ctx, int species, double* x, double* w, double* weight,
+                      int64_t* id, void* stream);
+
+/* Sort every mobile species by cell now (counting sort, out of place).
+ * Asynchronous. */
+int pic_sort(pic_ctx* ctx, void* stream);
+
+/* Tuning of the particle-step kernel: fraction of particles that took the
+ * global-memory path (outside their tile's LDS region) in the last step, or
+ * -1 if not recorded.  Synchronizes the stream. */
+double pic_last_fallback_fraction(pic_ctx* ctx, void* stream);
+
+/* Per-phase timing with HIP events recorded on the stream of each pic_step
+ * (a profiling aid; events only, no device memory).  pic_timing_start begins
+ * recording the next max_steps steps (earlier records are dropped).
+ * pic_timing_stop waits for the recorded events and returns the summed
+ * durations in milliseconds of the phases of those steps:
+ *   ms[0] B half step, ms[1] particle kernels, ms[2] second B half step and E
+ *   update, ms[3] periodic sorts;  *steps = number of steps recorded. */
+int pic_timing_start(pic_ctx* ctx, int max_steps);
+int pic_timing_stop(pic_ctx* ctx, double ms[4], int64_t* steps);
+
+/* Destroy a context (does not free caller buffers). */
+void pic_destroy(pic_ctx* ctx);
+
+/* Last error message of a context (never NULL; "" if none).  With ctx == NULL,
+ * the last error of a failed pic_init_grid / pic_query_sizes in this thread. */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/* Version string of the library build. */
+const char* pic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,224 @@
+// diag.hip -- FP64 diagnostics on the GPU: charge density of the mobile
+// particles (Eq. rho), discrete Gauss residual R = div_h E - 4 pi rho at cell
+// centres and its drift from the reference R^0 (the charge-conservation
+// invariant of Section 2), div_h B at nodes, field and kinetic energies
+// (Section 4.1).  Reductions run over a fixed grid of workgroups followed by
+// one reducing workgroup, so the result does not depend on scheduling.
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;
+constexpr int kSlots = 8;
+// slots: 0 max|R-R0|  1 max|4 pi rho_m|  2 sum E^2  3 sum (B^n)^2  4 max|divB|
+//        5 sum rho    6 nonfinite      7 kinetic
+constexpr bool kIsMax[kSlots] = {true, true, false, false, true, false, false, false};
+
+__device__ __forceinline__ double combine(int slot, double a, double b)
+{
+    return kIsMax[slot] ? fmax(a, b) : a + b;
+}
+
+__device__ void block_reduce_store(double (&v)[kSlots], double* out)
+{
+    __shared__ double sh[kSlots][kRedThreads];
+    for (int s = 0; s < kSlots; ++s) sh[s][threadIdx.x] = v[s];
+    __syncthreads();
+    for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int s = 0; s < kSlots; ++s)
+                sh[s][threadIdx.x] = combine(s, sh[s][threadIdx.x], sh[s][threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int s = 0; s < kSlots; ++s) out[s] = sh[s][0];
+}
+
+__device__ __forceinline__ double gauss_at(const GridK& g, const double* f, const double* rho_m,
+                                           const double* rho_bg, int64_t p, int i, int j, int k)
+{
+    const int64_t N = g.ncell;
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t ip = i == g.n[0] - 1 ? p - (g.n[0] - 1) : p + 1;
+    const int64_t jp = j == g.n[1] - 1 ? p - (int64_t)(g.n[1] - 1) * sy : p + sy;
+    const int64_t kp = k == g.n[2] - 1 ? p - (int64_t)(g.n[2] - 1) * sz : p + sz;
+    const double div = (f[ip] - f[p]) * g.inv_h[0] + (f[N + jp] - f[N + p]) * g.inv_h[1] +
+                       (f[2 * N + kp] - f[2 * N + p]) * g.inv_h[2];
+    return div - 4.0 * kPi * (rho_m[p] + rho_bg[p]);
+}
+
+__device__ __forceinline__ void decode(const GridK& g, int64_t p, int& i, int& j, int& k)
+{
+    const int64_t row = p / g.n[0];
+    i = (int)(p - row * g.n[0]);
+    k = (int)(row / g.n[1]);
+    j = (int)(row - (int64_t)k * g.n[1]);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_capture_r0(GridK g, const double* __restrict__ f,
+                                                            const double* __restrict__ rho_m,
+                                                            const double* __restrict__ rho_bg,
+                                                            double* __restrict__ r0)
+{
+    for (int64_t p = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; p < g.ncell;
+         p += (int64_t)gridDim.x * kRedThreads) {
+        int i, j, k;
+        decode(g, p, i, j, k);
+        r0[p] = gauss_at(g, f, rho_m, rho_bg, p, i, j, k);
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_diag_cells(GridK g, const double* __restrict__ f,
+                                                            const double* __restrict__ rho_m,
+                                                            const double* __restrict__ rho_bg,
+                                                            const double* __restrict__ r0,
+                                                            double* __restrict__ part)
+{
+    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t N = g.ncell;
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    for (int64_t p = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * kRedThreads) {
+        int i, j, k;
+        decode(g, p, i, j, k);
+        const double R = gauss_at(g, f, rho_m, rho_bg, p, i, j, k);
+        v[0] = fmax(v[0], fabs(R - r0[p]));
+        v[1] = fmax(v[1], fabs(4.0 * kPi * rho_m[p]));
+        const double ex = f[p], ey = f[N + p], ez = f[2 * N + p];
+        v[2] += ex * ex + ey * ey + ez * ez;
+        // B^n = B^{n-1/2} - (1/2) curl_h E^n
+        const int64_t im = i == 0 ? p + (g.n[0] - 1) : p - 1;
+        const int64_t jm = j == 0 ? p + (int64_t)(g.n[1] - 1) * sy : p - sy;
+        const int64_t km = k == 0 ? p + (int64_t)(g.n[2] - 1) * sz : p - sz;
+        const double* Ex = f;
+        const double* Ey = f + N;
+        const double* Ez = f + 2 * N;
+        const double* Bx = f + 3 * N;
+        const double* By = f + 4 * N;
+        const double* Bz = f + 5 * N;
+        const double bx = Bx[p] - g.half_cfl[1] * (ez - Ez[jm]) + g.half_cfl[2] * (ey - Ey[km]);
+        const double by = By[p] - g.half_cfl[2] * (ex - Ex[km]) + g.half_cfl[0] * (ez - Ez[im]);
+        const double bz = Bz[p] - g.half_cfl[0] * (ey - Ey[im]) + g.half_cfl[1] * (ex - Ex[jm]);
+        v[3] += bx * bx + by * by + bz * bz;
+        const double db = (Bx[p] - Bx[im]) * g.inv_h[0] + (By[p] - By[jm]) * g.inv_h[1] +
+                          (Bz[p] - Bz[km]) * g.inv_h[2];
+        v[4] = fmax(v[4], fabs(db));
+        v[5] += rho_m[p] + rho_bg[p];
+        for (int c = 0; c < 6; ++c)
+            if (!isfinite(f[c * N + p])) v[6] += 1.0;
+    }
+    block_reduce_store(v, part + (int64_t)blockIdx.x * kSlots);
+}
+
+template <class R>
+__global__ __launch_bounds__(kRedThreads) void k_diag_particles(PartArrays a, int64_t n, double m,
+                                                                double inv_c2,
+                                                                double* __restrict__ part)
+{
+    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t p = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * kRedThreads) {
+        const double w0 = (double)((const R*)a.mom[0])[p];
+        const double w1 = (double)((const R*)a.mom[1])[p];
+        const double w2 = (double)((const R*)a.mom[2])[p];
+        const double w2s = w0 * w0 + w1 * w1 + w2 * w2;
+        if (!isfinite(w2s)) {
+            v[6] += 1.0;
+            continue;
+        }
+        const double gam = sqrt(1.0 + w2s * inv_c2);
+        v[7] += m * (double)((const R*)a.weight)[p] * w2s / (gam + 1.0);
+    }
+    block_reduce_store(v, part + (int64_t)blockIdx.x * kSlots);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ part, int nb,
+                                                              double* __restrict__ out)
+{
+    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads)
+        for (int s = 0; s < kSlots; ++s) v[s] = combine(s, v[s], part[(int64_t)b * kSlots + s]);
+    block_reduce_store(v, out);
+}
+
+__global__ void k_zero_f64(double* p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kRedThreads)
+        p[i] = 0.0;
+}
+
+hipError_t mobile_rho(Ctx& c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_f64, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.rho_m, c.k.ncell);
+    for (int i = 0; i < c.nsp; ++i)
+        if (c.sp[i].d.mobile) {
+            hipError_t e = launch_rho(c, c.sp[i], c.rho_m, s);
+            if (e != hipSuccess) return e;
+        }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_capture_r0(Ctx& c, hipStream_t s)
+{
+    hipError_t e = mobile_rho(c, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_capture_r0, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k, c.fields,
+                       c.rho_m, c.rho_bg, c.r0);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s)
+{
+    hipError_t e = mobile_rho(c, s);
+    if (e != hipSuccess) return e;
+    // partial layout: cells kRedBlocks x kSlots, then one block per species
+    double* part = c.red;
+    hipLaunchKernelGGL(k_diag_cells, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k, c.fields,
+                       c.rho_m, c.rho_bg, c.r0, part);
+    int nb = kRedBlocks;
+    int64_t nmob = 0;
+    for (int i = 0; i < c.nsp; ++i) {
+        const Species& sp = c.sp[i];
+        if (!sp.d.mobile) continue;
+        nmob += sp.n;
+        double* pp = part + (int64_t)nb * kSlots;
+        if (c.g.precision == PIC_FP64)
+            hipLaunchKernelGGL((k_diag_particles<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, s,
+                               sp.cur, sp.n, sp.d.m, 1.0 / (c.g.c * c.g.c), pp);
+        else
+            hipLaunchKernelGGL((k_diag_particles<float>), dim3(kRedBlocks), dim3(kRedThreads), 0, s,
+                               sp.cur, sp.n, sp.d.m, 1.0 / (c.g.c * c.g.c), pp);
+        nb += kRedBlocks;
+    }
+    double* fin = part + (int64_t)nb * kSlots;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, s, part, nb, fin);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double h[kSlots];
+    e = hipMemcpyAsync(h, fin, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    const double V = c.g.dx * c.g.dy * c.g.dz;
+    out->step = c.step;
+    out->n_particles = nmob;
+    out->kinetic = h[7];
+    out->field_e = V / (8.0 * kPi) * h[2];
+    out->field_b = V / (8.0 * kPi) * h[3];
+    out->charge = V * h[5];
+    out->gauss_abs = h[0];
+    out->rho_mobile_max = h[1];
+    out->gauss_rel = h[1] > 0.0 ? h[0] / h[1] : h[0];
+    out->divb_max = h[4];
+    out->nonfinite = (int64_t)h[6];
+    return hipSuccess;
+}
+
+size_t diag_partials_doubles(int nsp) { return (size_t)(kRedBlocks * (1 + nsp) + 1) * kSlots; }
+
+}  // namespace pic

@@ -1,0 +1,105 @@
+// fields.hip -- staggered-grid (Yee) field updates of the paper's Appendix:
+// the B half step (Eq. updateB) and the E update (Eq. escheme).
+//
+// Storage (see pic.h): FP64 planes [k][j][i], i fastest, periodic.
+//   Ex(i, j+1/2, k+1/2)  Ey(i+1/2, j, k+1/2)  Ez(i+1/2, j+1/2, k)
+//   Bx(i+1/2, j, k)      By(i, j+1/2, k)      Bz(i, j, k+1/2)
+// One thread per cell, consecutive threads on consecutive i, so every plane is
+// streamed with unit stride; the backward / forward neighbours along y and z
+// are re-reads of rows that the same or a neighbouring workgroup just fetched
+// and are served from L2.  Both kernels are HBM-bound (9 or 12 FP64 values
+// moved per cell).
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+constexpr int kFieldThreads = 256;
+
+struct CellIdx {
+    int64_t p;
+    int i, j, k;
+};
+
+__device__ __forceinline__ CellIdx cell_of(int64_t p, const GridK& g)
+{
+    CellIdx c;
+    c.p = p;
+    const int64_t row = p / g.n[0];
+    c.i = (int)(p - row * g.n[0]);
+    c.k = (int)(row / g.n[1]);
+    c.j = (int)(row - (int64_t)c.k * g.n[1]);
+    return c;
+}
+
+// B <- B - (1/2) curl_h E
+__global__ __launch_bounds__(kFieldThreads) void k_half_b(GridK g, double* __restrict__ f)
+{
+    const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
+    if (p >= g.ncell) return;
+    const CellIdx c = cell_of(p, g);
+    const int64_t N = g.ncell;
+    const double* Ex = f;
+    const double* Ey = f + N;
+    const double* Ez = f + 2 * N;
+    double* Bx = f + 3 * N;
+    double* By = f + 4 * N;
+    double* Bz = f + 5 * N;
+    const int64_t sx = 1, sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t im = c.i == 0 ? p + (g.n[0] - 1) * sx : p - sx;
+    const int64_t jm = c.j == 0 ? p + (int64_t)(g.n[1] - 1) * sy : p - sy;
+    const int64_t km = c.k == 0 ? p + (int64_t)(g.n[2] - 1) * sz : p - sz;
+    const double ex = Ex[p], ey = Ey[p], ez = Ez[p];
+    const double hx = g.half_cfl[0], hy = g.half_cfl[1], hz = g.half_cfl[2];
+    Bx[p] = Bx[p] - hy * (ez - Ez[jm]) + hz * (ey - Ey[km]);
+    By[p] = By[p] - hz * (ex - Ex[km]) + hx * (ez - Ez[im]);
+    Bz[p] = Bz[p] - hx * (ey - Ey[im]) + hy * (ex - Ex[jm]);
+}
+
+// E <- E - 4 pi dt J + curl_h B ; J <- 0
+__global__ __launch_bounds__(kFieldThreads) void k_update_e(GridK g, double* __restrict__ f)
+{
+    const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
+    if (p >= g.ncell) return;
+    const CellIdx c = cell_of(p, g);
+    const int64_t N = g.ncell;
+    double* Ex = f;
+    double* Ey = f + N;
+    double* Ez = f + 2 * N;
+    const double* Bx = f + 3 * N;
+    const double* By = f + 4 * N;
+    const double* Bz = f + 5 * N;
+    double* Jx = f + 6 * N;
+    double* Jy = f + 7 * N;
+    double* Jz = f + 8 * N;
+    const int64_t sx = 1, sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t ip = c.i == g.n[0] - 1 ? p - (g.n[0] - 1) * sx : p + sx;
+    const int64_t jp = c.j == g.n[1] - 1 ? p - (int64_t)(g.n[1] - 1) * sy : p + sy;
+    const int64_t kp = c.k == g.n[2] - 1 ? p - (int64_t)(g.n[2] - 1) * sz : p + sz;
+    const double bx = Bx[p], by = By[p], bz = Bz[p];
+    const double cx = g.cfl[0], cy = g.cfl[1], cz = g.cfl[2];
+    Ex[p] = Ex[p] - g.fourpidt * Jx[p] + cy * (Bz[jp] - bz) - cz * (By[kp] - by);
+    Ey[p] = Ey[p] - g.fourpidt * Jy[p] + cz * (Bx[kp] - bx) - cx * (Bz[ip] - bz);
+    Ez[p] = Ez[p] - g.fourpidt * Jz[p] + cx * (By[ip] - by) - cy * (Bx[jp] - bx);
+    Jx[p] = 0.0;
+    Jy[p] = 0.0;
+    Jz[p] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_field_half_b(const Ctx& c, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
+    hipLaunchKernelGGL(k_half_b, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_update_e(const Ctx& c, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
+    hipLaunchKernelGGL(k_update_e, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields);
+    return hipGetLastError();
+}
+
+}  // namespace pic

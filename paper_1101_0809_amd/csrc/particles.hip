@@ -1,0 +1,963 @@
+// particles.hip -- the per-particle hot path of one time step (paper Appendix):
+// alternating-order form factor at x^n (Section 4.5), gather of E with the
+// alpha weights (Eq. alphax) and of B^n with the beta weights (Eq. betax),
+// momentum advance (Eq. p2 and the three-stage split before it), position
+// advance (Eq. coordscheme) and the charge-conserving current of Eq. current.
+//
+// Kernel organisation (one workgroup per cell tile; particles are cell-sorted
+// so a tile's particles are contiguous):
+//   1. stage E^n and B^n of the tile plus guard cells into LDS (R precision);
+//   2. clear an LDS current tile covering the deposit reach plus guards;
+//   3. each thread advances particles of the tile; a particle whose cell lies
+//      within M cells of its tile (it may have drifted since the last sort)
+//      gathers from LDS and deposits with LDS atomics, any other particle uses
+//      the same arithmetic on global memory (wrapped indices, global atomics);
+//   4. flush the LDS current tile into the global FP64 J with atomics.
+// Precision R = double (FP64 mode: absolute FP64 positions) or float (FP32
+// mode: packed int cell + FP32 offset; the LDS current is a hi/lo pair of
+// FP32 arrays updated with two-sum compensation).
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Order-1 1/2 alternating form factor of one axis (Section 4.5): with
+// i = floor(x), d = x - i, node weights (1-d; d) at nodes i, i+1 and cell
+// weights ((1-d)^2/2; 3/4 - (1/2-d)^2; d^2/2) at cells i-1, i, i+1.
+// ---------------------------------------------------------------------------
+template <class R>
+struct Axis {
+    R f[2];
+    R s[3];
+};
+
+template <class R>
+__device__ __forceinline__ Axis<R> form_factor(R d)
+{
+    Axis<R> a;
+    const R e = R(1) - d;
+    const R h = R(0.5) - d;
+    a.f[0] = e;
+    a.f[1] = d;
+    a.s[0] = R(0.5) * e * e;
+    a.s[1] = R(0.75) - h * h;
+    a.s[2] = R(0.5) * d * d;
+    return a;
+}
+
+// Cell weights only (the end point of the move).
+template <class R>
+__device__ __forceinline__ void cell_weights(R d, R s[3])
+{
+    const R e = R(1) - d;
+    const R h = R(0.5) - d;
+    s[0] = R(0.5) * e * e;
+    s[1] = R(0.75) - h * h;
+    s[2] = R(0.5) * d * d;
+}
+
+// ---------------------------------------------------------------------------
+// Gather (Eqs. alphax, betax).  F(comp, a, b, c) returns the grid value of
+// component comp (0..2 = Ex..Ez, 3..5 = Bx..Bz) at offset (a, b, c) from the
+// particle cell (a, b, c in {-1, 0, 1}; node factors use 0, 1).
+// ---------------------------------------------------------------------------
+template <class R, class Acc>
+__device__ __forceinline__ void gather3(const Axis<R> (&w)[3], Acc F, R E[3], R B[3])
+{
+    const Axis<R>& X = w[0];
+    const Axis<R>& Y = w[1];
+    const Axis<R>& Z = w[2];
+    // E^x: f_x(node) S_y S_z
+    {
+        R acc = 0;
+        for (int a = 0; a < 2; ++a) {
+            R sa = 0;
+            for (int b = -1; b <= 1; ++b) {
+                R sb = 0;
+                for (int c = -1; c <= 1; ++c) sb += Z.s[c + 1] * F(0, a, b, c);
+                sa += Y.s[b + 1] * sb;
+            }
+            acc += X.f[a] * sa;
+        }
+        E[0] = acc;
+    }
+    // E^y: S_x f_y S_z
+    {
+        R acc = 0;
+        for (int a = -1; a <= 1; ++a) {
+            R sa = 0;
+            for (int b = 0; b < 2; ++b) {
+                R sb = 0;
+                for (int c = -1; c <= 1; ++c) sb += Z.s[c + 1] * F(1, a, b, c);
+                sa += Y.f[b] * sb;
+            }
+            acc += X.s[a + 1] * sa;
+        }
+        E[1] = acc;
+    }
+    // E^z: S_x S_y f_z
+    {
+        R acc = 0;
+        for (int a = -1; a <= 1; ++a) {
+            R sa = 0;
+            for (int b = -1; b <= 1; ++b) {
+                R sb = Z.f[0] * F(2, a, b, 0) + Z.f[1] * F(2, a, b, 1);
+                sa += Y.s[b + 1] * sb;
+            }
+            acc += X.s[a + 1] * sa;
+        }
+        E[2] = acc;
+    }
+    // B^x: S_x f_y f_z
+    {
+        R acc = 0;
+        for (int a = -1; a <= 1; ++a) {
+            R sa = 0;
+            for (int b = 0; b < 2; ++b) {
+                R sb = Z.f[0] * F(3, a, b, 0) + Z.f[1] * F(3, a, b, 1);
+                sa += Y.f[b] * sb;
+            }
+            acc += X.s[a + 1] * sa;
+        }
+        B[0] = acc;
+    }
+    // B^y: f_x S_y f_z
+    {
+        R acc = 0;
+        for (int a = 0; a < 2; ++a) {
+            R sa = 0;
+            for (int b = -1; b <= 1; ++b) {
+                R sb = Z.f[0] * F(4, a, b, 0) + Z.f[1] * F(4, a, b, 1);
+                sa += Y.s[b + 1] * sb;
+            }
+            acc += X.f[a] * sa;
+        }
+        B[1] = acc;
+    }
+    // B^z: f_x f_y S_z
+    {
+        R acc = 0;
+        for (int a = 0; a < 2; ++a) {
+            R sa = 0;
+            for (int b = 0; b < 2; ++b) {
+                R sb = 0;
+                for (int c = -1; c <= 1; ++c) sb += Z.s[c + 1] * F(5, a, b, c);
+                sa += Y.f[b] * sb;
+            }
+            acc += X.f[a] * sa;
+        }
+        B[2] = acc;
+    }
+}
+
+// 2D3V: nothing depends on z, so every z sum of a partition of unity is 1.
+template <class R, class Acc>
+__device__ __forceinline__ void gather2(const Axis<R> (&w)[3], Acc F, R E[3], R B[3])
+{
+    const Axis<R>& X = w[0];
+    const Axis<R>& Y = w[1];
+    R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
+    for (int a = 0; a < 2; ++a) {
+        R s = 0;
+        for (int b = -1; b <= 1; ++b) s += Y.s[b + 1] * F(0, a, b, 0);
+        ex += X.f[a] * s;
+    }
+    for (int a = -1; a <= 1; ++a) {
+        ey += X.s[a + 1] * (Y.f[0] * F(1, a, 0, 0) + Y.f[1] * F(1, a, 1, 0));
+        R s = 0;
+        for (int b = -1; b <= 1; ++b) s += Y.s[b + 1] * F(2, a, b, 0);
+        ez += X.s[a + 1] * s;
+        bx += X.s[a + 1] * (Y.f[0] * F(3, a, 0, 0) + Y.f[1] * F(3, a, 1, 0));
+    }
+    for (int a = 0; a < 2; ++a) {
+        R s = 0;
+        for (int b = -1; b <= 1; ++b) s += Y.s[b + 1] * F(4, a, b, 0);
+        by += X.f[a] * s;
+        bz += X.f[a] * (Y.f[0] * F(5, a, 0, 0) + Y.f[1] * F(5, a, 1, 0));
+    }
+    E[0] = ex;
+    E[1] = ey;
+    E[2] = ez;
+    B[0] = bx;
+    B[1] = by;
+    B[2] = bz;
+}
+
+// ---------------------------------------------------------------------------
+// Momentum advance (Appendix): e = q dt E/(2m); w~ = w + e;
+// b = q dt B / (2 m sqrt(w~^2 + c^2)); w' = w~ + w~ x b;
+// w_new = w~ + e + 2 (w' x b)/(1 + b^2).
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void push(R qmdt2, R c2, const R E[3], const R B[3], R w[3])
+{
+    R e[3], wt[3], b[3];
+    for (int a = 0; a < 3; ++a) e[a] = qmdt2 * E[a];
+    for (int a = 0; a < 3; ++a) wt[a] = w[a] + e[a];
+    const R g = sqrt(wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2] + c2);
+    const R k = qmdt2 / g;
+    for (int a = 0; a < 3; ++a) b[a] = k * B[a];
+    const R wp0 = wt[0] + (wt[1] * b[2] - wt[2] * b[1]);
+    const R wp1 = wt[1] + (wt[2] * b[0] - wt[0] * b[2]);
+    const R wp2 = wt[2] + (wt[0] * b[1] - wt[1] * b[0]);
+    const R s = R(2) / (R(1) + b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    w[0] = wt[0] + e[0] + s * (wp1 * b[2] - wp2 * b[1]);
+    w[1] = wt[1] + e[1] + s * (wp2 * b[0] - wp0 * b[2]);
+    w[2] = wt[2] + e[2] + s * (wp0 * b[1] - wp1 * b[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Current of one particle (Eq. current, one-quarter form).  Per axis the
+// start and end cell weights are placed on a common window of 4 cells
+// starting at s = min(i0, i1) - 1; dm = S1 - S0, dp = S1 + S0 on the window;
+// the cumulative difference at face s+t+1 is P_t = sum_{t' <= t} dm_t'
+// (t = 0..2; the face s+4 gets sum of all dm = 0).  The last prefix is taken
+// as -dm_3, which is the same value and exactly zero whenever the window's
+// last cell is empty.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void window(const R s0[3], const R s1[3], int delta, R dm[4], R dp[4])
+{
+    const bool o0 = delta < 0;  // start weights shifted one cell right in the window
+    const bool o1 = delta > 0;  // end weights shifted one cell right
+    const R a0 = o0 ? R(0) : s0[0], a1 = o0 ? s0[0] : s0[1], a2 = o0 ? s0[1] : s0[2],
+            a3 = o0 ? s0[2] : R(0);
+    const R b0 = o1 ? R(0) : s1[0], b1 = o1 ? s1[0] : s1[1], b2 = o1 ? s1[1] : s1[2],
+            b3 = o1 ? s1[2] : R(0);
+    dm[0] = b0 - a0;
+    dm[1] = b1 - a1;
+    dm[2] = b2 - a2;
+    dm[3] = b3 - a3;
+    dp[0] = b0 + a0;
+    dp[1] = b1 + a1;
+    dp[2] = b2 + a2;
+    dp[3] = b3 + a3;
+}
+
+// Sink(comp, ix, iy, iz, v) adds v to component comp at window position
+// (ix, iy, iz), each in 0..3 (window cells s..s+3; the face s+t+1 of the
+// component's own axis is position t+1).
+template <class R, class Sink>
+__device__ __forceinline__ void deposit3(const R (&dm)[3][4], const R (&dp)[3][4],
+                                         const R jfac[3], Sink S)
+{
+    const R third = R(1) / R(3);
+    R m3[3][4];
+    for (int a = 0; a < 3; ++a)
+        for (int t = 0; t < 4; ++t) m3[a][t] = dm[a][t] * third;
+    for (int comp = 0; comp < 3; ++comp) {
+        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
+        R P[3];
+        P[0] = dm[comp][0];
+        P[1] = dm[comp][0] + dm[comp][1];
+        P[2] = -dm[comp][3];
+        for (int t = 0; t < 3; ++t) P[t] *= jfac[comp];
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c) {
+                const R tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
+                for (int t = 0; t < 3; ++t) {
+                    int ijk[3];
+                    ijk[comp] = t + 1;
+                    ijk[u] = b;
+                    ijk[v] = c;
+                    S(comp, ijk[0], ijk[1], ijk[2], P[t] * tr);
+                }
+            }
+    }
+}
+
+// 2D3V: the z sums collapse (sum of dp_z = 2, sum of dm_z = 0, sum over the
+// z faces of P_z = z0 - z1), leaving 12 + 12 + 16 contributions.  jz is the
+// J^z factor per unit transverse weight: (q/V) u_z / 4.
+template <class R, class Sink>
+__device__ __forceinline__ void deposit2(const R (&dm)[3][4], const R (&dp)[3][4],
+                                         const R jfac[3], R jz, Sink S)
+{
+    const R third = R(1) / R(3);
+    for (int comp = 0; comp < 2; ++comp) {
+        const int u = 1 - comp;
+        R P[3];
+        P[0] = dm[comp][0];
+        P[1] = dm[comp][0] + dm[comp][1];
+        P[2] = -dm[comp][3];
+        for (int t = 0; t < 3; ++t) P[t] *= R(2) * jfac[comp];
+        for (int b = 0; b < 4; ++b)
+            for (int t = 0; t < 3; ++t) {
+                int ij[2];
+                ij[comp] = t + 1;
+                ij[u] = b;
+                S(comp, ij[0], ij[1], 0, P[t] * dp[u][b]);
+            }
+    }
+    for (int a = 0; a < 4; ++a) {
+        const R mx = dm[0][a] * third;
+        for (int b = 0; b < 4; ++b) S(2, a, b, 0, jz * (dp[0][a] * dp[1][b] + mx * dm[1][b]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Particle representations.
+// ---------------------------------------------------------------------------
+struct StepArgs {
+    void* pos[3];
+    void* mom[3];
+    const void* weight;
+    uint32_t* cell;
+    const int64_t* tile_start;
+    double q;        // charge per unit weight
+    double qm;       // q / m
+    unsigned long long* counters;
+};
+
+__device__ __forceinline__ int wrapi(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ uint32_t pack_cell(int i, int j, int k)
+{
+    return (uint32_t)i | ((uint32_t)j << 11) | ((uint32_t)k << 22);
+}
+
+__device__ __forceinline__ void unpack_cell(uint32_t c, int i[3])
+{
+    i[0] = (int)(c & 2047u);
+    i[1] = (int)((c >> 11) & 2047u);
+    i[2] = (int)(c >> 22);
+}
+
+// Load the start state: cell index i[a], offset d[a] in [0,1).
+template <class R, int D>
+struct PosIO;
+
+template <int D>
+struct PosIO<double, D> {
+    static __device__ __forceinline__ void load(const StepArgs& a, int64_t p, int i[3], double d[3])
+    {
+        for (int ax = 0; ax < D; ++ax) {
+            const double x = ((const double*)a.pos[ax])[p];
+            const double fl = floor(x);
+            i[ax] = (int)fl;
+            d[ax] = x - fl;
+        }
+        if (D == 2) {
+            i[2] = 0;
+            d[2] = 0.0;
+        }
+    }
+    // Advance by disp (cell units), wrap, store; return the end offsets d1 and
+    // the cell shift delta in {-1, 0, 1} consistent with the stored position.
+    static __device__ __forceinline__ void move(const StepArgs& a, int64_t p, const GridK& g,
+                                                const int i0[3], const double d0[3],
+                                                const double disp[3], double d1[3], int delta[3],
+                                                bool store)
+    {
+        for (int ax = 0; ax < D; ++ax) {
+            const double N = (double)g.n[ax];
+            double x = ((double)i0[ax] + d0[ax]) + disp[ax];
+            if (x >= N) x -= N;
+            if (x < 0.0) x += N;
+            if (x >= N) x -= N;  // a tiny negative value can round up to N
+            const double fl = floor(x);
+            d1[ax] = x - fl;
+            delta[ax] = (int)rint((d0[ax] + disp[ax]) - d1[ax]);
+            if (store) ((double*)a.pos[ax])[p] = x;
+        }
+    }
+};
+
+template <int D>
+struct PosIO<float, D> {
+    static __device__ __forceinline__ void load(const StepArgs& a, int64_t p, int i[3], float d[3])
+    {
+        unpack_cell(a.cell[p], i);
+        for (int ax = 0; ax < D; ++ax) d[ax] = ((const float*)a.pos[ax])[p];
+        if (D == 2) d[2] = 0.0f;
+    }
+    static __device__ __forceinline__ void move(const StepArgs& a, int64_t p, const GridK& g,
+                                                const int i0[3], const float d0[3],
+                                                const float disp[3], float d1[3], int delta[3],
+                                                bool store)
+    {
+        int i1[3] = {i0[0], i0[1], i0[2]};
+        for (int ax = 0; ax < D; ++ax) {
+            float o = d0[ax] + disp[ax];
+            int dl = 0;
+            if (o >= 1.0f) {
+                o -= 1.0f;  // exact: o is in [1, 2)
+                dl = 1;
+            } else if (o < 0.0f) {
+                o += 1.0f;
+                dl = -1;
+                if (o >= 1.0f) {  // |o| below half an ulp of 1: the position is the node
+                    o = 0.0f;
+                    dl = 0;
+                }
+            }
+            d1[ax] = o;
+            delta[ax] = dl;
+            int c = i0[ax] + dl;
+            c = c < 0 ? c + g.n[ax] : (c >= g.n[ax] ? c - g.n[ax] : c);
+            i1[ax] = c;
+            if (store) ((float*)a.pos[ax])[p] = o;
+        }
+        if (store) a.cell[p] = pack_cell(i1[0], i1[1], i1[2]);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// LDS current storage: FP64 accumulates directly; FP32 keeps hi and lo arrays
+// and compensates every add with the two-sum error of the atomic's own add
+// (the atomic returns the old value o, the stored sum is fl(o + v)).
+// ---------------------------------------------------------------------------
+template <class R, int NJ>
+struct LdsJ;
+
+template <int NJ>
+struct LdsJ<double, NJ> {
+    double v[NJ];
+    __device__ __forceinline__ void zero(int i) { v[i] = 0.0; }
+    __device__ __forceinline__ void add(int i, double x) { atomicAdd(&v[i], x); }
+    __device__ __forceinline__ double get(int i) const { return v[i]; }
+};
+
+template <int NJ>
+struct LdsJ<float, NJ> {
+    float hi[NJ];
+    float lo[NJ];
+    __device__ __forceinline__ void zero(int i)
+    {
+        hi[i] = 0.0f;
+        lo[i] = 0.0f;
+    }
+    __device__ __forceinline__ void add(int i, float x)
+    {
+        const float o = atomicAdd(&hi[i], x);
+        const float s = o + x;
+        const float bv = s - o;
+        const float err = (o - (s - bv)) + (x - bv);
+        if (err != 0.0f) atomicAdd(&lo[i], err);
+    }
+    __device__ __forceinline__ double get(int i) const { return (double)hi[i] + (double)lo[i]; }
+};
+
+__device__ __forceinline__ void global_add(double* p, double v)
+{
+    unsafeAtomicAdd(p, v);
+}
+
+// Workgroup -> tile map: consecutive workgroup ids are dealt round-robin to
+// the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
+// share field rows and J guard cells in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles)
+{
+    const int per = ntiles / kXcds, rem = ntiles % kXcds;
+    const int x = bid % kXcds, local = bid / kXcds;
+    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
+// ---------------------------------------------------------------------------
+// The particle-step kernel.
+// ---------------------------------------------------------------------------
+template <class R, int D, int T, int M, int NT>
+__global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const double* __restrict__ fields,
+                                                     double* __restrict__ Jg)
+{
+    constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
+    constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
+    constexpr int NF = D == 3 ? LF * LF * LF : LF * LF;
+    constexpr int NJ = D == 3 ? LJ * LJ * LJ : LJ * LJ;
+    constexpr int SFY = LF, SFZ = LF * LF;
+    constexpr int SJY = LJ, SJZ = LJ * LJ;
+    __shared__ R sf[6 * NF];
+    __shared__ LdsJ<R, 3 * NJ> sj;
+    __shared__ unsigned int n_fallback;
+
+    const int tile = xcd_tile(blockIdx.x, g.ntiles);
+    const int tx = tile % g.nt[0];
+    const int ty = (tile / g.nt[0]) % g.nt[1];
+    const int tz = D == 3 ? tile / (g.nt[0] * g.nt[1]) : 0;
+    const int T0[3] = {tx * T, ty * T, tz * T};
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+
+    // 1. stage E^n, B^n (+ guard cells) into LDS
+    for (int e = threadIdx.x; e < 6 * NF; e += NT) {
+        const int comp = e / NF;
+        const int r = e - comp * NF;
+        const int lx = r % LF;
+        const int ly = (r / LF) % LF;
+        const int lz = D == 3 ? r / (LF * LF) : 0;
+        const int gx = wrapi(T0[0] - 1 - M + lx, nx);
+        const int gy = wrapi(T0[1] - 1 - M + ly, ny);
+        const int gz = D == 3 ? wrapi(T0[2] - 1 - M + lz, nz) : 0;
+        sf[e] = (R)fields[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
+    }
+    // 2. clear the LDS current tile
+    for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
+    if (threadIdx.x == 0) n_fallback = 0;
+    __syncthreads();
+
+    const R c = (R)g.c;
+    const R c2 = c * c;
+    const R qmdt2 = (R)(0.5 * a.qm * g.dt);
+    const R cfl[3] = {(R)g.cfl[0], (R)g.cfl[1], (R)g.cfl[2]};
+    const R bext[3] = {(R)g.bext[0], (R)g.bext[1], (R)g.bext[2]};
+    const int64_t begin = a.tile_start[tile], end = a.tile_start[tile + 1];
+    unsigned int my_fallback = 0;
+
+    // 3. particles
+    for (int64_t p = begin + threadIdx.x; p < end; p += NT) {
+        int i0[3];
+        R d0[3];
+        PosIO<R, D>::load(a, p, i0, d0);
+        R w[3];
+        for (int ax = 0; ax < 3; ++ax) w[ax] = ((const R*)a.mom[ax])[p];
+        const R qp = (R)a.q * ((const R*)a.weight)[p];
+
+        Axis<R> ax0[3];
+        for (int ax = 0; ax < D; ++ax) ax0[ax] = form_factor<R>(d0[ax]);
+        if (D == 2) ax0[2] = form_factor<R>(R(0));
+
+        // position relative to the tile, periodic-corrected
+        int rel[3];
+        bool inside = true;
+        for (int ax = 0; ax < D; ++ax) {
+            int r = i0[ax] - T0[ax];
+            const int n = g.n[ax];
+            if (r > n / 2) r -= n;
+            if (r < -(n / 2)) r += n;
+            rel[ax] = r;
+            inside = inside && (r >= -M) && (r <= T - 1 + M);
+        }
+        if (D == 2) rel[2] = 0;
+
+        R E[3], B[3];
+        if (inside) {
+            const int base = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SFY +
+                             (D == 3 ? (rel[2] + 1 + M) * SFZ : 0);
+            auto F = [&](int comp, int da, int db, int dc) -> R {
+                return sf[comp * NF + base + da + db * SFY + (D == 3 ? dc * SFZ : 0)];
+            };
+            if (D == 3) gather3<R>(ax0, F, E, B);
+            else gather2<R>(ax0, F, E, B);
+        } else {
+            ++my_fallback;
+            int xi[3], yj[3];
+            int64_t zk[3];
+            for (int o = 0; o < 3; ++o) {
+                xi[o] = wrapi(i0[0] + o - 1, nx);
+                yj[o] = wrapi(i0[1] + o - 1, ny) * nx;
+                zk[o] = D == 3 ? (int64_t)wrapi(i0[2] + o - 1, nz) * nx * ny : 0;
+            }
+            auto F = [&](int comp, int da, int db, int dc) -> R {
+                return (R)fields[comp * N + zk[dc + 1] + yj[db + 1] + xi[da + 1]];
+            };
+            if (D == 3) gather3<R>(ax0, F, E, B);
+            else gather2<R>(ax0, F, E, B);
+        }
+        for (int ax = 0; ax < 3; ++ax) B[ax] += bext[ax];
+
+        push<R>(qmdt2, c2, E, B, w);
+        for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
+
+        const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
+        R disp[3];
+        for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * cfl[ax];
+        R d1[3];
+        int delta[3] = {0, 0, 0};
+        PosIO<R, D>::move(a, p, g, i0, d0, disp, d1, delta, true);
+
+        // deposit
+        R dm[3][4], dp[3][4];
+        for (int ax = 0; ax < D; ++ax) {
+            R s1[3];
+            cell_weights<R>(d1[ax], s1);
+            window<R>(ax0[ax].s, s1, delta[ax], dm[ax], dp[ax]);
+        }
+        R jfac[3];
+        for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+        const R jz2 = D == 2 ? qp * (R)(0.25 * g.inv_vol) * c * w[2] * inv : R(0);
+        int s[3];
+        for (int ax = 0; ax < 3; ++ax) s[ax] = (ax < D) ? rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1 : 0;
+
+        if (inside) {
+            const int jb = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (D == 3 ? (s[2] + 2 + M) * SJZ : 0);
+            auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                sj.add(comp * NJ + jb + ix + iy * SJY + (D == 3 ? iz * SJZ : 0), v);
+            };
+            if (D == 3) deposit3<R>(dm, dp, jfac, S);
+            else deposit2<R>(dm, dp, jfac, jz2, S);
+        } else {
+            int xi[4], yj[4];
+            int64_t zk[4];
+            for (int o = 0; o < 4; ++o) {
+                xi[o] = wrapi(T0[0] + s[0] + o, nx);
+                yj[o] = wrapi(T0[1] + s[1] + o, ny) * nx;
+                zk[o] = D == 3 ? (int64_t)wrapi(T0[2] + s[2] + o, nz) * nx * ny : 0;
+            }
+            auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
+            };
+            if (D == 3) deposit3<R>(dm, dp, jfac, S);
+            else deposit2<R>(dm, dp, jfac, jz2, S);
+        }
+    }
+    if (my_fallback) atomicAdd(&n_fallback, my_fallback);
+    __syncthreads();
+
+    // 4. flush the LDS current tile
+    for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
+        const double v = sj.get(e);
+        if (v == 0.0) continue;
+        const int comp = e / NJ;
+        const int r = e - comp * NJ;
+        const int lx = r % LJ;
+        const int ly = (r / LJ) % LJ;
+        const int lz = D == 3 ? r / (LJ * LJ) : 0;
+        const int gx = wrapi(T0[0] - 2 - M + lx, nx);
+        const int gy = wrapi(T0[1] - 2 - M + ly, ny);
+        const int gz = D == 3 ? wrapi(T0[2] - 2 - M + lz, nz) : 0;
+        global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
+    }
+    if (threadIdx.x == 0 && a.counters) {
+        atomicAdd(&a.counters[1], (unsigned long long)n_fallback);
+        atomicAdd(&a.counters[2], (unsigned long long)(end - begin));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Standalone current of position pairs (pic_deposit_J): same arithmetic,
+// global atomics.
+// ---------------------------------------------------------------------------
+template <class R, int D>
+__global__ __launch_bounds__(256) void k_deposit_pairs(GridK g, const double* __restrict__ x0,
+                                                       const double* __restrict__ x1,
+                                                       const double* __restrict__ charge, int64_t n,
+                                                       double* __restrict__ Jg)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    int i0[3] = {0, 0, 0};
+    R d0[3] = {0, 0, 0}, disp[3] = {0, 0, 0}, d1[3] = {0, 0, 0};
+    int delta[3] = {0, 0, 0};
+    for (int ax = 0; ax < D; ++ax) {
+        const double a0 = x0[ax * n + p], a1 = x1[ax * n + p];
+        double fl = floor(a0);
+        R o = (R)(a0 - fl);
+        if (o >= R(1)) {  // FP32 rounding of an offset just below 1
+            o = R(0);
+            fl += 1.0;
+        }
+        i0[ax] = wrapi((int)fl, g.n[ax]);
+        d0[ax] = o;
+        disp[ax] = (R)(a1 - a0);
+    }
+    StepArgs dummy{};
+    PosIO<R, D>::move(dummy, p, g, i0, d0, disp, d1, delta, false);
+    const R qp = (R)charge[p];
+    R dm[3][4], dp[3][4];
+    for (int ax = 0; ax < D; ++ax) {
+        R s0[3], s1[3];
+        cell_weights<R>(d0[ax], s0);
+        cell_weights<R>(d1[ax], s1);
+        window<R>(s0, s1, delta[ax], dm[ax], dp[ax]);
+    }
+    R jfac[3];
+    for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+    // 2D: J^z from the z displacement, u_z = (z1 - z0) dz / dt
+    const R jz2 = D == 2 ? qp * (R)(0.25 * g.inv_vol * (x1[2 * n + p] - x0[2 * n + p]) /
+                                    g.inv_h[2] / g.dt)
+                         : R(0);
+    int xi[4], yj[4];
+    int64_t zk[4];
+    int s[3];
+    for (int ax = 0; ax < 3; ++ax) s[ax] = (ax < D) ? i0[ax] + (delta[ax] < 0 ? -1 : 0) - 1 : 0;
+    for (int o = 0; o < 4; ++o) {
+        xi[o] = wrapi(s[0] + o, nx);
+        yj[o] = wrapi(s[1] + o, ny) * nx;
+        zk[o] = D == 3 ? (int64_t)wrapi(s[2] + o, nz) * nx * ny : 0;
+    }
+    auto S = [&](int comp, int ix, int iy, int iz, R v) {
+        global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
+    };
+    if (D == 3) deposit3<R>(dm, dp, jfac, S);
+    else deposit2<R>(dm, dp, jfac, jz2, S);
+}
+
+// ---------------------------------------------------------------------------
+// Load (FP64 input -> species layout) and readback.
+// ---------------------------------------------------------------------------
+template <class R, int D>
+__global__ __launch_bounds__(256) void k_load(GridK g, PartArrays dst, int64_t offset,
+                                              const double* __restrict__ x,
+                                              const double* __restrict__ w,
+                                              const double* __restrict__ weight, int64_t n,
+                                              unsigned long long* bad)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const int64_t q = offset + p;
+    bool ok = true;
+    int ic[3] = {0, 0, 0};
+    for (int ax = 0; ax < 3; ++ax) {
+        const double v = x[ax * n + p];
+        if (ax < D) ok = ok && (v >= 0.0) && (v < (double)g.n[ax]);
+        if (sizeof(R) == 8) {
+            ((double*)dst.pos[ax])[q] = v;
+        } else if (ax < D) {
+            double fl = floor(v);
+            float o = (float)(v - fl);
+            if (o >= 1.0f) {
+                o = 0.0f;
+                fl += 1.0;
+            }
+            int ci = (int)fl;
+            if (ci >= g.n[ax]) ci -= g.n[ax];
+            ic[ax] = ci;
+            ((float*)dst.pos[ax])[q] = o;
+        }
+        ((R*)dst.mom[ax])[q] = (R)w[ax * n + p];
+    }
+    const double wt = weight[p];
+    ok = ok && (wt > 0.0) && isfinite(wt);
+    ((R*)dst.weight)[q] = (R)wt;
+    if (sizeof(R) == 4) dst.cell[q] = pack_cell(ic[0], ic[1], ic[2]);
+    dst.id[q] = q;
+    if (!ok) atomicAdd(bad, 1ull);
+}
+
+template <class R, int D>
+__global__ __launch_bounds__(256) void k_get(PartArrays src, int64_t n, double* __restrict__ x,
+                                             double* __restrict__ w, double* __restrict__ weight,
+                                             int64_t* __restrict__ id)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int ic[3] = {0, 0, 0};
+    if (sizeof(R) == 4) unpack_cell(src.cell[p], ic);
+    for (int ax = 0; ax < 3; ++ax) {
+        if (x) {
+            double v;
+            if (sizeof(R) == 8) v = ((const double*)src.pos[ax])[p];
+            else v = ax < D ? (double)ic[ax] + (double)((const float*)src.pos[ax])[p] : 0.5;
+            x[ax * n + p] = v;
+        }
+        if (w) w[ax * n + p] = (double)((const R*)src.mom[ax])[p];
+    }
+    if (weight) weight[p] = (double)((const R*)src.weight)[p];
+    if (id) id[p] = src.id[p];
+}
+
+// Charge density of particles (Eq. rho), FP64, global atomics.
+template <class R, int D>
+__global__ __launch_bounds__(256) void k_rho(GridK g, PartArrays src, int64_t n, double q,
+                                             double* __restrict__ rho)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int i[3] = {0, 0, 0};
+    double d[3] = {0, 0, 0};
+    if (sizeof(R) == 4) {
+        unpack_cell(src.cell[p], i);
+        for (int ax = 0; ax < D; ++ax) d[ax] = (double)((const float*)src.pos[ax])[p];
+    } else {
+        for (int ax = 0; ax < D; ++ax) {
+            const double x = ((const double*)src.pos[ax])[p];
+            const double fl = floor(x);
+            i[ax] = (int)fl;
+            d[ax] = x - fl;
+        }
+    }
+    double s[3][3];
+    for (int ax = 0; ax < 3; ++ax) cell_weights<double>(ax < D ? d[ax] : 0.0, s[ax]);
+    const double qv = q * (double)((const R*)src.weight)[p] * g.inv_vol;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    for (int c = (D == 3 ? -1 : 0); c <= (D == 3 ? 1 : 0); ++c) {
+        const double wz = D == 3 ? s[2][c + 1] : 1.0;
+        const int64_t kz = (int64_t)wrapi(i[2] + c, nz) * ny * nx;
+        for (int b = -1; b <= 1; ++b) {
+            const int64_t jy = (int64_t)wrapi(i[1] + b, ny) * nx;
+            for (int a2 = -1; a2 <= 1; ++a2)
+                global_add(&rho[kz + jy + wrapi(i[0] + a2, nx)], qv * wz * s[1][b + 1] * s[0][a2 + 1]);
+        }
+    }
+}
+
+// Charge density of FP64 position arrays [3][n] (immobile species at load).
+template <int D>
+__global__ __launch_bounds__(256) void k_rho_raw(GridK g, const double* __restrict__ x,
+                                                 const double* __restrict__ weight, double q,
+                                                 int64_t n, double* __restrict__ rho)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int i[3] = {0, 0, 0};
+    double s[3][3];
+    for (int ax = 0; ax < 3; ++ax) {
+        double d = 0.0;
+        if (ax < D) {
+            const double v = x[ax * n + p];
+            const double fl = floor(v);
+            i[ax] = (int)fl;
+            d = v - fl;
+        }
+        cell_weights<double>(d, s[ax]);
+    }
+    const double qv = q * weight[p] * g.inv_vol;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    for (int c = (D == 3 ? -1 : 0); c <= (D == 3 ? 1 : 0); ++c) {
+        const double wz = D == 3 ? s[2][c + 1] : 1.0;
+        const int64_t kz = (int64_t)wrapi(i[2] + c, nz) * ny * nx;
+        for (int b = -1; b <= 1; ++b) {
+            const int64_t jy = (int64_t)wrapi(i[1] + b, ny) * nx;
+            for (int a2 = -1; a2 <= 1; ++a2)
+                global_add(&rho[kz + jy + wrapi(i[0] + a2, nx)], qv * wz * s[1][b + 1] * s[0][a2 + 1]);
+        }
+    }
+}
+
+template <class R>
+StepArgs step_args(const Species& sp, unsigned long long* counters)
+{
+    StepArgs a{};
+    for (int ax = 0; ax < 3; ++ax) {
+        a.pos[ax] = sp.cur.pos[ax];
+        a.mom[ax] = sp.cur.mom[ax];
+    }
+    a.weight = sp.cur.weight;
+    a.cell = sp.cur.cell;
+    a.tile_start = sp.tile_start;
+    a.q = sp.d.q;
+    a.qm = sp.d.q / sp.d.m;
+    a.counters = counters;
+    return a;
+}
+
+// Tile and threads per workgroup of each instantiation.
+constexpr int kThreads3 = 512;
+constexpr int kThreads2 = 256;
+constexpr int kMargin3 = 1;
+constexpr int kMargin2 = 2;
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
+{
+    if (sp.n == 0) return hipSuccess;
+    double* J = c.fields + 6 * c.k.ncell;
+    const dim3 grid(c.k.ntiles);
+    if (c.g.precision == PIC_FP64) {
+        StepArgs a = step_args<double>(sp, c.counters);
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_particle_step<double, 3, kTile3, kMargin3, kThreads3>), grid,
+                               dim3(kThreads3), 0, s, c.k, a, c.fields, J);
+        else
+            hipLaunchKernelGGL((k_particle_step<double, 2, kTile2, kMargin2, kThreads2>), grid,
+                               dim3(kThreads2), 0, s, c.k, a, c.fields, J);
+    } else {
+        StepArgs a = step_args<float>(sp, c.counters);
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_particle_step<float, 3, kTile3, kMargin3, kThreads3>), grid,
+                               dim3(kThreads3), 0, s, c.k, a, c.fields, J);
+        else
+            hipLaunchKernelGGL((k_particle_step<float, 2, kTile2, kMargin2, kThreads2>), grid,
+                               dim3(kThreads2), 0, s, c.k, a, c.fields, J);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_only(const Ctx& c, const double* x0, const double* x1,
+                               const double* charge, int64_t n, double* J, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const dim3 grid(blocks_for(n));
+    if (c.g.precision == PIC_FP64) {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_deposit_pairs<double, 3>), grid, dim3(256), 0, s, c.k, x0, x1, charge, n, J);
+        else
+            hipLaunchKernelGGL((k_deposit_pairs<double, 2>), grid, dim3(256), 0, s, c.k, x0, x1, charge, n, J);
+    } else {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_deposit_pairs<float, 3>), grid, dim3(256), 0, s, c.k, x0, x1, charge, n, J);
+        else
+            hipLaunchKernelGGL((k_deposit_pairs<float, 2>), grid, dim3(256), 0, s, c.k, x0, x1, charge, n, J);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_load(Ctx& c, Species& sp, int64_t n, const double* x, const double* w,
+                       const double* weight, hipStream_t s)
+{
+    const dim3 grid(blocks_for(n));
+    unsigned long long* bad = c.counters;
+    if (c.g.precision == PIC_FP64) {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_load<double, 3>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, x, w, weight, n, bad);
+        else
+            hipLaunchKernelGGL((k_load<double, 2>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, x, w, weight, n, bad);
+    } else {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_load<float, 3>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, x, w, weight, n, bad);
+        else
+            hipLaunchKernelGGL((k_load<float, 2>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, x, w, weight, n, bad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_get(const Ctx& c, const Species& sp, double* x, double* w, double* weight,
+                      int64_t* id, hipStream_t s)
+{
+    if (sp.n == 0) return hipSuccess;
+    const dim3 grid(blocks_for(sp.n));
+    if (c.g.precision == PIC_FP64) {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_get<double, 3>), grid, dim3(256), 0, s, sp.cur, sp.n, x, w, weight, id);
+        else
+            hipLaunchKernelGGL((k_get<double, 2>), grid, dim3(256), 0, s, sp.cur, sp.n, x, w, weight, id);
+    } else {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_get<float, 3>), grid, dim3(256), 0, s, sp.cur, sp.n, x, w, weight, id);
+        else
+            hipLaunchKernelGGL((k_get<float, 2>), grid, dim3(256), 0, s, sp.cur, sp.n, x, w, weight, id);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rho(const Ctx& c, const Species& sp, double* rho, hipStream_t s)
+{
+    if (sp.n == 0) return hipSuccess;
+    const dim3 grid(blocks_for(sp.n));
+    if (c.g.precision == PIC_FP64) {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_rho<double, 3>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, sp.d.q, rho);
+        else
+            hipLaunchKernelGGL((k_rho<double, 2>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, sp.d.q, rho);
+    } else {
+        if (c.k.dims == 3)
+            hipLaunchKernelGGL((k_rho<float, 3>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, sp.d.q, rho);
+        else
+            hipLaunchKernelGGL((k_rho<float, 2>), grid, dim3(256), 0, s, c.k, sp.cur, sp.n, sp.d.q, rho);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_raw(const Ctx& c, const double* x, const double* weight, double charge,
+                          int64_t n, double* rho, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const dim3 grid(blocks_for(n));
+    if (c.k.dims == 3)
+        hipLaunchKernelGGL((k_rho_raw<3>), grid, dim3(256), 0, s, c.k, x, weight, charge, n, rho);
+    else
+        hipLaunchKernelGGL((k_rho_raw<2>), grid, dim3(256), 0, s, c.k, x, weight, charge, n, rho);
+    return hipGetLastError();
+}
+
+}  // namespace pic

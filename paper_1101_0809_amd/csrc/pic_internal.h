@@ -1,0 +1,106 @@
+// pic_internal.h -- internal declarations of the gfx950 PIC library: the
+// context, the particle-buffer layouts and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxSpecies = 4;
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Tile edge (cells) of the particle-step kernel, per dimensionality.
+constexpr int kTile3 = 8;
+constexpr int kTile2 = 16;
+
+// Particle arrays of one copy (the library keeps two for out-of-place sorts).
+// FP64 mode: pos[a] are double absolute positions in [0, N_a).
+// FP32 mode: cell packs (i | j << 11 | k << 22), pos[a] are float offsets in [0, 1).
+struct PartArrays {
+    void* pos[3];
+    void* mom[3];
+    void* weight;
+    uint32_t* cell;  // FP32 mode only
+    int64_t* id;
+};
+
+struct Species {
+    pic_species_desc d{};
+    int64_t n = 0;
+    char* buf = nullptr;
+    size_t bytes = 0;
+    PartArrays cur{}, alt{};
+    uint32_t* key = nullptr;   // sort key per particle
+    uint32_t* rank = nullptr;  // rank within the key bucket (from the histogram atomics)
+    int64_t* tile_start = nullptr;  // ntiles + 1 entries
+    bool sorted = false;
+};
+
+// Grid constants handed to kernels by value.
+struct GridK {
+    int n[3];        // cells per axis
+    int nt[3];       // tiles per axis
+    int tile[3];     // tile edge per axis (1 for z in 2D)
+    int dims;
+    int ntiles;
+    int64_t ncell;
+    double cfl[3];   // c dt / d_a
+    double half_cfl[3];
+    double dt, c;
+    double bext[3];
+    double inv_vol;  // 1 / (dx dy dz)
+    double jscale[3];  // -(1/4) d_a / dt / V : xi -> J factor per unit charge
+    double fourpidt;   // 4 pi dt
+    double inv_h[3];   // 1 / d_a
+};
+
+struct Ctx {
+    pic_grid_desc g{};
+    GridK k{};
+    double* fields = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    // workspace carve-up
+    double* rho_bg = nullptr;   // immobile charge density
+    double* r0 = nullptr;       // Gauss reference R^0
+    double* rho_m = nullptr;    // scratch: mobile charge density
+    uint32_t* hist = nullptr;   // nkeys + 1 counts / offsets
+    uint32_t* scan_part = nullptr;
+    double* red = nullptr;      // reduction partials
+    unsigned long long* counters = nullptr;  // [0] range errors, [1] fallback particles,
+                                             // [2] particles processed
+    uint32_t nkeys = 0;
+    Species sp[kMaxSpecies];
+    int nsp = 0;
+    int64_t step = 0;
+    int since_sort = 0;
+    bool r0_valid = false;
+    std::string err;
+};
+
+size_t align_up(size_t v, size_t a);
+
+// ---- launchers (stream = hipStream_t) ----
+hipError_t launch_field_half_b(const Ctx& c, hipStream_t s);
+hipError_t launch_field_update_e(const Ctx& c, hipStream_t s);
+hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s);
+hipError_t launch_load(Ctx& c, Species& sp, int64_t n, const double* x, const double* w,
+                       const double* weight, hipStream_t s);
+hipError_t launch_get(const Ctx& c, const Species& sp, double* x, double* w, double* weight,
+                      int64_t* id, hipStream_t s);
+hipError_t launch_deposit_only(const Ctx& c, const double* x0, const double* x1,
+                               const double* charge, int64_t n, double* J, hipStream_t s);
+hipError_t launch_rho(const Ctx& c, const Species& sp, double* rho, hipStream_t s);
+hipError_t launch_rho_raw(const Ctx& c, const double* x, const double* weight, double charge,
+                          int64_t n, double* rho, hipStream_t s);
+hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t s);
+hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s);
+hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
+
+}  // namespace pic

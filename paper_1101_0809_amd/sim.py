@@ -1,0 +1,216 @@
+"""Thin Python front end of the gfx950 PIC library.
+
+PyTorch provides the device memory (every buffer is a torch tensor on the
+GPU) and the stream (torch's current stream); each method marshals pointers
+and sizes into one C-ABI call of ``include/pic.h``.  No step of the method
+runs in Python.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(a, device) -> torch.Tensor:
+    t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64))
+    return t.to(device=device, dtype=torch.float64).contiguous()
+
+
+@dataclass
+class SpeciesInfo:
+    index: int
+    q: float
+    m: float
+    mobile: bool
+    capacity: int
+    buffer: torch.Tensor = None
+
+
+class Sim:
+    """One simulation context: grid, fields and particle species on one GPU.
+
+    Positions are in cell units, momenta are w = gamma v (momentum over
+    mass); see include/pic.h for the conventions.
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, dt: float, dims: int = 3,
+                 precision: str = "fp64", dx: float = 1.0, dy: float = 1.0, dz: float = 1.0,
+                 c: float = 1.0, sort_every: int = 0, bext=(0.0, 0.0, 0.0),
+                 device: str = "cuda:0", fields: np.ndarray = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
+        self.lib = L.load()
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        d = L.GridDesc()
+        d.dims, d.nx, d.ny, d.nz = dims, nx, ny, nz
+        d.precision = {"fp64": L.PIC_FP64, "fp32c": L.PIC_FP32C}[precision]
+        d.order, d.sort_every, d.reserved = 1, sort_every, 0
+        d.dx, d.dy, d.dz, d.dt, d.c = dx, dy, dz, dt, c
+        for a in range(3):
+            d.bext[a] = float(bext[a])
+        self.desc = d
+        self.precision = precision
+        self.shape = (nz, ny, nx)
+        self.ncell = nx * ny * nz
+        sz = L.Sizes()
+        L.check(self.lib.pic_query_sizes(ctypes.byref(d), 0, ctypes.byref(sz)))
+        self.fields_t = torch.zeros(9 * self.ncell, dtype=torch.float64, device=self.device)
+        if fields is not None:
+            self.fields_t.copy_(_dev_f64(fields, self.device).reshape(-1))
+        self.workspace = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        L.check(self.lib.pic_init_grid(ctypes.byref(d), ctypes.c_void_p(self.fields_t.data_ptr()),
+                                       sz.field_bytes, ctypes.c_void_p(self.workspace.data_ptr()),
+                                       sz.workspace_bytes, ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.species = []
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            torch.cuda.synchronize()
+            self.lib.pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        L.check(rc, self.ctx)
+
+    # -- particles -------------------------------------------------------
+    def add_species(self, q: float, m: float, capacity: int, mobile: bool = True) -> int:
+        s = L.SpeciesDesc()
+        s.q, s.m, s.mobile, s.reserved, s.capacity = q, m, int(mobile), 0, capacity
+        buf = None
+        nbytes = 0
+        if mobile:
+            sz = L.Sizes()
+            L.check(self.lib.pic_query_sizes(ctypes.byref(self.desc), capacity, ctypes.byref(sz)))
+            buf = torch.empty(sz.particle_bytes, dtype=torch.uint8, device=self.device)
+            nbytes = sz.particle_bytes
+        idx = ctypes.c_int()
+        self._check(self.lib.pic_add_species(
+            self.ctx, ctypes.byref(s), ctypes.c_void_p(buf.data_ptr() if buf is not None else 0),
+            nbytes, ctypes.byref(idx)))
+        self.species.append(SpeciesInfo(idx.value, q, m, mobile, capacity, buf))
+        return idx.value
+
+    def load(self, species: int, x, w, weight):
+        """Append particles: x, w of shape (3, n) (cell units, momentum over
+        mass), weight (n,).  Host (numpy) or device arrays."""
+        x = x if isinstance(x, torch.Tensor) else _dev_f64(x, self.device)
+        w = w if isinstance(w, torch.Tensor) else _dev_f64(w, self.device)
+        weight = weight if isinstance(weight, torch.Tensor) else _dev_f64(weight, self.device)
+        x, w, weight = (t.to(self.device, torch.float64).contiguous() for t in (x, w, weight))
+        n = weight.numel()
+        assert x.numel() == 3 * n and w.numel() == 3 * n
+        self._check(self.lib.pic_load_particles(
+            self.ctx, species, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+            ctypes.c_void_p(weight.data_ptr()), _stream()))
+
+    def count(self, species: int = 0) -> int:
+        return int(self.lib.pic_particle_count(self.ctx, species))
+
+    def particles(self, species: int = 0):
+        """Return (x, w, weight, id) as host numpy arrays in id order."""
+        n = self.count(species)
+        x = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        w = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        wt = torch.empty(n, dtype=torch.float64, device=self.device)
+        pid = torch.empty(n, dtype=torch.int64, device=self.device)
+        self._check(self.lib.pic_get_particles(
+            self.ctx, species, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+            ctypes.c_void_p(wt.data_ptr()), ctypes.c_void_p(pid.data_ptr()), _stream()))
+        torch.cuda.synchronize()
+        order = torch.argsort(pid)
+        return (x[:, order].cpu().numpy(), w[:, order].cpu().numpy(),
+                wt[order].cpu().numpy(), pid[order].cpu().numpy())
+
+    # -- stepping --------------------------------------------------------
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.pic_step(self.ctx, nsteps, _stream()))
+
+    def sort(self):
+        self._check(self.lib.pic_sort(self.ctx, _stream()))
+
+    def field_solve(self, what: str):
+        op = {"b_half": L.PIC_B_HALF, "e_full": L.PIC_E_FULL}[what]
+        self._check(self.lib.pic_field_solve(self.ctx, op, _stream()))
+
+    def deposit(self, x0, x1, charge) -> torch.Tensor:
+        """Current J (3, nz, ny, nx) of particles moving x0 -> x1 (arrays (3, n))."""
+        x0 = _dev_f64(x0, self.device) if not isinstance(x0, torch.Tensor) else x0.contiguous()
+        x1 = _dev_f64(x1, self.device) if not isinstance(x1, torch.Tensor) else x1.contiguous()
+        q = _dev_f64(charge, self.device) if not isinstance(charge, torch.Tensor) else charge.contiguous()
+        J = torch.zeros((3,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.pic_deposit_J(
+            self.ctx, ctypes.c_void_p(x0.data_ptr()), ctypes.c_void_p(x1.data_ptr()),
+            ctypes.c_void_p(q.data_ptr()), q.numel(), ctypes.c_void_p(J.data_ptr()), _stream()))
+        return J
+
+    def diagnostics(self) -> dict:
+        d = L.Diag()
+        self._check(self.lib.pic_diagnostics(self.ctx, ctypes.byref(d), _stream()))
+        return d.as_dict()
+
+    def timing_start(self, max_steps: int):
+        self._check(self.lib.pic_timing_start(self.ctx, max_steps))
+
+    def timing_stop(self):
+        """Summed event times (ms) of the recorded steps: dict with b_half,
+        particles, e_update, sort and the number of steps."""
+        ms = (ctypes.c_double * 4)()
+        n = ctypes.c_int64()
+        self._check(self.lib.pic_timing_stop(self.ctx, ms, ctypes.byref(n)))
+        return {"b_half": ms[0], "particles": ms[1], "e_update": ms[2], "sort": ms[3],
+                "steps": n.value}
+
+    def fallback_fraction(self) -> float:
+        return float(self.lib.pic_last_fallback_fraction(self.ctx, _stream()))
+
+    # -- fields ----------------------------------------------------------
+    @property
+    def fields(self) -> torch.Tensor:
+        """(9, nz, ny, nx) view: Ex Ey Ez Bx By Bz Jx Jy Jz."""
+        return self.fields_t.view((9,) + self.shape)
+
+    def fields_numpy(self) -> np.ndarray:
+        torch.cuda.synchronize()
+        return self.fields.cpu().numpy()
+EOF
+cat > /root/repo/paper_1101_0809_amd/__init__.py <<'EOF'
+"""MI355X (gfx950) implementation of the per-particle step of the
+charge-conserving PIC scheme with alternating-order interpolation
+(Sokolov, arXiv:1101.0809).
+
+The compute path is the HIP library ``libpic.so`` (C ABI in include/pic.h);
+``Sim`` is a thin PyTorch-backed front end that owns device buffers and
+passes pointers.
+"""
+from ._lib import PicError, load as load_library  # noqa: F401
+
+__all__ = ["Sim", "PicError", "load_library"]
+
+
+def __getattr__(name):
+    if name == "Sim":
+        from .sim import Sim
+        return Sim
+    raise AttributeError(name)
+EOF
+echo ok

@@ -1,0 +1,277 @@
+"""GPU (HIP, gfx950) vs FP64 CPU oracle, element by element, through the C ABI.
+
+Tolerances.  FP64 mode: the GPU evaluates the same formulas in another order
+and with fused multiply-adds, so single operations differ in the last bit
+(~1e-16 relative); the charge-conserving current differences F(x1) - F(x0)
+cancel to the size of one move, amplifying that to ~1e-13 of the current.
+Over a run, plasma dynamics amplify differences by a modest factor
+(omega_pe t <= 2.5 here).  The bars: relative field error <= 1e-12 (2-norm
+per field), particle state <= 1e-12 relative, Gauss-law drift <= 1e-12 of
+max |4 pi rho_e|.  FP32 mode is compared with the FP64 oracle and its error
+is reported; only the Gauss drift (<= 1e-6) is a hard bar there, plus a loose
+bound on the field error stated in each test.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import picgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(**kw):
+    from paper_1101_0809_amd import Sim
+    return Sim(**kw)
+
+
+def _rel(a, b):
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / den if den > 0 else np.linalg.norm(a - b)
+
+
+def _wrapdiff(a, b, n):
+    d = a - b
+    return d - n * np.round(d / n)
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32c", 3e-6)])
+@pytest.mark.parametrize("dims", [3, 2])
+def test_deposit_matches_oracle(precision, tol, dims):
+    """pic_deposit_J of many random moves (several tiles, moves across the
+    periodic boundary, a ragged count) equals the oracle's current."""
+    n = 16
+    nz = n if dims == 3 else 1
+    sim = _sim(nx=n, ny=12, nz=nz, dt=0.41, dims=dims, precision=precision,
+               dx=1.1, dy=0.9, dz=1.0)
+    g = oracle.Grid(n, 12, nz, 0.41, dx=1.1, dy=0.9, dz=1.0)
+    x0, x1 = picgen.random_moves(1237, seed=5, box=(n, 12, nz), max_step=0.9)
+    if dims == 2:
+        x1[2] = x0[2] + (x1[2] - x0[2]) * 0.5
+    if precision == "fp32c":
+        # the FP32 path represents positions as cell + FP32 offset: give both
+        # sides the same representable start and displacement
+        x0 = np.floor(x0) + (x0 - np.floor(x0)).astype(np.float32).astype(np.float64)
+        x1 = x0 + (x1 - x0).astype(np.float32).astype(np.float64)
+    q = np.random.Generator(np.random.PCG64(6)).uniform(-1, 1, x0.shape[1])
+    J = sim.deposit(x0, x1, q).cpu().numpy()
+    ref = np.zeros((3,) + g.shape)
+    for p in range(x0.shape[1]):
+        oracle.deposit(g, x0[:, p], x1[:, p], q[p], J=ref)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(J - ref)) / scale < tol
+
+
+def test_field_solve_matches_oracle():
+    n = (10, 9, 8)
+    rng = np.random.Generator(np.random.PCG64(3))
+    fields = rng.normal(0, 1, (9, n[2], n[1], n[0]))
+    sim = _sim(nx=n[0], ny=n[1], nz=n[2], dt=0.45, dims=3, dx=1.0, dy=1.2, dz=0.9, fields=fields)
+    g = oracle.Grid(*n, 0.45, dx=1.0, dy=1.2, dz=0.9)
+    ref = fields.copy()
+    sim.field_solve("b_half")
+    oracle.half_b(g, ref)
+    assert np.max(np.abs(sim.fields_numpy() - ref)) < 1e-14
+    sim.field_solve("e_full")
+    oracle.half_b(g, ref)
+    oracle.update_e(g, ref)
+    ref[6:9] = 0.0
+    assert np.max(np.abs(sim.fields_numpy() - ref)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# whole runs
+# ---------------------------------------------------------------------------
+
+def _run_pair(wl, precision, steps, sort_every=None, ions=True):
+    e = picgen.electrons(wl)
+    sim = _sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=wl.dims, precision=precision,
+               sort_every=wl.sort_every if sort_every is None else sort_every, bext=wl.bext)
+    se = sim.add_species(e.q, e.m, e.n)
+    sim.load(se, e.x, e.w, e.weight)
+    species = [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m)]
+    if ions:
+        ion = picgen.ions_like(wl, e)
+        si = sim.add_species(ion.q, ion.m, 0, mobile=False)
+        sim.load(si, ion.x, ion.w, ion.weight)
+        species.append(oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=False))
+    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext), species)
+    sim.step(steps)
+    st.step(steps)
+    return sim, st, e
+
+
+def _compare(sim, st, wl, field_tol, part_tol, gauss_tol):
+    F = sim.fields_numpy()
+    for c, name in enumerate(["Ex", "Ey", "Ez", "Bx", "By", "Bz"]):
+        err = _rel(F[c], st.fields[c])
+        assert err <= field_tol, (name, err)
+    x, w, _, ids = sim.particles(0)
+    sp = st.species[0]
+    dims = wl.dims
+    for a, n in enumerate((wl.nx, wl.ny, wl.nz)[:dims]):
+        dx = _wrapdiff(x[a], sp.x[a], n)
+        assert np.max(np.abs(dx)) <= part_tol * n, ("x", a, np.max(np.abs(dx)))
+    werr = np.max(np.abs(w - sp.w)) / np.max(np.abs(sp.w))
+    assert werr <= part_tol, ("w", werr)
+    d = sim.diagnostics()
+    assert d["gauss_rel"] <= gauss_tol, d
+    assert d["nonfinite"] == 0
+    # the oracle's own Gauss drift, for reference
+    return d
+
+
+def test_2d3v_32x32_fp64_parity():
+    """The 32x32 2D3V parity workload: 4096 electrons, 100 steps, FP64."""
+    wl = picgen.WORKLOADS["2d3v_32x32_fp64"]
+    sim, st, _ = _run_pair(wl, "fp64", wl.steps, sort_every=10)
+    _compare(sim, st, wl, 1e-12, 1e-12, 1e-12)
+
+
+def test_3d_small_fp64_parity():
+    """3D, 16^3 cells (8 tiles) x 8 per cell, 20 steps, re-sorted every 5 steps
+    (so particles drift out of their tiles between sorts)."""
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=16, ny=16, nz=16, steps=20, sort_every=5)
+    sim, st, _ = _run_pair(wl, "fp64", wl.steps)
+    _compare(sim, st, wl, 1e-12, 1e-12, 1e-12)
+
+
+def test_3d_ragged_tiles_fp64_parity():
+    """Cell counts that are not multiples of the tile (partial tiles), hot
+    plasma so many particles take the out-of-tile path, no re-sort."""
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=13, ny=10, nz=11, w_th=(0.5, 0.5, 0.5),
+                                                  ppc=3, steps=12, sort_every=0)
+    sim, st, _ = _run_pair(wl, "fp64", wl.steps)
+    assert sim.fallback_fraction() > 0.0
+    _compare(sim, st, wl, 1e-12, 1e-12, 1e-12)
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_fp32c_against_fp64_oracle(dims):
+    """FP32 mode vs the FP64 oracle: Gauss drift <= 1e-6 (hard), field and
+    particle errors within the FP32 rounding envelope (reported)."""
+    if dims == 2:
+        wl = picgen.WORKLOADS["2d3v_32x32_fp64"].scaled(steps=40)
+    else:
+        wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=16, ny=16, nz=16, steps=20, sort_every=5)
+    sim, st, _ = _run_pair(wl, "fp32c", wl.steps)
+    d = _compare(sim, st, wl, 1e-3, 1e-5, 1e-6)
+    print("fp32c", dims, d)
+
+
+def test_2d_kernel_equals_3d_kernel_with_one_z_cell():
+    """The 2D3V kernels equal the 3D kernels run on an nz = 1 grid (every z sum
+    of a partition of unity is one)."""
+    wl = picgen.WORKLOADS["2d3v_32x32_fp64"].scaled(steps=10)
+    e = picgen.electrons(wl)
+    out = []
+    for dims in (2, 3):
+        sim = _sim(nx=wl.nx, ny=wl.ny, nz=1, dt=wl.dt, dims=dims, sort_every=5)
+        s = sim.add_species(e.q, e.m, e.n)
+        sim.load(s, e.x, e.w, e.weight)
+        sim.step(wl.steps)
+        x, w, _, _ = sim.particles(0)
+        out.append((sim.fields_numpy(), x, w))
+    (F2, x2, w2), (F3, x3, w3) = out
+    for c in range(6):
+        assert _rel(F2[c], F3[c]) < 1e-14 or np.max(np.abs(F3[c])) == 0
+    assert np.max(np.abs(_wrapdiff(x2[:2], x3[:2], 32))) < 1e-13
+    assert np.max(np.abs(w2 - w3)) < 1e-14 * np.max(np.abs(w3))
+
+
+def test_gyration_on_gpu():
+    """A lone electron in a uniform external B with the gyration parameters of
+    Section 5 (omega_B dt = 0.25, |w| = 0.5 c, c dt/dx = 0.5) moves on the
+    closed-form circle through the full GPU step; its weight is 1e-30 so its
+    own current leaves the fields at round-off level."""
+    dt = 0.025
+    dx = 2 * dt
+    n = 32
+    sim = _sim(nx=n, ny=n, nz=n, dt=dt, dims=3, dx=dx, dy=dx, dz=dx, bext=(0.0, 0.0, 10.0))
+    s = sim.add_species(-1.0, 1.0, 1)
+    sim.load(s, np.array([[16.0], [16.0], [16.0]]), np.array([[0.5], [0.0], [0.0]]),
+             np.array([1e-30]))
+    pts = []
+    for _ in range(64):
+        sim.step(1)
+        pts.append(sim.particles(0)[0][:, 0])
+    pts = np.array(pts)
+    gam = math.sqrt(1.25)
+    theta = 2 * math.atan(0.25 / (2 * gam))
+    R = (0.5 / gam) * dt / (2 * math.sin(theta / 2)) / dx
+    a, b, c = pts[0, :2], pts[1, :2], pts[2, :2]
+    d = 2 * (a[0] * (b[1] - c[1]) + b[0] * (c[1] - a[1]) + c[0] * (a[1] - b[1]))
+    ux = ((a @ a) * (b[1] - c[1]) + (b @ b) * (c[1] - a[1]) + (c @ c) * (a[1] - b[1])) / d
+    uy = ((a @ a) * (c[0] - b[0]) + (b @ b) * (a[0] - c[0]) + (c @ c) * (b[0] - a[0])) / d
+    r = np.hypot(pts[:, 0] - ux, pts[:, 1] - uy)
+    assert np.max(np.abs(r - R)) < 1e-11
+
+
+def test_load_rejects_out_of_range():
+    from paper_1101_0809_amd import PicError
+    sim = _sim(nx=8, ny=8, nz=8, dt=0.4, dims=3)
+    s = sim.add_species(-1.0, 1.0, 4)
+    x = np.array([[1.0, 2.0, 8.0, 3.0], [1.0, 1.0, 1.0, 1.0], [1.0, 1.0, 1.0, 1.0]])
+    with pytest.raises(PicError) as ei:
+        sim.load(s, x, np.zeros((3, 4)), np.ones(4))
+    assert ei.value.code == -2
+    assert sim.count(s) == 0
+
+
+def test_empty_species_and_zero_steps():
+    sim = _sim(nx=8, ny=8, nz=8, dt=0.4, dims=3)
+    sim.add_species(-1.0, 1.0, 16)
+    sim.step(0)
+    sim.step(3)
+    d = sim.diagnostics()
+    assert d["n_particles"] == 0 and d["gauss_abs"] == 0.0
+    assert np.all(sim.fields_numpy() == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# the full-size 64^3 x 8 workload (the benchmark configuration), sampled
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_64cube_fullsize_sampled(precision):
+    """Full 64^3 x 8 per cell (2,097,152 electrons) in the launch
+    configuration the benchmark times: after 20 steps (two re-sorts), one more
+    step is checked particle by particle on a sample against the oracle's
+    single-particle step using the GPU's own pre-step fields; the Gauss drift
+    holds over the whole grid."""
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"]
+    e = picgen.electrons(wl)
+    ion = picgen.ions_like(wl, e)
+    sim = _sim(nx=64, ny=64, nz=64, dt=wl.dt, dims=3, precision=precision, sort_every=10)
+    s = sim.add_species(e.q, e.m, e.n)
+    sim.load(s, e.x, e.w, e.weight)
+    si = sim.add_species(ion.q, ion.m, 0, mobile=False)
+    sim.load(si, ion.x, ion.w, ion.weight)
+    sim.step(20)
+    fields = sim.fields_numpy()
+    x0, w0, wt, ids = sim.particles(0)
+    sim.step(1)
+    x1, w1, _, ids1 = sim.particles(0)
+    assert np.array_equal(ids, ids1)
+    g = oracle.Grid(64, 64, 64, wl.dt)
+    bn = fields.copy()
+    oracle.half_b(g, bn)
+    rng = np.random.Generator(np.random.PCG64(99))
+    sample = rng.choice(e.n, 3000, replace=False)
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    for p in sample:
+        E, B = oracle.gather(g, bn, x0[:, p])
+        wn = oracle.push(-1.0, wl.dt, 1.0, E, B, w0[:, p])
+        xn = x0[:, p] + oracle.displacement(g, wn)
+        assert np.max(np.abs(wn - w1[:, p])) <= tol * max(1e-3, np.max(np.abs(wn)))
+        assert np.max(np.abs(_wrapdiff(xn, x1[:, p], 64))) <= tol * 64
+    d = sim.diagnostics()
+    assert d["gauss_rel"] <= (1e-12 if precision == "fp64" else 1e-6), d
+    assert d["nonfinite"] == 0
+    assert abs(d["charge"]) < 1e-9 * e.n * e.weight[0]
