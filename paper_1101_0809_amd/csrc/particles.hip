@@ -362,7 +362,10 @@ struct PosIO<double, D> {
             if (x >= N) x -= N;  // a tiny negative value can round up to N
             const double fl = floor(x);
             d1[ax] = x - fl;
-            delta[ax] = (int)rint((d0[ax] + disp[ax]) - d1[ax]);
+            // in {-1, 0, 1} for any finite move shorter than a cell; the clamp
+            // keeps window indices in range for non-finite input
+            const double dd = rint((d0[ax] + disp[ax]) - d1[ax]);
+            delta[ax] = dd > 0.5 ? 1 : (dd < -0.5 ? -1 : 0);
             if (store) ((double*)a.pos[ax])[p] = x;
         }
     }
@@ -721,7 +724,9 @@ __global__ __launch_bounds__(256) void k_load(GridK g, PartArrays dst, int64_t o
             ic[ax] = ci;
             ((float*)dst.pos[ax])[q] = o;
         }
-        ((R*)dst.mom[ax])[q] = (R)w[ax * n + p];
+        const double wv = w[ax * n + p];
+        ok = ok && isfinite(wv);
+        ((R*)dst.mom[ax])[q] = (R)wv;
     }
     const double wt = weight[p];
     ok = ok && (wt > 0.0) && isfinite(wt);

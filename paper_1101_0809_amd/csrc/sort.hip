@@ -29,6 +29,8 @@ __device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, 
     } else {
         for (int ax = 0; ax < D; ++ax) i[ax] = (int)floor(((const double*)a.pos[ax])[p]);
     }
+    for (int ax = 0; ax < 3; ++ax)  // positions are in [0, N); clamp so keys stay in range
+        i[ax] = i[ax] < 0 ? 0 : (i[ax] >= g.n[ax] ? g.n[ax] - 1 : i[ax]);
     const int tx = i[0] / T, ty = i[1] / T, tz = D == 3 ? i[2] / T : 0;
     const uint32_t tile = ((uint32_t)tz * g.nt[1] + ty) * g.nt[0] + tx;
     const uint32_t lx = i[0] - tx * T, ly = i[1] - ty * T, lz = D == 3 ? i[2] - tz * T : 0;
