@@ -797,7 +797,7 @@ __global__ __launch_bounds__(256) void k_rho(GridK g, PartArrays src, int64_t n,
 template <int D>
 __global__ __launch_bounds__(256) void k_rho_raw(GridK g, const double* __restrict__ x,
                                                  const double* __restrict__ weight, double q,
-                                                 int64_t n, double* __restrict__ rho)
+                                                 int64_t n, double* __restrict__ rho, bool w32)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
@@ -813,7 +813,10 @@ __global__ __launch_bounds__(256) void k_rho_raw(GridK g, const double* __restri
         }
         cell_weights<double>(d, s[ax]);
     }
-    const double qv = q * weight[p] * g.inv_vol;
+    // FP32 mode stores every weight in FP32; the background uses the same
+    // rounded weight so that a co-located neutral start has zero total charge
+    const double wt = w32 ? (double)(float)weight[p] : weight[p];
+    const double qv = q * wt * g.inv_vol;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     for (int c = (D == 3 ? -1 : 0); c <= (D == 3 ? 1 : 0); ++c) {
         const double wz = D == 3 ? s[2][c + 1] : 1.0;
@@ -958,10 +961,11 @@ hipError_t launch_rho_raw(const Ctx& c, const double* x, const double* weight, d
 {
     if (n == 0) return hipSuccess;
     const dim3 grid(blocks_for(n));
+    const bool w32 = c.g.precision == PIC_FP32C;
     if (c.k.dims == 3)
-        hipLaunchKernelGGL((k_rho_raw<3>), grid, dim3(256), 0, s, c.k, x, weight, charge, n, rho);
+        hipLaunchKernelGGL((k_rho_raw<3>), grid, dim3(256), 0, s, c.k, x, weight, charge, n, rho, w32);
     else
-        hipLaunchKernelGGL((k_rho_raw<2>), grid, dim3(256), 0, s, c.k, x, weight, charge, n, rho);
+        hipLaunchKernelGGL((k_rho_raw<2>), grid, dim3(256), 0, s, c.k, x, weight, charge, n, rho, w32);
     return hipGetLastError();
 }
 
