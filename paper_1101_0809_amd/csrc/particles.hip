@@ -441,7 +441,7 @@ struct LdsJ<float, NJ> {
         const float s = o + x;
         const float bv = s - o;
         const float err = (o - (s - bv)) + (x - bv);
-        if (err != 0.0f) atomicAdd(&lo[i], err);
+        atomicAdd(&lo[i], err);  // unconditional: no divergent branch per contribution
     }
     __device__ __forceinline__ double get(int i) const { return (double)hi[i] + (double)lo[i]; }
 };

@@ -1,9 +1,10 @@
 // sort.hip -- periodic counting sort of a species by cell, in tile-major cell
 // order, so that the particles of one tile (the unit of work of the particle
-// kernel) are contiguous.  Out of place: histogram with atomics (the returned
-// slot is the particle's rank in its bucket), exclusive scan of the counts,
-// scatter of every particle array into the second copy, then swap.  Not part
-// of the paper's method; it only fixes the memory order of the particles.
+// kernel) are contiguous.  Histogram with atomics (the returned slot is the
+// particle's rank in its cell), exclusive scan of the counts, scatter of every
+// particle array into the spare copy, then a per-tile pass that writes the
+// tile back rank-interleaved (see k_interleave).  Not part of the paper's
+// method; it only fixes the memory order of the particles.
 #include "pic_internal.h"
 
 namespace pic {
@@ -147,6 +148,62 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(PartArrays src, PartAr
     dst.id[q] = src.id[p];
 }
 
+// Rank-interleave the cell-sorted particles of one tile: the particles of
+// rank 0 of every cell of the tile (in cell order), then those of rank 1, and
+// so on.  Consecutive particles then sit in distinct cells, so the 64 lanes of
+// a wave that take consecutive particles update distinct LDS current entries.
+// One workgroup per tile, one thread per cell of the tile.  Writes of one
+// rank level are contiguous.
+template <class R, int TPD>
+__global__ __launch_bounds__(TPD) void k_interleave(PartArrays src, PartArrays dst,
+                                                    const uint32_t* __restrict__ offs,
+                                                    int64_t nkeys, int64_t n)
+{
+    constexpr int NW = TPD / 64;
+    __shared__ uint32_t wsum[NW];
+    __shared__ uint32_t wmax[NW];
+    const int c = threadIdx.x;
+    const int lane = c & 63, wv = c >> 6;
+    const int64_t key = (int64_t)blockIdx.x * TPD + c;
+    const int64_t cb = offs[key];
+    const int64_t ce = key + 1 < nkeys ? (int64_t)offs[key + 1] : n;
+    const uint32_t cnt = (uint32_t)(ce - cb);
+    const int64_t base = offs[(int64_t)blockIdx.x * TPD];
+    // workgroup maximum of the cell counts
+    uint32_t m = cnt;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
+    if (lane == 0) wmax[wv] = m;
+    __syncthreads();
+    uint32_t maxcnt = 0;
+    for (int w = 0; w < NW; ++w) maxcnt = max(maxcnt, wmax[w]);
+    int64_t level_base = base;
+    for (uint32_t r = 0; r < maxcnt; ++r) {
+        const bool flag = cnt > r;
+        const unsigned long long mask = __ballot(flag);
+        const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wv] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+        for (int w = 0; w < NW; ++w) {
+            pre += w < wv ? wsum[w] : 0u;
+            tot += wsum[w];
+        }
+        if (flag) {
+            const int64_t from = cb + r;
+            const int64_t to = level_base + pre + below;
+            for (int ax = 0; ax < 3; ++ax) {
+                ((R*)dst.pos[ax])[to] = ((const R*)src.pos[ax])[from];
+                ((R*)dst.mom[ax])[to] = ((const R*)src.mom[ax])[from];
+            }
+            ((R*)dst.weight)[to] = ((const R*)src.weight)[from];
+            if (sizeof(R) == 4) dst.cell[to] = src.cell[from];
+            dst.id[to] = src.id[from];
+        }
+        level_base += tot;
+        __syncthreads();
+    }
+}
+
 template <int TPD>
 __global__ void k_tile_start(const uint32_t* __restrict__ offs, int ntiles, int64_t n,
                              int64_t* __restrict__ ts)
@@ -173,14 +230,14 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kSortThreads), 0, s, c.scan_part, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kSortThreads), 0, s, c.hist, nk,
                        c.scan_part);
+    constexpr int TPD = D == 3 ? T * T * T : T * T;
     if (n > 0) {
+        // cell-sorted into the spare copy, then rank-interleaved back
         hipLaunchKernelGGL((k_scatter<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur, sp.alt,
                            n, sp.key, sp.rank, c.hist);
-        PartArrays t = sp.cur;
-        sp.cur = sp.alt;
-        sp.alt = t;
+        hipLaunchKernelGGL((k_interleave<R, TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, sp.alt, sp.cur,
+                           c.hist, nk, n);
     }
-    constexpr int TPD = D == 3 ? T * T * T : T * T;
     hipLaunchKernelGGL((k_tile_start<TPD>), dim3(nblk(c.k.ntiles + 1)), dim3(kSortThreads), 0, s,
                        c.hist, c.k.ntiles, n, sp.tile_start);
     sp.sorted = true;

@@ -126,8 +126,9 @@ class Sim:
     def count(self, species: int = 0) -> int:
         return int(self.lib.pic_particle_count(self.ctx, species))
 
-    def particles(self, species: int = 0):
-        """Return (x, w, weight, id) as host numpy arrays in id order."""
+    def particles(self, species: int = 0, raw: bool = False):
+        """Return (x, w, weight, id) as host numpy arrays in id order (in the
+        library's storage order when raw is true)."""
         n = self.count(species)
         x = torch.empty((3, n), dtype=torch.float64, device=self.device)
         w = torch.empty((3, n), dtype=torch.float64, device=self.device)
@@ -137,6 +138,8 @@ class Sim:
             self.ctx, species, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()),
             ctypes.c_void_p(wt.data_ptr()), ctypes.c_void_p(pid.data_ptr()), _stream()))
         torch.cuda.synchronize()
+        if raw:
+            return x.cpu().numpy(), w.cpu().numpy(), wt.cpu().numpy(), pid.cpu().numpy()
         order = torch.argsort(pid)
         return (x[:, order].cpu().numpy(), w[:, order].cpu().numpy(),
                 wt[order].cpu().numpy(), pid[order].cpu().numpy())

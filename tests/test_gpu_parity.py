@@ -275,3 +275,41 @@ def test_64cube_fullsize_sampled(precision):
     assert d["gauss_rel"] <= (1e-12 if precision == "fp64" else 1e-6), d
     assert d["nonfinite"] == 0
     assert abs(d["charge"]) < 1e-9 * e.n * e.weight[0]
+
+
+@pytest.mark.parametrize("dims", [3, 2])
+def test_sort_order_is_tile_major_rank_interleaved(dims):
+    """After a sort, storage order is: tiles in order; inside a tile, rank
+    levels in order and, within a level, cells in increasing order.  The ids
+    are a permutation of the loaded ones."""
+    if dims == 3:
+        wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=20, ny=16, nz=9, steps=0)
+        T = 8
+    else:
+        wl = picgen.WORKLOADS["2d3v_32x32_fp64"].scaled(nx=40, ny=20, ppc=6)
+        T = 16
+    e = picgen.electrons(wl)
+    sim = _sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=dims)
+    s = sim.add_species(e.q, e.m, e.n)
+    sim.load(s, e.x, e.w, e.weight)
+    sim.sort()
+    x, _, _, ids = sim.particles(0, raw=True)
+    assert np.array_equal(np.sort(ids), np.arange(e.n))
+    cell = np.floor(x).astype(np.int64)
+    nt = [(wl.nx + T - 1) // T, (wl.ny + T - 1) // T, (wl.nz + T - 1) // T if dims == 3 else 1]
+    tz = cell[2] // T if dims == 3 else np.zeros_like(cell[0])
+    tile = (tz * nt[1] + cell[1] // T) * nt[0] + cell[0] // T
+    assert np.all(np.diff(tile) >= 0)
+    lz = cell[2] % T if dims == 3 else np.zeros_like(cell[0])
+    local = (lz * T + cell[1] % T) * T + cell[0] % T
+    for t in np.unique(tile):
+        loc = local[tile == t]
+        # a new rank level starts exactly where the local cell index drops
+        level = np.concatenate([[0], np.cumsum(np.diff(loc) <= 0)])
+        for lv in np.unique(level):
+            cells = loc[level == lv]
+            assert np.all(np.diff(cells) > 0)
+        # level r holds one particle of every cell with more than r particles
+        counts = np.bincount(loc, minlength=T ** dims)
+        for lv in np.unique(level):
+            assert np.sum(level == lv) == np.sum(counts > lv)
