@@ -197,6 +197,26 @@ double pic_last_fallback_fraction(pic_ctx* ctx, void* stream);
 int pic_timing_start(pic_ctx* ctx, int max_steps);
 int pic_timing_stop(pic_ctx* ctx, double ms[4], int64_t* steps);
 
+/* Host-side state of a context: everything that is not in the caller's
+ * buffers.  A checkpoint is the field buffer, the grid workspace, every
+ * particle buffer (byte copies) and this struct; restoring copies the buffers
+ * into a context created with the same descriptions and then sets the
+ * struct.  Synchronizes nothing. */
+typedef struct pic_host_state {
+    int64_t step;          /* steps taken */
+    int32_t since_sort;    /* steps since the last sort */
+    int32_t r0_valid;      /* Gauss reference R^0 captured in the workspace */
+    int32_t nsp;           /* species registered */
+    int32_t reserved;
+    int64_t n[4];          /* particles per species */
+    int32_t sorted[4];     /* species sorted since its last load */
+} pic_host_state;
+
+int pic_get_host_state(const pic_ctx* ctx, pic_host_state* out);
+/* Fails with PIC_ESTATE unless the context has the same species count and each
+ * count fits its capacity. */
+int pic_set_host_state(pic_ctx* ctx, const pic_host_state* in);
+
 /* Destroy a context (does not free caller buffers). */
 void pic_destroy(pic_ctx* ctx);
 

@@ -21,7 +21,7 @@ EXPORTS = (
     "pic_query_sizes", "pic_init_grid", "pic_add_species", "pic_load_particles", "pic_step",
     "pic_deposit_J", "pic_field_solve", "pic_diagnostics", "pic_particle_count",
     "pic_get_particles", "pic_sort", "pic_last_fallback_fraction", "pic_timing_start",
-    "pic_timing_stop", "pic_destroy",
+    "pic_timing_stop", "pic_get_host_state", "pic_set_host_state", "pic_destroy",
     "pic_last_error", "pic_version",
 )
 
@@ -54,6 +54,12 @@ class Diag(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class HostState(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("since_sort", ctypes.c_int32),
+                ("r0_valid", ctypes.c_int32), ("nsp", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 4), ("sorted", ctypes.c_int32 * 4)]
 
 
 class PicError(RuntimeError):
@@ -91,6 +97,8 @@ def load(path: str = LIB_PATH):
         "pic_last_fallback_fraction": (D, [P, P]),
         "pic_timing_start": (I, [P, I]),
         "pic_timing_stop": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),
+        "pic_get_host_state": (I, [P, ctypes.POINTER(HostState)]),
+        "pic_set_host_state": (I, [P, ctypes.POINTER(HostState)]),
         "pic_destroy": (None, [P]),
         "pic_last_error": (ctypes.c_char_p, [P]),
         "pic_version": (ctypes.c_char_p, []),

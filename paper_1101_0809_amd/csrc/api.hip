@@ -510,6 +510,41 @@ int pic_timing_stop(pic_ctx* ctx, double ms[4], int64_t* steps)
     return PIC_OK;
 }
 
+int pic_get_host_state(const pic_ctx* ctx, pic_host_state* out)
+{
+    if (!ctx || !out) return fail(nullptr, PIC_EINVAL, "null argument");
+    const Ctx& c = ctx->c;
+    *out = pic_host_state{};
+    out->step = c.step;
+    out->since_sort = c.since_sort;
+    out->r0_valid = c.r0_valid ? 1 : 0;
+    out->nsp = c.nsp;
+    for (int i = 0; i < c.nsp; ++i) {
+        out->n[i] = c.sp[i].n;
+        out->sorted[i] = c.sp[i].sorted ? 1 : 0;
+    }
+    return PIC_OK;
+}
+
+int pic_set_host_state(pic_ctx* ctx, const pic_host_state* in)
+{
+    if (!ctx || !in) return fail(ctx ? &ctx->c : nullptr, PIC_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    if (in->nsp != c.nsp || in->step < 0 || in->since_sort < 0)
+        return fail(&c, PIC_ESTATE, "host state does not match this context");
+    for (int i = 0; i < c.nsp; ++i)
+        if (in->n[i] < 0 || (c.sp[i].d.mobile && in->n[i] > c.sp[i].d.capacity))
+            return fail(&c, PIC_ESTATE, "host state particle count exceeds a capacity");
+    c.step = in->step;
+    c.since_sort = in->since_sort;
+    c.r0_valid = in->r0_valid != 0;
+    for (int i = 0; i < c.nsp; ++i) {
+        c.sp[i].n = c.sp[i].d.mobile ? in->n[i] : 0;
+        c.sp[i].sorted = in->sorted[i] != 0;
+    }
+    return PIC_OK;
+}
+
 void pic_destroy(pic_ctx* ctx) { delete ctx; }
 
 }  // extern "C"

@@ -316,6 +316,13 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return r < 0 ? r + n : r;
 }
 
+// Periodic wrap of v in [-n, 2n): one compare-and-add instead of a modulo.
+__device__ __forceinline__ int wrap1(int v, int n)
+{
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+}
+
 __device__ __forceinline__ uint32_t pack_cell(int i, int j, int k)
 {
     return (uint32_t)i | ((uint32_t)j << 11) | ((uint32_t)k << 22);
@@ -486,6 +493,11 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
 
+    // every region index lies in [-n, 2n) unless an axis is shorter than the
+    // current region; then the general modulo is used
+    const bool small = nx < LJ || ny < LJ || (D == 3 && nz < LJ);
+    auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
+
     // 1. stage E^n, B^n (+ guard cells) into LDS
     for (int e = threadIdx.x; e < 6 * NF; e += NT) {
         const int comp = e / NF;
@@ -493,9 +505,9 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
         const int lx = r % LF;
         const int ly = (r / LF) % LF;
         const int lz = D == 3 ? r / (LF * LF) : 0;
-        const int gx = wrapi(T0[0] - 1 - M + lx, nx);
-        const int gy = wrapi(T0[1] - 1 - M + ly, ny);
-        const int gz = D == 3 ? wrapi(T0[2] - 1 - M + lz, nz) : 0;
+        const int gx = wr(T0[0] - 1 - M + lx, nx);
+        const int gy = wr(T0[1] - 1 - M + ly, ny);
+        const int gz = D == 3 ? wr(T0[2] - 1 - M + lz, nz) : 0;
         sf[e] = (R)fields[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
     }
     // 2. clear the LDS current tile
@@ -620,9 +632,9 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
         const int lx = r % LJ;
         const int ly = (r / LJ) % LJ;
         const int lz = D == 3 ? r / (LJ * LJ) : 0;
-        const int gx = wrapi(T0[0] - 2 - M + lx, nx);
-        const int gy = wrapi(T0[1] - 2 - M + ly, ny);
-        const int gz = D == 3 ? wrapi(T0[2] - 2 - M + lz, nz) : 0;
+        const int gx = wr(T0[0] - 2 - M + lx, nx);
+        const int gy = wr(T0[1] - 2 - M + ly, ny);
+        const int gz = D == 3 ? wr(T0[2] - 2 - M + lz, nz) : 0;
         global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
     }
     if (threadIdx.x == 0 && a.counters) {
@@ -793,6 +805,78 @@ __global__ __launch_bounds__(256) void k_rho(GridK g, PartArrays src, int64_t n,
     }
 }
 
+// Charge density of a cell-sorted species (Eq. rho), one workgroup per tile:
+// particles within M cells of their tile accumulate into an LDS density tile
+// (cells T0-1-M .. T0+T+M), the rest go straight to global memory; the tile
+// is then added to the global density with atomics.
+template <class R, int D, int T, int M, int NT>
+__global__ __launch_bounds__(NT) void k_rho_tiled(GridK g, PartArrays src, const int64_t* __restrict__ ts,
+                                                  double q, double* __restrict__ rho)
+{
+    constexpr int L = T + 2 + 2 * M;
+    constexpr int NL = D == 3 ? L * L * L : L * L;
+    __shared__ double sr[NL];
+    const int tile = xcd_tile(blockIdx.x, g.ntiles);
+    const int T0[3] = {(tile % g.nt[0]) * T, ((tile / g.nt[0]) % g.nt[1]) * T,
+                       D == 3 ? (tile / (g.nt[0] * g.nt[1])) * T : 0};
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    for (int e = threadIdx.x; e < NL; e += NT) sr[e] = 0.0;
+    __syncthreads();
+    const int64_t begin = ts[tile], end = ts[tile + 1];
+    for (int64_t p = begin + threadIdx.x; p < end; p += NT) {
+        int i[3] = {0, 0, 0};
+        double d[3] = {0, 0, 0};
+        if (sizeof(R) == 4) {
+            unpack_cell(src.cell[p], i);
+            for (int ax = 0; ax < D; ++ax) d[ax] = (double)((const float*)src.pos[ax])[p];
+        } else {
+            for (int ax = 0; ax < D; ++ax) {
+                const double x = ((const double*)src.pos[ax])[p];
+                const double fl = floor(x);
+                i[ax] = (int)fl;
+                d[ax] = x - fl;
+            }
+        }
+        double w3[3][3];
+        for (int ax = 0; ax < 3; ++ax) cell_weights<double>(ax < D ? d[ax] : 0.0, w3[ax]);
+        const double qv = q * (double)((const R*)src.weight)[p] * g.inv_vol;
+        int rel[3] = {0, 0, 0};
+        bool inside = true;
+        for (int ax = 0; ax < D; ++ax) {
+            int r = i[ax] - T0[ax];
+            const int n = g.n[ax];
+            if (r > n / 2) r -= n;
+            if (r < -(n / 2)) r += n;
+            rel[ax] = r;
+            inside = inside && r >= -M && r <= T - 1 + M;
+        }
+        for (int c = (D == 3 ? -1 : 0); c <= (D == 3 ? 1 : 0); ++c) {
+            const double wz = D == 3 ? w3[2][c + 1] : 1.0;
+            for (int b = -1; b <= 1; ++b)
+                for (int a2 = -1; a2 <= 1; ++a2) {
+                    const double v = qv * wz * w3[1][b + 1] * w3[0][a2 + 1];
+                    if (inside) {
+                        const int li = rel[0] + 1 + M + a2, lj = rel[1] + 1 + M + b;
+                        const int lk = D == 3 ? rel[2] + 1 + M + c : 0;
+                        atomicAdd(&sr[(lk * L + lj) * L + li], v);
+                    } else {
+                        const int64_t kz = D == 3 ? (int64_t)wrapi(i[2] + c, nz) * ny * nx : 0;
+                        global_add(&rho[kz + (int64_t)wrapi(i[1] + b, ny) * nx + wrapi(i[0] + a2, nx)], v);
+                    }
+                }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NL; e += NT) {
+        const double v = sr[e];
+        if (v == 0.0) continue;
+        const int lx = e % L, ly = (e / L) % L, lz = D == 3 ? e / (L * L) : 0;
+        const int gx = wrapi(T0[0] - 1 - M + lx, nx), gy = wrapi(T0[1] - 1 - M + ly, ny);
+        const int gz = D == 3 ? wrapi(T0[2] - 1 - M + lz, nz) : 0;
+        global_add(&rho[((int64_t)gz * ny + gy) * nx + gx], v);
+    }
+}
+
 // Charge density of FP64 position arrays [3][n] (immobile species at load).
 template <int D>
 __global__ __launch_bounds__(256) void k_rho_raw(GridK g, const double* __restrict__ x,
@@ -941,6 +1025,22 @@ hipError_t launch_get(const Ctx& c, const Species& sp, double* x, double* w, dou
 hipError_t launch_rho(const Ctx& c, const Species& sp, double* rho, hipStream_t s)
 {
     if (sp.n == 0) return hipSuccess;
+    if (sp.sorted) {  // tiles are valid: LDS accumulation per tile
+        const dim3 tg(c.k.ntiles);
+        const bool f64 = c.g.precision == PIC_FP64;
+        if (c.k.dims == 3) {
+            if (f64)
+                hipLaunchKernelGGL((k_rho_tiled<double, 3, kTile3, 2, 256>), tg, dim3(256), 0, s, c.k, sp.cur, sp.tile_start, sp.d.q, rho);
+            else
+                hipLaunchKernelGGL((k_rho_tiled<float, 3, kTile3, 2, 256>), tg, dim3(256), 0, s, c.k, sp.cur, sp.tile_start, sp.d.q, rho);
+        } else {
+            if (f64)
+                hipLaunchKernelGGL((k_rho_tiled<double, 2, kTile2, 2, 256>), tg, dim3(256), 0, s, c.k, sp.cur, sp.tile_start, sp.d.q, rho);
+            else
+                hipLaunchKernelGGL((k_rho_tiled<float, 2, kTile2, 2, 256>), tg, dim3(256), 0, s, c.k, sp.cur, sp.tile_start, sp.d.q, rho);
+        }
+        return hipGetLastError();
+    }
     const dim3 grid(blocks_for(sp.n));
     if (c.g.precision == PIC_FP64) {
         if (c.k.dims == 3)

@@ -186,6 +186,48 @@ class Sim:
     def fallback_fraction(self) -> float:
         return float(self.lib.pic_last_fallback_fraction(self.ctx, _stream()))
 
+    # -- checkpoint ------------------------------------------------------
+    def state_dict(self) -> dict:
+        """Everything needed to continue the run: byte copies of the caller
+        buffers (fields, workspace, particle buffers) and the host state."""
+        hs = L.HostState()
+        self._check(self.lib.pic_get_host_state(self.ctx, ctypes.byref(hs)))
+        torch.cuda.synchronize()
+        return {
+            "desc": {name: (list(getattr(self.desc, name)) if name == "bext"
+                            else getattr(self.desc, name)) for name, _ in L.GridDesc._fields_},
+            "fields": self.fields_t.clone(),
+            "workspace": self.workspace.clone(),
+            "species": [{"q": s.q, "m": s.m, "mobile": s.mobile, "capacity": s.capacity,
+                         "buffer": None if s.buffer is None else s.buffer.clone()}
+                        for s in self.species],
+            "host": {"step": hs.step, "since_sort": hs.since_sort, "r0_valid": hs.r0_valid,
+                     "nsp": hs.nsp, "n": list(hs.n), "sorted": list(hs.sorted)},
+        }
+
+    @classmethod
+    def from_state_dict(cls, st: dict, device: str = "cuda:0") -> "Sim":
+        d = st["desc"]
+        prec = {L.PIC_FP64: "fp64", L.PIC_FP32C: "fp32c"}[d["precision"]]
+        sim = cls(d["nx"], d["ny"], d["nz"], d["dt"], dims=d["dims"], precision=prec,
+                  dx=d["dx"], dy=d["dy"], dz=d["dz"], c=d["c"], sort_every=d["sort_every"],
+                  bext=tuple(d["bext"]), device=device)
+        for sp in st["species"]:
+            sim.add_species(sp["q"], sp["m"], sp["capacity"], mobile=sp["mobile"])
+        sim.fields_t.copy_(st["fields"])
+        sim.workspace.copy_(st["workspace"])
+        for mine, sp in zip(sim.species, st["species"]):
+            if sp["buffer"] is not None:
+                mine.buffer.copy_(sp["buffer"])
+        h = st["host"]
+        hs = L.HostState()
+        hs.step, hs.since_sort, hs.r0_valid, hs.nsp = h["step"], h["since_sort"], h["r0_valid"], h["nsp"]
+        for i in range(4):
+            hs.n[i], hs.sorted[i] = h["n"][i], h["sorted"][i]
+        torch.cuda.synchronize()
+        sim._check(sim.lib.pic_set_host_state(sim.ctx, ctypes.byref(hs)))
+        return sim
+
     # -- fields ----------------------------------------------------------
     @property
     def fields(self) -> torch.Tensor:

@@ -160,3 +160,45 @@ def random_moves(n: int, seed: int, box=(16, 16, 16), max_step=0.9):
     x0 = np.stack([rng.uniform(0, box[a], n) for a in range(3)])
     dx = rng.uniform(-max_step, max_step, (3, n))
     return x0, x0 + dx
+
+
+def device_chunks(wl: Workload, device, chunk: int = 1 << 26, ions: bool = False):
+    """Yield (x, w, weight) torch float64 tensors on ``device`` covering the
+    whole species in chunks of ``chunk`` particles, drawn with
+    ``torch.Generator(device)`` seeded by (workload seed, chunk index) -- for
+    workloads too large to draw on the host.  Same distributions as
+    ``electrons`` / ``ions_like``; ions (``ions=True``) are co-located with the
+    electrons of the same chunk (same position draws)."""
+    import torch
+
+    n = wl.n_electrons
+    lo_x, hi_x = (0.0, float(wl.nx)) if wl.slab is None else (float(wl.slab[0]), float(wl.slab[1]))
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        gen = torch.Generator(device=device)
+        gen.manual_seed(wl.seed * 1000003 + c0 // chunk)
+        u = torch.rand((3, m), generator=gen, dtype=torch.float64, device=device)
+        x = torch.empty((3, m), dtype=torch.float64, device=device)
+        x[0] = lo_x + (hi_x - lo_x) * u[0]
+        x[1] = float(wl.ny) * u[1]
+        x[2] = float(wl.nz) * u[2]
+        del u
+        tops = torch.tensor([hi_x, float(wl.ny), float(wl.nz)], dtype=torch.float64,
+                            device=device)[:, None]
+        x = torch.where(x >= tops, torch.zeros_like(x), x)
+        if ions:
+            gi = torch.Generator(device=device)
+            gi.manual_seed(wl.seed * 1000003 + 7919 + c0 // chunk)
+            if wl.ions_mobile:
+                w = wl.ion_w_th * torch.randn((3, m), generator=gi, dtype=torch.float64,
+                                              device=device)
+            else:
+                w = torch.zeros((3, m), dtype=torch.float64, device=device)
+        else:
+            w = torch.randn((3, m), generator=gen, dtype=torch.float64, device=device)
+            for a in range(3):
+                w[a] *= wl.w_th[a]
+            if wl.drift:
+                w[0, : m // 2] += wl.drift
+                w[0, m // 2:] -= wl.drift
+        yield x, w, torch.full((m,), wl.weight, dtype=torch.float64, device=device)
