@@ -36,11 +36,17 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+AUX = 8192  # auxiliary line length of the plane-wave source (ORC_AUX)
+
+
 class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("dt", ctypes.c_double), ("c", ctypes.c_double),
-                ("bext", ctypes.c_double * 3)]
+                ("bext", ctypes.c_double * 3),
+                ("src_kind", ctypes.c_int64), ("src_plane", ctypes.c_int64),
+                ("src_amp", ctypes.c_double), ("src_omega", ctypes.c_double),
+                ("src_ramp", ctypes.c_double)]
 
 
 class _Species(ctypes.Structure):
@@ -71,6 +77,7 @@ def lib():
             "orc_update_e": (None, [g, p]),
             "orc_particle_step": (None, [g, p, s, p]),
             "orc_step": (None, [g, p, ctypes.c_int, s, ctypes.c_int]),
+            "orc_step_src": (None, [g, p, ctypes.c_int, s, ctypes.c_int, p, ctypes.c_int64]),
             "orc_gauss_residual": (None, [g, p, p, p]),
             "orc_div_b": (None, [g, p, p]),
             "orc_energies": (None, [g, p, ctypes.c_int, s, p]),
@@ -102,6 +109,7 @@ class Grid:
     dz: float = 1.0
     c: float = 1.0
     bext: tuple = (0.0, 0.0, 0.0)
+    source: tuple = None   # (plane, amplitude, omega, ramp time): +x plane wave, E^y
 
     @property
     def shape(self):
@@ -117,6 +125,10 @@ class Grid:
         g.dx, g.dy, g.dz, g.dt, g.c = self.dx, self.dy, self.dz, self.dt, self.c
         for a in range(3):
             g.bext[a] = float(self.bext[a])
+        if self.source is not None:
+            g.src_kind = 1
+            g.src_plane, g.src_amp, g.src_omega, g.src_ramp = (int(self.source[0]),
+                                                               *map(float, self.source[1:]))
         return g
 
 
@@ -162,10 +174,13 @@ class State:
     species: list = field(default_factory=list)
     fields: np.ndarray = None
 
+    step_index: int = 0
+
     def __post_init__(self):
         if self.fields is None:
             self.fields = np.zeros((9,) + self.grid.shape)
         self.fields = _f64(self.fields).copy()
+        self.aux = np.zeros(2 * AUX)   # source line: E^y then B^z
 
     @property
     def E(self):
@@ -180,8 +195,10 @@ class State:
         return self.fields[6:9]
 
     def step(self, nsteps: int = 1):
-        lib().orc_step(ctypes.byref(self.grid._c()), _ptr(self.fields),
-                       len(self.species), _species_array(self.species), nsteps)
+        lib().orc_step_src(ctypes.byref(self.grid._c()), _ptr(self.fields),
+                           len(self.species), _species_array(self.species), nsteps,
+                           _ptr(self.aux), self.step_index)
+        self.step_index += nsteps
 
     def rho(self, species=None):
         sp = self.species if species is None else species

@@ -353,6 +353,60 @@ void orc_update_e(const orc_grid* g, double* fields)
 }
 
 /* ---------------------------------------------------------------------------
+ * Plane-wave source (not part of the paper's method: the laser of the slab
+ * workload).  The incident wave lives on an auxiliary 1D line with the same
+ * staggered operators as the grid restricted to x (E^y at faces, B^z at
+ * nodes), so a plane wave uniform in y and z evolves identically on both and
+ * the correction terms below inject it without leakage into x < plane.
+ * Aux index a sits at grid index src_plane - 2 + a.
+ * ------------------------------------------------------------------------- */
+static double src_wave(const orc_grid* g, double t)
+{
+    double ramp = 1.0;
+    if (t < g->src_ramp) {
+        double s = sin(0.5 * PI * t / g->src_ramp);
+        ramp = s * s;
+    }
+    return g->src_amp * ramp * sin(g->src_omega * t);
+}
+
+static void aux_half_b(const orc_grid* g, double* aux)
+{
+    double *ey = aux, *bz = aux + ORC_AUX;
+    const double hc = 0.5 * g->c * g->dt / g->dx;
+    for (int a = 1; a < ORC_AUX; ++a) bz[a] = bz[a] - hc * (ey[a] - ey[a - 1]);
+}
+
+static void aux_update_e(const orc_grid* g, double* aux, double t_new)
+{
+    double *ey = aux, *bz = aux + ORC_AUX;
+    const double cx = g->c * g->dt / g->dx;
+    for (int a = 1; a < ORC_AUX - 1; ++a) ey[a] = ey[a] - cx * (bz[a + 1] - bz[a]);
+    ey[0] = src_wave(g, t_new);
+}
+
+/* grid corrections at the plane: B^z at node i0 sees the incident E^y at
+ * face i0 + 1/2 removed; E^y at face i0 + 1/2 sees the incident B^z at node
+ * i0 added. */
+static void src_fix_b(const orc_grid* g, double* fields, const double* aux)
+{
+    const size_t nc = ncell(g);
+    double* Bz = fields + 5 * nc;
+    const double v = 0.5 * (g->c * g->dt / g->dx) * aux[2];
+    for (long k = 0; k < g->nz; ++k)
+        for (long j = 0; j < g->ny; ++j) Bz[idx(g, g->src_plane, j, k)] += v;
+}
+
+static void src_fix_e(const orc_grid* g, double* fields, const double* aux)
+{
+    const size_t nc = ncell(g);
+    double* Ey = fields + nc;
+    const double v = (g->c * g->dt / g->dx) * aux[ORC_AUX + 2];
+    for (long k = 0; k < g->nz; ++k)
+        for (long j = 0; j < g->ny; ++j) Ey[idx(g, g->src_plane, j, k)] += v;
+}
+
+/* ---------------------------------------------------------------------------
  * One full time step in the Appendix order: B half step; for every particle,
  * in index order, form factors at x^n, gather, push, new position, current;
  * second B half step; E update.  J is cleared before the particle loop, so
@@ -390,18 +444,37 @@ void orc_particle_step(const orc_grid* g, const double* fields, const orc_specie
     }
 }
 
-void orc_step(const orc_grid* g, double* fields, int nsp, const orc_species* sp, int nsteps)
+void orc_step_src(const orc_grid* g, double* fields, int nsp, const orc_species* sp, int nsteps,
+                  double* aux, int64_t step0)
 {
     const size_t nc = ncell(g);
     double* J = fields + 6 * nc;
+    const int src = g->src_kind == 1 && aux != NULL;
     for (int it = 0; it < nsteps; ++it) {
         orc_half_b(g, fields);
+        if (src) {
+            src_fix_b(g, fields, aux);
+            aux_half_b(g, aux);
+        }
         memset(J, 0, 3 * nc * sizeof(double));
         for (int s = 0; s < nsp; ++s)
             if (sp[s].mobile) orc_particle_step(g, fields, &sp[s], J);
         orc_half_b(g, fields);
+        if (src) {
+            src_fix_b(g, fields, aux);
+            aux_half_b(g, aux);
+        }
         orc_update_e(g, fields);
+        if (src) {
+            src_fix_e(g, fields, aux);
+            aux_update_e(g, aux, (double)(step0 + it + 1) * g->dt);
+        }
     }
+}
+
+void orc_step(const orc_grid* g, double* fields, int nsp, const orc_species* sp, int nsteps)
+{
+    orc_step_src(g, fields, nsp, sp, nsteps, NULL, 0);
 }
 
 /* ---------------------------------------------------------------------------

@@ -15,7 +15,16 @@ typedef struct orc_grid {
     double dt;           /* time step */
     double c;            /* speed of light */
     double bext[3];      /* uniform external B added at the gather */
+    /* plane-wave source (kind 1): E^y wave travelling along +x, injected at
+     * the total-field / scattered-field plane between node src_plane and face
+     * src_plane + 1/2; incident values from an auxiliary 1D line of ORC_AUX
+     * cells whose first E^y point (x = src_plane - 2 + 1/2) is driven as
+     * E0 ramp(t) sin(omega t), ramp = sin^2(pi t / (2 src_ramp)) until src_ramp */
+    int64_t src_kind, src_plane;
+    double src_amp, src_omega, src_ramp;
 } orc_grid;
+
+#define ORC_AUX 8192  /* auxiliary line length: E^y[ORC_AUX] then B^z[ORC_AUX] */
 
 typedef struct orc_species {
     int64_t n;             /* particle count */
@@ -46,6 +55,10 @@ void orc_update_e(const orc_grid* g, double* fields);
 void orc_particle_step(const orc_grid* g, const double* fields, const orc_species* s,
                        double* J);
 void orc_step(const orc_grid* g, double* fields, int nsp, const orc_species* sp, int nsteps);
+/* same, with the source's auxiliary line state aux[2 * ORC_AUX] and the step
+ * index of the first step (the source time is counted from step 0) */
+void orc_step_src(const orc_grid* g, double* fields, int nsp, const orc_species* sp, int nsteps,
+                  double* aux, int64_t step0);
 void orc_gauss_residual(const orc_grid* g, const double* fields, const double* rho, double* R);
 void orc_div_b(const orc_grid* g, const double* fields, double* D);
 void orc_energies(const orc_grid* g, const double* fields, int nsp, const orc_species* sp,

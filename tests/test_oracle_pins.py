@@ -475,3 +475,45 @@ def test_lone_particle_with_ion_stays_at_rest():
                           oracle.Species(x, np.zeros((3, 1)), np.ones(1), q=1.0, mobile=False)])
     st.step(10)
     assert np.all(st.species[0].x == x) and np.all(st.fields == 0.0)
+
+
+# --------------------------------------------------------------------------
+# plane-wave source of the slab workload (total-field / scattered-field)
+# --------------------------------------------------------------------------
+
+def test_plane_wave_source_is_one_sided_and_exact():
+    """The injected wave exists only in x > plane and there equals the
+    auxiliary line's wave at every (y, z): no leakage into the scattered
+    region, no transverse structure (until the wave wraps round the box)."""
+    n, plane, dt = 128, 8, 0.45   # long box: the precursor must not wrap round
+    omega = 2 * math.pi / 20
+    g = oracle.Grid(n, 3, 4, dt, source=(plane, omega, omega, 2 * math.pi / omega))
+    st = oracle.State(g, [])
+    for _ in range(70):   # front travels 0.45 cells/step: no wrap within 70 steps
+        st.step(1)
+        Ey, Bz = st.fields[1], st.fields[5]
+        # round-off leakage only (the grid and line values agree to the last bits)
+        assert np.max(np.abs(Ey[:, :, :plane])) < 1e-13 * omega      # faces x = i + 1/2 < plane
+        assert np.max(np.abs(Bz[:, :, :plane + 1])) < 1e-13 * omega  # nodes x = i <= plane
+        aux_ey = st.aux[:oracle.AUX]
+        a = np.arange(plane, n) - (plane - 2)
+        assert np.max(np.abs(Ey[:, :, plane:] - aux_ey[a][None, None, :])) < 1e-13 * omega
+        for c in (0, 2, 3, 4):
+            assert np.max(np.abs(st.fields[c])) == 0.0
+    assert np.max(np.abs(st.fields[1])) > 0.5 * omega   # the wave is there (ramp done)
+
+
+def test_plane_wave_source_keeps_gauss_and_divb():
+    wl = picgen.Workload("src", 24, 6, 6, 3, 0.45, 2, (0.05,) * 3, 0.3, 30)
+    e = picgen.electrons(wl)
+    ion = picgen.ions_like(wl, e)
+    omega = 2 * math.pi / 10
+    g = oracle.Grid(24, 6, 6, wl.dt, source=(4, omega, omega, 10.0))
+    st = oracle.State(g, [oracle.Species(e.x, e.w, e.weight),
+                          oracle.Species(ion.x, ion.w, ion.weight, q=1.0, m=100.0, mobile=False)])
+    R0 = st.gauss_residual()
+    rho_e = np.max(np.abs(4 * np.pi * st.rho(st.species[:1])))
+    st.step(30)
+    assert np.max(np.abs(st.gauss_residual() - R0)) / rho_e < 1e-12
+    assert np.max(np.abs(st.div_b())) < 1e-14
+    assert np.max(np.abs(st.fields[1])) > 0.1 * omega
