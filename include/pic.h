@@ -82,7 +82,20 @@ typedef struct pic_grid_desc {
     double c;            /* speed of light */
     double bext[3];      /* uniform external B, added to the gathered B; it is not
                             stored in the field buffer and not in field energies */
+    /* Plane-wave source (not part of the paper's method; the laser of the slab
+     * workload).  src_kind 0: none.  src_kind 1: an E^y plane wave travelling
+     * along +x, injected at the total-field / scattered-field plane between the
+     * node x = src_plane and the face x = src_plane + 1/2 (2 <= src_plane <= nx-2).
+     * The incident wave is carried by an auxiliary 1D line of PIC_AUX cells with
+     * the grid's own staggered operators along x; its E^y point at
+     * x = src_plane - 2 + 1/2 is driven as src_amp * ramp(t) * sin(src_omega t),
+     * ramp = sin^2(pi t / (2 src_ramp)) for t < src_ramp and 1 after, t = n dt. */
+    int32_t src_kind;
+    int32_t src_plane;
+    double src_amp, src_omega, src_ramp;
 } pic_grid_desc;
+
+#define PIC_AUX 8192
 
 /* Particle species (copied by pic_add_species). */
 typedef struct pic_species_desc {

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 PIC_OK, PIC_EINVAL, PIC_ERANGE, PIC_ECFL, PIC_EDEVICE, PIC_ESTATE, PIC_ESIZE = 0, -1, -2, -3, -4, -5, -6
 PIC_FP64, PIC_FP32C = 0, 1
 PIC_B_HALF, PIC_E_FULL = 1, 2
+PIC_AUX = 8192  # source line length (include/pic.h)
 
 # Every symbol include/pic.h declares (checked by the CPU tests).
 EXPORTS = (
@@ -31,7 +32,10 @@ class GridDesc(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("precision", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("sort_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
-                ("dt", ctypes.c_double), ("c", ctypes.c_double), ("bext", ctypes.c_double * 3)]
+                ("dt", ctypes.c_double), ("c", ctypes.c_double), ("bext", ctypes.c_double * 3),
+                ("src_kind", ctypes.c_int32), ("src_plane", ctypes.c_int32),
+                ("src_amp", ctypes.c_double), ("src_omega", ctypes.c_double),
+                ("src_ramp", ctypes.c_double)]
 
 
 class SpeciesDesc(ctypes.Structure):

@@ -117,6 +117,21 @@ int make_grid(const pic_grid_desc* g, GridK* k, std::string* msg)
     k->inv_vol = 1.0 / V;
     for (int a = 0; a < 3; ++a) k->jscale[a] = -0.25 * h[a] / g->dt / V;
     k->fourpidt = 4.0 * kPi * g->dt;
+    if (g->src_kind != 0 && g->src_kind != 1) {
+        *msg = "src_kind must be 0 or 1";
+        return PIC_EINVAL;
+    }
+    if (g->src_kind == 1 && (g->src_plane < 2 || g->src_plane > g->nx - 2 || !(g->src_ramp >= 0.0)
+                             || !isfinite(g->src_amp) || !isfinite(g->src_omega))) {
+        *msg = "plane-wave source needs 2 <= src_plane <= nx - 2, finite amplitude and omega, ramp >= 0";
+        return PIC_EINVAL;
+    }
+    k->src_kind = g->src_kind;
+    k->src_plane = g->src_plane;
+    k->src_amp = g->src_amp;
+    k->src_omega = g->src_omega;
+    k->src_ramp = g->src_ramp;
+    k->aux = nullptr;
     return PIC_OK;
 }
 
@@ -128,6 +143,7 @@ size_t workspace_bytes(const GridK& k, uint32_t nkeys)
     b += align_up(((size_t)nkeys / 1024 + 2) * 4, kAlign);               // scan partials
     b += align_up(diag_partials_doubles(kMaxSpecies) * 8, kAlign);       // reductions
     b += align_up(8 * sizeof(unsigned long long), kAlign);               // counters
+    b += align_up(2 * (size_t)PIC_AUX * 8, kAlign);                      // source line
     return b;
 }
 
@@ -272,7 +288,9 @@ int pic_init_grid(const pic_grid_desc* g, void* fields, size_t field_bytes, void
     c.scan_part = (uint32_t*)take(((size_t)nkeys / 1024 + 2) * 4);
     c.red = (double*)take(diag_partials_doubles(kMaxSpecies) * 8);
     c.counters = (unsigned long long*)take(8 * sizeof(unsigned long long));
+    c.k.aux = (double*)take(2 * (size_t)PIC_AUX * 8);
     hipError_t e = hipMemset(c.rho_bg, 0, (size_t)k.ncell * 8);
+    if (e == hipSuccess) e = hipMemset(c.k.aux, 0, 2 * (size_t)PIC_AUX * 8);
     if (e == hipSuccess) e = hipMemset(c.counters, 0, 8 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -370,7 +388,7 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
             if (c.sp[i].d.mobile) e = launch_particle_step(c, c.sp[i], s);
         mark(2);
         if (e == hipSuccess) e = launch_field_half_b(c, s);
-        if (e == hipSuccess) e = launch_field_update_e(c, s);
+        if (e == hipSuccess) e = launch_field_update_e(c, s, c.step);
         mark(3);
         if (e != hipSuccess) return hip_fail(&c, e, "step");
         ++c.step;
@@ -410,7 +428,7 @@ int pic_field_solve(pic_ctx* ctx, int what, void* stream)
         e = launch_field_half_b(c, s);
     } else if (what == PIC_E_FULL) {
         e = launch_field_half_b(c, s);
-        if (e == hipSuccess) e = launch_field_update_e(c, s);
+        if (e == hipSuccess) e = launch_field_update_e(c, s, c.step);
     } else {
         return fail(&c, PIC_EINVAL, "what must be PIC_B_HALF or PIC_E_FULL");
     }

@@ -53,8 +53,41 @@ __global__ __launch_bounds__(kFieldThreads) void k_half_b(GridK g, double* __res
     const double hx = g.half_cfl[0], hy = g.half_cfl[1], hz = g.half_cfl[2];
     Bx[p] = Bx[p] - hy * (ez - Ez[jm]) + hz * (ey - Ey[km]);
     By[p] = By[p] - hz * (ex - Ex[km]) + hx * (ez - Ez[im]);
-    Bz[p] = Bz[p] - hx * (ey - Ey[im]) + hy * (ex - Ex[jm]);
+    double bz = Bz[p] - hx * (ey - Ey[im]) + hy * (ex - Ex[jm]);
+    if (g.src_kind == 1 && c.i == g.src_plane)  // B^z at the plane is scattered-field:
+        bz += hx * g.aux[2];                   // remove the incident E^y of face plane+1/2
+    Bz[p] = bz;
 }
+
+// The source's auxiliary line, advanced by a one-workgroup kernel after each
+// grid kernel: the grid's B correction uses the line's E^y of time n, its E
+// correction the line's B^z of time n + 1/2, the values before each advance.
+__device__ void aux_half_b(const GridK& g)
+{
+    double* ey = g.aux;
+    double* bz = g.aux + PIC_AUX;
+    const double hx = g.half_cfl[0];
+    for (int a = 1 + threadIdx.x; a < PIC_AUX; a += kFieldThreads) bz[a] = bz[a] - hx * (ey[a] - ey[a - 1]);
+}
+
+__device__ void aux_update_e(const GridK& g, double t)
+{
+    double* ey = g.aux;
+    const double* bz = g.aux + PIC_AUX;
+    const double cx = g.cfl[0];
+    for (int a = 1 + threadIdx.x; a < PIC_AUX - 1; a += kFieldThreads) ey[a] = ey[a] - cx * (bz[a + 1] - bz[a]);
+    if (threadIdx.x == 0) {
+        double ramp = 1.0;
+        if (t < g.src_ramp) {
+            const double s = sin(0.5 * kPi * t / g.src_ramp);
+            ramp = s * s;
+        }
+        ey[0] = g.src_amp * ramp * sin(g.src_omega * t);
+    }
+}
+
+__global__ __launch_bounds__(kFieldThreads) void k_aux_half_b(GridK g) { aux_half_b(g); }
+__global__ __launch_bounds__(kFieldThreads) void k_aux_update_e(GridK g, double t) { aux_update_e(g, t); }
 
 // E <- E - 4 pi dt J + curl_h B ; J <- 0
 __global__ __launch_bounds__(kFieldThreads) void k_update_e(GridK g, double* __restrict__ f)
@@ -79,7 +112,10 @@ __global__ __launch_bounds__(kFieldThreads) void k_update_e(GridK g, double* __r
     const double bx = Bx[p], by = By[p], bz = Bz[p];
     const double cx = g.cfl[0], cy = g.cfl[1], cz = g.cfl[2];
     Ex[p] = Ex[p] - g.fourpidt * Jx[p] + cy * (Bz[jp] - bz) - cz * (By[kp] - by);
-    Ey[p] = Ey[p] - g.fourpidt * Jy[p] + cz * (Bx[kp] - bx) - cx * (Bz[ip] - bz);
+    double ey = Ey[p] - g.fourpidt * Jy[p] + cz * (Bx[kp] - bx) - cx * (Bz[ip] - bz);
+    if (g.src_kind == 1 && c.i == g.src_plane)  // E^y at face plane+1/2 is total-field:
+        ey += cx * g.aux[PIC_AUX + 2];         // add the incident B^z of node plane
+    Ey[p] = ey;
     Ez[p] = Ez[p] - g.fourpidt * Jz[p] + cx * (By[ip] - by) - cy * (Bx[jp] - bx);
     Jx[p] = 0.0;
     Jy[p] = 0.0;
@@ -92,13 +128,18 @@ hipError_t launch_field_half_b(const Ctx& c, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
     hipLaunchKernelGGL(k_half_b, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields);
+    if (c.k.src_kind == 1)  // after the grid kernel, which reads the line's E^y only
+        hipLaunchKernelGGL(k_aux_half_b, dim3(1), dim3(kFieldThreads), 0, s, c.k);
     return hipGetLastError();
 }
 
-hipError_t launch_field_update_e(const Ctx& c, hipStream_t s)
+hipError_t launch_field_update_e(const Ctx& c, hipStream_t s, int64_t step)
 {
     const unsigned blocks = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
     hipLaunchKernelGGL(k_update_e, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields);
+    if (c.k.src_kind == 1)  // the line's E^y at t = (step + 1) dt
+        hipLaunchKernelGGL(k_aux_update_e, dim3(1), dim3(kFieldThreads), 0, s, c.k,
+                           (double)(step + 1) * c.k.dt);
     return hipGetLastError();
 }
 

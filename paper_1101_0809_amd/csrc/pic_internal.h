@@ -58,6 +58,11 @@ struct GridK {
     double jscale[3];  // -(1/4) d_a / dt / V : xi -> J factor per unit charge
     double fourpidt;   // 4 pi dt
     double inv_h[3];   // 1 / d_a
+    // plane-wave source (see pic_grid_desc): kind, plane, amplitude, omega, ramp
+    int src_kind;
+    int src_plane;
+    double src_amp, src_omega, src_ramp;
+    double* aux;       // auxiliary line: E^y[PIC_AUX] then B^z[PIC_AUX] (workspace)
 };
 
 struct Ctx {
@@ -88,7 +93,7 @@ size_t align_up(size_t v, size_t a);
 
 // ---- launchers (stream = hipStream_t) ----
 hipError_t launch_field_half_b(const Ctx& c, hipStream_t s);
-hipError_t launch_field_update_e(const Ctx& c, hipStream_t s);
+hipError_t launch_field_update_e(const Ctx& c, hipStream_t s, int64_t step);
 hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_load(Ctx& c, Species& sp, int64_t n, const double* x, const double* w,
                        const double* weight, hipStream_t s);

@@ -20,6 +20,10 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _align(n: int, a: int = 256) -> int:
+    return (n + a - 1) // a * a
+
+
 def _dev_f64(a, device) -> torch.Tensor:
     t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64))
     return t.to(device=device, dtype=torch.float64).contiguous()
@@ -45,7 +49,9 @@ class Sim:
     def __init__(self, nx: int, ny: int, nz: int, dt: float, dims: int = 3,
                  precision: str = "fp64", dx: float = 1.0, dy: float = 1.0, dz: float = 1.0,
                  c: float = 1.0, sort_every: int = 0, bext=(0.0, 0.0, 0.0),
-                 device: str = "cuda:0", fields: np.ndarray = None):
+                 device: str = "cuda:0", fields: np.ndarray = None, source=None):
+        """source: None or (plane, amplitude, omega, ramp time) for the +x
+        E^y plane-wave source of include/pic.h."""
         if not torch.cuda.is_available():
             raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
         self.lib = L.load()
@@ -58,6 +64,9 @@ class Sim:
         d.dx, d.dy, d.dz, d.dt, d.c = dx, dy, dz, dt, c
         for a in range(3):
             d.bext[a] = float(bext[a])
+        if source is not None:
+            d.src_kind, d.src_plane = 1, int(source[0])
+            d.src_amp, d.src_omega, d.src_ramp = (float(v) for v in source[1:])
         self.desc = d
         self.precision = precision
         self.shape = (nz, ny, nx)
@@ -209,9 +218,11 @@ class Sim:
     def from_state_dict(cls, st: dict, device: str = "cuda:0") -> "Sim":
         d = st["desc"]
         prec = {L.PIC_FP64: "fp64", L.PIC_FP32C: "fp32c"}[d["precision"]]
+        src = ((d["src_plane"], d["src_amp"], d["src_omega"], d["src_ramp"])
+               if d["src_kind"] == 1 else None)
         sim = cls(d["nx"], d["ny"], d["nz"], d["dt"], dims=d["dims"], precision=prec,
                   dx=d["dx"], dy=d["dy"], dz=d["dz"], c=d["c"], sort_every=d["sort_every"],
-                  bext=tuple(d["bext"]), device=device)
+                  bext=tuple(d["bext"]), device=device, source=src)
         for sp in st["species"]:
             sim.add_species(sp["q"], sp["m"], sp["capacity"], mobile=sp["mobile"])
         sim.fields_t.copy_(st["fields"])
@@ -229,6 +240,15 @@ class Sim:
         return sim
 
     # -- fields ----------------------------------------------------------
+    def aux_line(self) -> np.ndarray:
+        """The source's auxiliary line (E^y then B^z, PIC_AUX each) from the workspace."""
+        torch.cuda.synchronize()
+        sz = L.Sizes()
+        L.check(self.lib.pic_query_sizes(ctypes.byref(self.desc), 0, ctypes.byref(sz)))
+        nbytes = 2 * L.PIC_AUX * 8
+        raw = self.workspace[sz.workspace_bytes - _align(nbytes):][:nbytes]
+        return raw.view(torch.float64).cpu().numpy()
+
     @property
     def fields(self) -> torch.Tensor:
         """(9, nz, ny, nx) view: Ex Ey Ez Bx By Bz Jx Jy Jz."""

@@ -432,3 +432,84 @@ def test_checkpoint_restore_continue(precision, tmp_path):
         assert _rel(f[c], ref_f[c]) < tol
     assert np.max(np.abs(w - ref_w)) < tol * np.max(np.abs(ref_w))
     assert np.max(np.abs(_wrapdiff(x, ref_x, 16))) < tol * 16
+
+
+# ---------------------------------------------------------------------------
+# plane-wave source (the laser of the 128^3 slab workload)
+# ---------------------------------------------------------------------------
+
+def _slab_oracle_state(wl, source, e=None):
+    e = picgen.electrons(wl) if e is None else e
+    ion = picgen.ions_like(wl, e)
+    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, source=source),
+                      [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m),
+                       oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=False)])
+    return st, e, ion
+
+
+def test_plane_wave_source_vacuum_matches_oracle():
+    omega = 2 * math.pi / 20
+    src = (8, omega, omega, 20.0)
+    sim = _sim(nx=64, ny=8, nz=8, dt=0.45, dims=3, source=src)
+    st = oracle.State(oracle.Grid(64, 8, 8, 0.45, source=src), [])
+    sim.step(60)
+    st.step(60)
+    F = sim.fields_numpy()
+    for c in range(6):
+        assert np.max(np.abs(F[c] - st.fields[c])) <= 1e-13 * omega, c
+    aux = sim.aux_line()
+    assert np.max(np.abs(aux - st.aux)) <= 1e-13 * omega
+    assert np.max(np.abs(F[1])) > 0.5 * omega
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_slab_with_laser_parity(precision):
+    """The slab workload at reduced size (48 x 16 x 16 cells, electrons at 8 per
+    cell in x in [12, 36), cold, immobile ions) with the laser plane at x = 4:
+    40 steps against the oracle."""
+    wl = picgen.WORKLOADS["3d_128cube_slab"].scaled(nx=48, ny=16, nz=16, ppc=8, slab=(12, 36),
+                                                   steps=40, sort_every=10)
+    omega = 2 * math.pi / 20
+    src = (4, omega, omega, 20.0)
+    st, e, ion = _slab_oracle_state(wl, src)
+    sim = _sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=3, precision=precision,
+               sort_every=wl.sort_every, source=src)
+    s = sim.add_species(e.q, e.m, e.n)
+    sim.load(s, e.x, e.w, e.weight)
+    si = sim.add_species(ion.q, ion.m, 0, mobile=False)
+    sim.load(si, ion.x, ion.w, ion.weight)
+    sim.step(wl.steps)
+    st.step(wl.steps)
+    if precision == "fp64":
+        _compare(sim, st, wl, 1e-12, 1e-12, 1e-12)
+    else:
+        _compare(sim, st, wl, 1e-4, 1e-5, 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_128cube_slab_laser_fullsize_sampled(precision):
+    """The full 128^3 slab workload: 16 electrons per slab cell in x in [32, 96)
+    (16,777,216 electrons), w_th = 0.01 c, a0 = 1 laser of 20-cell wavelength
+    from the plane x = 8 with a one-period sin^2 ramp.  After 60 steps the
+    wave has entered the plasma; one more step is checked on a sample against
+    the oracle, and the Gauss drift over the grid."""
+    wl = picgen.WORKLOADS["3d_128cube_slab"]
+    omega = 2 * math.pi / 20
+    src = (8, omega, omega, 20.0)
+    e = picgen.electrons(wl)
+    ion = picgen.ions_like(wl, e)
+    sim = _sim(nx=128, ny=128, nz=128, dt=wl.dt, dims=3, precision=precision,
+               sort_every=wl.sort_every, source=src)
+    s = sim.add_species(e.q, e.m, e.n)
+    sim.load(s, e.x, e.w, e.weight)
+    si = sim.add_species(ion.q, ion.m, 0, mobile=False)
+    sim.load(si, ion.x, ion.w, ion.weight)
+    del e, ion
+    sim.step(59)
+    g = oracle.Grid(128, 128, 128, wl.dt)   # the source only acts on the grid
+    _sampled_step_check(sim, g, -1.0, 3, (128, 128, 128),
+                        1e-12 if precision == "fp64" else 2e-6, nsample=1500)
+    d = sim.diagnostics()
+    assert d["gauss_rel"] <= (1e-12 if precision == "fp64" else 1e-6), d
+    assert d["nonfinite"] == 0
+    assert d["field_e"] > 0.0
