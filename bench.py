@@ -122,7 +122,21 @@ def main(argv=None):
     ap.add_argument("--workload", default="3d_64cube_8ppc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32c"], default="both")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 256 MiB (5 times), the reference "
+                         "for scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args(argv)
+    if args.copy_probe:
+        import torch
+        n = 256 * 1024 * 1024 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                          "launches": 5}))
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU "
                                    "decomposition is a design (see the design notes), "

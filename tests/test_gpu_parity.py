@@ -322,26 +322,29 @@ def _sampled_step_check(sim, g, qm, dims, n_axis, tol, rng_seed=99, nsample=2000
     fields = sim.fields_numpy()
     n = sim.count(species)
     rng = np.random.Generator(np.random.PCG64(rng_seed))
-    sample = np.sort(rng.choice(n, nsample, replace=False))
+    sample = np.sort(rng.choice(n, nsample, replace=False))   # particle ids
 
     def read():
+        """Sampled particles by id (the storage order may change at a sort)."""
+        import ctypes
         x = torch.empty((3, n), dtype=torch.float64, device=sim.device)
         w = torch.empty((3, n), dtype=torch.float64, device=sim.device)
         pid = torch.empty(n, dtype=torch.int64, device=sim.device)
-        import ctypes
         sim._check(sim.lib.pic_get_particles(sim.ctx, species, ctypes.c_void_p(x.data_ptr()),
                                               ctypes.c_void_p(w.data_ptr()), None,
                                               ctypes.c_void_p(pid.data_ptr()),
                                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
-        idx = torch.as_tensor(sample, device=sim.device)
+        where = torch.empty(n, dtype=torch.int64, device=sim.device)
+        where[pid] = torch.arange(n, device=sim.device)
+        idx = where[torch.as_tensor(sample, device=sim.device)]
         out = (x[:, idx].cpu().numpy(), w[:, idx].cpu().numpy(), pid[idx].cpu().numpy())
-        del x, w, pid
+        del x, w, pid, where
         return out
 
     x0, w0, id0 = read()
     sim.step(1)
     x1, w1, id1 = read()
-    assert np.array_equal(id0, id1)  # no sort in between: same storage order
+    assert np.array_equal(id0, sample) and np.array_equal(id1, sample)
     bn = fields.copy()
     oracle.half_b(g, bn)
     for k in range(nsample):
