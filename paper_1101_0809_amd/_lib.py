@@ -80,6 +80,10 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+    # load it first so that this library binds to it and can take torch's
+    # streams and allocations.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1101_0809_amd.build`")
     lib = ctypes.CDLL(path)
