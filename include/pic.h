@@ -58,8 +58,9 @@ enum pic_status {
 
 enum pic_precision {
     PIC_FP64 = 0,  /* particles as FP64 absolute positions; all arithmetic FP64 */
-    PIC_FP32C = 1  /* particles as int cell + FP32 offset, FP32 push/deposit with
-                      two-sum compensated FP32 current sums; grid and reductions FP64 */
+    PIC_FP32C = 1  /* particles as int cell + FP32 offset; gather, push and current
+                      contributions in FP32; contributions summed in FP64 (exact for
+                      FP32 terms) in the LDS tile; grid and reductions FP64 */
 };
 
 enum pic_field_op {

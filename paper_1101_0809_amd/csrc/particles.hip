@@ -14,8 +14,8 @@
 //      the same arithmetic on global memory (wrapped indices, global atomics);
 //   4. flush the LDS current tile into the global FP64 J with atomics.
 // Precision R = double (FP64 mode: absolute FP64 positions) or float (FP32
-// mode: packed int cell + FP32 offset; the LDS current is a hi/lo pair of
-// FP32 arrays updated with two-sum compensation).
+// mode: packed int cell + FP32 offset, FP32 gather, push and current
+// contributions); the LDS current tile is FP64 in both.
 #include "pic_internal.h"
 
 namespace pic {
@@ -418,39 +418,19 @@ struct PosIO<float, D> {
 };
 
 // ---------------------------------------------------------------------------
-// LDS current storage: FP64 accumulates directly; FP32 keeps hi and lo arrays
-// and compensates every add with the two-sum error of the atomic's own add
-// (the atomic returns the old value o, the stored sum is fl(o + v)).
+// LDS current storage.  Both precisions accumulate in FP64: an FP32
+// contribution is exact in FP64, so the tile sums carry only FP64 rounding
+// (relative 2^-53 per add).  This is the compensated accumulation of the FP32
+// mode: a hi/lo pair of FP32 arrays updated by two-sum from the atomic's
+// returned old value moves the same LDS bytes per contribution but needs the
+// round trip of a returning atomic, and measured about ten times slower.
 // ---------------------------------------------------------------------------
 template <class R, int NJ>
-struct LdsJ;
-
-template <int NJ>
-struct LdsJ<double, NJ> {
+struct LdsJ {
     double v[NJ];
     __device__ __forceinline__ void zero(int i) { v[i] = 0.0; }
-    __device__ __forceinline__ void add(int i, double x) { atomicAdd(&v[i], x); }
+    __device__ __forceinline__ void add(int i, R x) { atomicAdd(&v[i], (double)x); }
     __device__ __forceinline__ double get(int i) const { return v[i]; }
-};
-
-template <int NJ>
-struct LdsJ<float, NJ> {
-    float hi[NJ];
-    float lo[NJ];
-    __device__ __forceinline__ void zero(int i)
-    {
-        hi[i] = 0.0f;
-        lo[i] = 0.0f;
-    }
-    __device__ __forceinline__ void add(int i, float x)
-    {
-        const float o = atomicAdd(&hi[i], x);
-        const float s = o + x;
-        const float bv = s - o;
-        const float err = (o - (s - bv)) + (x - bv);
-        atomicAdd(&lo[i], err);  // unconditional: no divergent branch per contribution
-    }
-    __device__ __forceinline__ double get(int i) const { return (double)hi[i] + (double)lo[i]; }
 };
 
 __device__ __forceinline__ void global_add(double* p, double v)
