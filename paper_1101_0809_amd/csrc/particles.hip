@@ -910,11 +910,14 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
     return a;
 }
 
-// Tile and threads per workgroup of each instantiation.
+// Tile and threads per workgroup of each instantiation.  The bank order of
+// the sort (plane_order in sort.hip) assumes the 3D LDS current row stride
+// kTile3 + 4 + 2 * kMargin3 = 14.
 constexpr int kThreads3 = 512;
 constexpr int kThreads2 = 256;
 constexpr int kMargin3 = 1;
 constexpr int kMargin2 = 2;
+static_assert(kTile3 + 4 + 2 * kMargin3 == 14, "plane_order in sort.hip assumes a row stride of 14");
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 

@@ -21,6 +21,21 @@ __device__ __forceinline__ void unpack(uint32_t c, int i[3])
     i[2] = (int)(c >> 22);
 }
 
+// Order of the 64 cells of one z-plane of a 3D tile (T = 8).  The particle
+// kernel's LDS current tile has a row stride of 14 doubles, so cell (lx, ly)
+// of a plane sits in 8-byte bank pair r = (lx + 14 ly) mod 16.  Each r is
+// taken by exactly four cells of the plane; ordering the plane as (q, r) --
+// q the rank of the cell among those four -- makes any 16 consecutive cells
+// hit 16 distinct bank pairs, so a wave of rank-interleaved particles issues
+// its current atomics without bank conflicts.
+__device__ __forceinline__ uint32_t plane_order(uint32_t lx, uint32_t ly)
+{
+    const uint32_t r = (lx + 14u * ly) & 15u;
+    uint32_t q = 0;
+    for (uint32_t y = 0; y < ly; ++y) q += ((r + 2u * y) & 15u) < 8u ? 1u : 0u;
+    return q * 16u + r;
+}
+
 template <class R, int D, int T>
 __device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, int64_t p)
 {
@@ -35,7 +50,7 @@ __device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, 
     const int tx = i[0] / T, ty = i[1] / T, tz = D == 3 ? i[2] / T : 0;
     const uint32_t tile = ((uint32_t)tz * g.nt[1] + ty) * g.nt[0] + tx;
     const uint32_t lx = i[0] - tx * T, ly = i[1] - ty * T, lz = D == 3 ? i[2] - tz * T : 0;
-    const uint32_t local = D == 3 ? (lz * T + ly) * T + lx : ly * T + lx;
+    const uint32_t local = D == 3 ? lz * T * T + plane_order(lx, ly) : ly * T + lx;
     return tile * (uint32_t)(D == 3 ? T * T * T : T * T) + local;
 }
 

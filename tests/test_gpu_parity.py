@@ -287,8 +287,9 @@ def test_64cube_fullsize_sampled(precision):
 @pytest.mark.parametrize("dims", [3, 2])
 def test_sort_order_is_tile_major_rank_interleaved(dims):
     """After a sort, storage order is: tiles in order; inside a tile, rank
-    levels in order and, within a level, cells in increasing order.  The ids
-    are a permutation of the loaded ones."""
+    levels in order and, within a level, cells in the tile's cell order (3D:
+    z-planes in order, each plane in bank order).  The ids are a permutation
+    of the loaded ones."""
     if dims == 3:
         wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=20, ny=16, nz=9, steps=0)
         T = 8
@@ -308,7 +309,17 @@ def test_sort_order_is_tile_major_rank_interleaved(dims):
     tile = (tz * nt[1] + cell[1] // T) * nt[0] + cell[0] // T
     assert np.all(np.diff(tile) >= 0)
     lz = cell[2] % T if dims == 3 else np.zeros_like(cell[0])
-    local = (lz * T + cell[1] % T) * T + cell[0] % T
+    lx, ly = cell[0] % T, cell[1] % T
+    if dims == 3:
+        # in-plane bank order: r = (lx + 14 ly) mod 16, q = rank of the cell among
+        # the four cells of the plane with that r (in y order)
+        r = (lx + 14 * ly) % 16
+        q = np.zeros_like(r)
+        for y in range(T):
+            q += (y < ly) & (((r + 2 * y) % 16) < 8)
+        local = lz * T * T + q * 16 + r
+    else:
+        local = ly * T + lx
     for t in np.unique(tile):
         loc = local[tile == t]
         # a new rank level starts exactly where the local cell index drops
