@@ -913,7 +913,8 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
 // Tile and threads per workgroup of each instantiation.  The bank order of
 // the sort (plane_order in sort.hip) assumes the 3D LDS current row stride
 // kTile3 + 4 + 2 * kMargin3 = 14.
-constexpr int kThreads3 = 512;
+constexpr int kThreads3 = 768;    // FP64: 3 waves per SIMD, <= 170 VGPRs
+constexpr int kThreads3f = 1024;  // FP32: 4 waves per SIMD
 constexpr int kThreads2 = 256;
 constexpr int kMargin3 = 1;
 constexpr int kMargin2 = 2;
@@ -939,8 +940,8 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
     } else {
         StepArgs a = step_args<float>(sp, c.counters);
         if (c.k.dims == 3)
-            hipLaunchKernelGGL((k_particle_step<float, 3, kTile3, kMargin3, kThreads3>), grid,
-                               dim3(kThreads3), 0, s, c.k, a, c.fields, J);
+            hipLaunchKernelGGL((k_particle_step<float, 3, kTile3, kMargin3, kThreads3f>), grid,
+                               dim3(kThreads3f), 0, s, c.k, a, c.fields, J);
         else
             hipLaunchKernelGGL((k_particle_step<float, 2, kTile2, kMargin2, kThreads2>), grid,
                                dim3(kThreads2), 0, s, c.k, a, c.fields, J);
