@@ -81,6 +81,26 @@ def run_gpu(wl, precision: str, steps: int, warmup: int):
             "fallback": fallback}
 
 
+def measured_traffic(precision: str, workload: str):
+    """HBM bytes per particle-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or
+    None if there is none or the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_particle_step_{workload}.md")
+    src = os.path.join(ROOT, "paper_1101_0809_amd", "csrc", "particles.hip")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"<!-- traffic-json (\{.*\}) -->", open(path).read())
+    if not m:
+        return None
+    info = json.loads(m.group(1))
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if info.get("source_sha256_16") != digest:
+        return None
+    return info["traffic"].get(precision)
+
+
 def roofline(res, precision, wl):
     per_launch_ms = res["phases"]["particles"] / max(1, res["phases"]["steps"])
     bytes_launch = (res["n"] * particle_bytes(precision, wl.dims)
@@ -88,7 +108,7 @@ def roofline(res, precision, wl):
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "k_particle_step", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "bytes_per_launch": bytes_launch,
+            "traffic": measured_traffic(precision, wl.name), "bytes_per_launch": bytes_launch,
             "avg_launch_ms": round(per_launch_ms, 5)}
 
 
