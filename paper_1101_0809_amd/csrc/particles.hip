@@ -11,7 +11,10 @@
 //   3. each thread advances particles of the tile; a particle whose cell lies
 //      within M cells of its tile (it may have drifted since the last sort)
 //      gathers from LDS and deposits with LDS atomics, any other particle uses
-//      the same arithmetic on global memory (wrapped indices, global atomics);
+//      the same arithmetic on global memory (wrapped indices, global atomics).
+//      In 3D a particle that stays in its cell deposits its 54 non-zero
+//      contributions at once; one that crosses a cell face is queued and
+//      deposited with the full 144-entry window after the loop, by all lanes;
 //   4. flush the LDS current tile into the global FP64 J with atomics.
 // Precision R = double (FP64 mode: absolute FP64 positions) or float (FP32
 // mode: packed int cell + FP32 offset, FP32 gather, push and current
@@ -267,6 +270,41 @@ __device__ __forceinline__ void deposit3(const R (&dm)[3][4], const R (&dp)[3][4
     }
 }
 
+// A particle that stays in its cell (shift 0 on every axis) has start and end
+// weights on the same three cells per axis, so the window's fourth cell and
+// the face s+3 carry exactly zero: only faces s+1, s+2 and cells s..s+2 remain,
+// 2 x 3 x 3 = 18 contributions per component.  The values are those of
+// deposit3 on the same window.
+template <class R, class Sink>
+__device__ __forceinline__ void deposit3_still(const R (&s0)[3][3], const R (&s1)[3][3],
+                                               const R jfac[3], Sink S)
+{
+    const R third = R(1) / R(3);
+    R dm[3][3], dp[3][3], m3[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) {
+            dm[a][k] = s1[a][k] - s0[a][k];
+            dp[a][k] = s1[a][k] + s0[a][k];
+            m3[a][k] = dm[a][k] * third;
+        }
+    for (int comp = 0; comp < 3; ++comp) {
+        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
+        const R P0 = dm[comp][0] * jfac[comp];
+        const R P1 = (dm[comp][0] + dm[comp][1]) * jfac[comp];
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) {
+                const R tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
+                int ijk[3];
+                ijk[u] = b;
+                ijk[v] = c;
+                ijk[comp] = 1;
+                S(comp, ijk[0], ijk[1], ijk[2], P0 * tr);
+                ijk[comp] = 2;
+                S(comp, ijk[0], ijk[1], ijk[2], P1 * tr);
+            }
+    }
+}
+
 // 2D3V: the z sums collapse (sum of dp_z = 2, sum of dm_z = 0, sum over the
 // z faces of P_z = z0 - z1), leaving 12 + 12 + 16 contributions.  jz is the
 // J^z factor per unit transverse weight: (q/V) u_z / 4.
@@ -308,6 +346,11 @@ struct StepArgs {
     double q;        // charge per unit weight
     double qm;       // q / m
     unsigned long long* counters;
+    // queue of the tile's cell-crossing particles, kept in the spare copy of
+    // the particle arrays (idle between sorts) at the tile's own index range:
+    // start offsets qd0[a] and one packed word per entry
+    void* qd0[3];
+    int64_t* qword;
 };
 
 __device__ __forceinline__ int wrapi(int v, int n)
@@ -464,6 +507,7 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     __shared__ R sf[6 * NF];
     __shared__ LdsJ<R, 3 * NJ> sj;
     __shared__ unsigned int n_fallback;
+    __shared__ unsigned int n_queue;
 
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     const int tx = tile % g.nt[0];
@@ -492,7 +536,10 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     }
     // 2. clear the LDS current tile
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
-    if (threadIdx.x == 0) n_fallback = 0;
+    if (threadIdx.x == 0) {
+        n_fallback = 0;
+        n_queue = 0;
+    }
     __syncthreads();
 
     const R c = (R)g.c;
@@ -566,14 +613,55 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
         PosIO<R, D>::move(a, p, g, i0, d0, disp, d1, delta, true);
 
         // deposit
+        R jfac[3];
+        for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+        if (D == 3) {
+            // 3D: a particle inside the tile region that stays in its cell takes
+            // the compact deposit now; one that crosses a face is queued for a
+            // dense pass after the loop (a mixed wave would otherwise issue both
+            // the compact and the full set of atomics)
+            const bool still = (delta[0] | delta[1] | delta[2]) == 0;
+            const bool enq = inside && !still;
+            const unsigned long long mask = __ballot(enq);
+            if (mask) {
+                const int lane = threadIdx.x & 63;
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned int qbase = 0;
+                if (lane == leader) qbase = atomicAdd(&n_queue, (unsigned int)__popcll(mask));
+                qbase = __shfl(qbase, leader, 64);
+                if (enq) {
+                    const int64_t e = begin + qbase + __popcll(mask & ((1ull << lane) - 1ull));
+                    for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[e] = d0[ax];
+                    int64_t word = p - begin;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
+                        word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
+                    }
+                    a.qword[e] = word;
+                }
+            }
+            if (inside) {
+                if (still) {
+                    R s1[3][3], s0[3][3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        cell_weights<R>(d1[ax], s1[ax]);
+                        for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
+                    }
+                    const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
+                    auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                        sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
+                    };
+                    deposit3_still<R>(s0, s1, jfac, S);
+                }
+                continue;
+            }
+        }
         R dm[3][4], dp[3][4];
         for (int ax = 0; ax < D; ++ax) {
             R s1[3];
             cell_weights<R>(d1[ax], s1);
             window<R>(ax0[ax].s, s1, delta[ax], dm[ax], dp[ax]);
         }
-        R jfac[3];
-        for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
         const R jz2 = D == 2 ? qp * (R)(0.25 * g.inv_vol) * c * w[2] * inv : R(0);
         int s[3];
         for (int ax = 0; ax < 3; ++ax) s[ax] = (ax < D) ? rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1 : 0;
@@ -602,6 +690,47 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     }
     if (my_fallback) atomicAdd(&n_fallback, my_fallback);
     __syncthreads();
+
+    // 3b. (3D) the queued cell-crossing particles, densely: the full window
+    if (D == 3) {
+        const unsigned int nq = n_queue;
+        for (unsigned int q = threadIdx.x; q < nq; q += NT) {
+            const int64_t e = begin + q;
+            const int64_t word = a.qword[e];
+            const int64_t p = begin + (word & 0xffffffffll);
+            int rel[3], delta[3];
+            R d0[3], d1[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                rel[ax] = (int)((word >> (32 + 4 * ax)) & 15) - M;
+                delta[ax] = (int)((word >> (44 + 2 * ax)) & 3) - 1;
+                d0[ax] = ((const R*)a.qd0[ax])[e];
+                if (sizeof(R) == 8) {  // the stored end position, as in PosIO::move
+                    const double x = ((const double*)a.pos[ax])[p];
+                    d1[ax] = (R)(x - floor(x));
+                } else {
+                    d1[ax] = ((const R*)a.pos[ax])[p];
+                }
+            }
+            const R qp = (R)a.q * ((const R*)a.weight)[p];
+            R jfac[3];
+            for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+            R dm[3][4], dp[3][4];
+            for (int ax = 0; ax < 3; ++ax) {
+                R s0[3], s1[3];
+                cell_weights<R>(d0[ax], s0);
+                cell_weights<R>(d1[ax], s1);
+                window<R>(s0, s1, delta[ax], dm[ax], dp[ax]);
+            }
+            int sw[3];
+            for (int ax = 0; ax < 3; ++ax) sw[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
+            const int jb = (sw[0] + 2 + M) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
+            auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
+            };
+            deposit3<R>(dm, dp, jfac, S);
+        }
+        __syncthreads();
+    }
 
     // 4. flush the LDS current tile
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
@@ -907,6 +1036,8 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
     a.q = sp.d.q;
     a.qm = sp.d.q / sp.d.m;
     a.counters = counters;
+    for (int ax = 0; ax < 3; ++ax) a.qd0[ax] = sp.alt.pos[ax];
+    a.qword = sp.alt.id;
     return a;
 }
 
