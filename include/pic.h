@@ -196,9 +196,9 @@ int pic_get_particles(pic_ctx* ctx, int species, double* x, double* w, double* w
  * Asynchronous. */
 int pic_sort(pic_ctx* ctx, void* stream);
 
-/* Tuning of the particle-step kernel: fraction of particles that took the
- * global-memory path (outside their tile's LDS region) in the last step, or
- * -1 if not recorded.  Synchronizes the stream. */
+/* Tuning of the particle-step kernel: fraction of particle updates that took
+ * the global-memory path (outside their tile's LDS region) during the last
+ * pic_step call, or -1 if not recorded.  Synchronizes the stream. */
 double pic_last_fallback_fraction(pic_ctx* ctx, void* stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each pic_step

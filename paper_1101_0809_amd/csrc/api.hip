@@ -374,13 +374,15 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
     hipError_t e = ensure_sorted(c, s);
     if (e == hipSuccess) e = ensure_r0(c, s);
     if (e != hipSuccess) return hip_fail(&c, e, "step setup");
+    // fallback statistics of this call (pic_last_fallback_fraction)
+    e = zero_counters(c.counters + 1, 2, s);
+    if (e != hipSuccess) return hip_fail(&c, e, "step");
     for (int it = 0; it < nsteps; ++it) {
         const bool timed = ctx->timing_used < ctx->timing_cap;
         hipEvent_t* ev = timed ? &ctx->ev[5 * (size_t)ctx->timing_used] : nullptr;
         auto mark = [&](int k) {
             if (timed && e == hipSuccess) e = hipEventRecord(ev[k], s);
         };
-        e = zero_counters(c.counters + 1, 2, s);
         mark(0);
         if (e == hipSuccess) e = launch_field_half_b(c, s);
         mark(1);
