@@ -224,6 +224,7 @@ typedef struct pic_host_state {
     int32_t reserved;
     int64_t n[4];          /* particles per species */
     int32_t sorted[4];     /* species sorted since its last load */
+    int32_t copy[4];       /* which of the two particle-array copies is current */
 } pic_host_state;
 
 int pic_get_host_state(const pic_ctx* ctx, pic_host_state* out);

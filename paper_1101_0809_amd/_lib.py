@@ -63,7 +63,8 @@ class Diag(ctypes.Structure):
 class HostState(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("since_sort", ctypes.c_int32),
                 ("r0_valid", ctypes.c_int32), ("nsp", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("n", ctypes.c_int64 * 4), ("sorted", ctypes.c_int32 * 4)]
+                ("n", ctypes.c_int64 * 4), ("sorted", ctypes.c_int32 * 4),
+                ("copy", ctypes.c_int32 * 4)]
 
 
 class PicError(RuntimeError):

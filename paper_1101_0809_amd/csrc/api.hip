@@ -159,7 +159,7 @@ size_t particle_copy_bytes(int precision, int64_t cap)
 size_t particle_bytes(const GridK& k, int precision, int64_t cap)
 {
     const size_t C = (size_t)cap;
-    return 2 * particle_copy_bytes(precision, cap) + 2 * align_up(C * 4, kAlign) +
+    return 2 * particle_copy_bytes(precision, cap) + 3 * align_up(C * 4, kAlign) +
            align_up(((size_t)k.ntiles + 1) * 8, kAlign);
 }
 
@@ -324,6 +324,8 @@ int pic_add_species(pic_ctx* ctx, const pic_species_desc* s, void* buffer, size_
         sp.key = (uint32_t*)p;
         p += align_up((size_t)s->capacity * 4, kAlign);
         sp.rank = (uint32_t*)p;
+        p += align_up((size_t)s->capacity * 4, kAlign);
+        sp.dest = (uint32_t*)p;
         p += align_up((size_t)s->capacity * 4, kAlign);
         sp.tile_start = (int64_t*)p;
     }
@@ -542,6 +544,7 @@ int pic_get_host_state(const pic_ctx* ctx, pic_host_state* out)
     for (int i = 0; i < c.nsp; ++i) {
         out->n[i] = c.sp[i].n;
         out->sorted[i] = c.sp[i].sorted ? 1 : 0;
+        out->copy[i] = c.sp[i].swapped;
     }
     return PIC_OK;
 }
@@ -559,8 +562,15 @@ int pic_set_host_state(pic_ctx* ctx, const pic_host_state* in)
     c.since_sort = in->since_sort;
     c.r0_valid = in->r0_valid != 0;
     for (int i = 0; i < c.nsp; ++i) {
-        c.sp[i].n = c.sp[i].d.mobile ? in->n[i] : 0;
-        c.sp[i].sorted = in->sorted[i] != 0;
+        Species& sp = c.sp[i];
+        sp.n = sp.d.mobile ? in->n[i] : 0;
+        sp.sorted = in->sorted[i] != 0;
+        if (sp.d.mobile && (in->copy[i] & 1) != sp.swapped) {
+            const PartArrays t = sp.cur;
+            sp.cur = sp.alt;
+            sp.alt = t;
+            sp.swapped ^= 1;
+        }
     }
     return PIC_OK;
 }

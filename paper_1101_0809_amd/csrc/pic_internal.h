@@ -38,8 +38,10 @@ struct Species {
     PartArrays cur{}, alt{};
     uint32_t* key = nullptr;   // sort key per particle
     uint32_t* rank = nullptr;  // rank within the key bucket (from the histogram atomics)
+    uint32_t* dest = nullptr;  // final slot of each cell-sorted position (sort scratch)
     int64_t* tile_start = nullptr;  // ntiles + 1 entries
     bool sorted = false;
+    int swapped = 0;           // 1: cur is the buffer's second copy
 };
 
 // Grid constants handed to kernels by value.

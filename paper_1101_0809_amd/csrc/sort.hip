@@ -1,10 +1,13 @@
 // sort.hip -- periodic counting sort of a species by cell, in tile-major cell
 // order, so that the particles of one tile (the unit of work of the particle
-// kernel) are contiguous.  Histogram with atomics (the returned slot is the
-// particle's rank in its cell), exclusive scan of the counts, scatter of every
-// particle array into the spare copy, then a per-tile pass that writes the
-// tile back rank-interleaved (see k_interleave).  Not part of the paper's
-// method; it only fixes the memory order of the particles.
+// kernel) are contiguous, and rank-interleaved inside each tile: the particle
+// of rank 0 of every cell of the tile (cells in the tile's cell order), then
+// those of rank 1, and so on, so that the 64 lanes of a wave that take
+// consecutive particles work in distinct cells.  Histogram with atomics (the
+// returned slot is the particle's rank in its cell), exclusive scan of the
+// counts, a per-tile pass computing every particle's final slot, and one
+// scatter of the particle arrays into the spare copy, which becomes current.
+// Not part of the paper's method; it only fixes the memory order.
 #include "pic_internal.h"
 
 namespace pic {
@@ -145,34 +148,14 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_apply(uint32_t* __restric
         if (base + i < n) data[base + i] = v[i] + off;
 }
 
-template <class R>
-__global__ __launch_bounds__(kSortThreads) void k_scatter(PartArrays src, PartArrays dst, int64_t n,
-                                                          const uint32_t* __restrict__ key,
-                                                          const uint32_t* __restrict__ rank,
-                                                          const uint32_t* __restrict__ offs)
-{
-    const int64_t p = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
-    if (p >= n) return;
-    const int64_t q = (int64_t)offs[key[p]] + rank[p];
-    for (int ax = 0; ax < 3; ++ax) {
-        ((R*)dst.pos[ax])[q] = ((const R*)src.pos[ax])[p];
-        ((R*)dst.mom[ax])[q] = ((const R*)src.mom[ax])[p];
-    }
-    ((R*)dst.weight)[q] = ((const R*)src.weight)[p];
-    if (sizeof(R) == 4) dst.cell[q] = src.cell[p];
-    dst.id[q] = src.id[p];
-}
-
-// Rank-interleave the cell-sorted particles of one tile: the particles of
-// rank 0 of every cell of the tile (in cell order), then those of rank 1, and
-// so on.  Consecutive particles then sit in distinct cells, so the 64 lanes of
-// a wave that take consecutive particles update distinct LDS current entries.
-// One workgroup per tile, one thread per cell of the tile.  Writes of one
-// rank level are contiguous.
-template <class R, int TPD>
-__global__ __launch_bounds__(TPD) void k_interleave(PartArrays src, PartArrays dst,
-                                                    const uint32_t* __restrict__ offs,
-                                                    int64_t nkeys, int64_t n)
+// Final slot of every particle of one tile in the rank-interleaved order,
+// written per cell-sorted position: dest[cb + r] for the particle of rank r of
+// the cell starting at cb.  Rank level r holds the cells with more than r
+// particles, in the tile's cell order, contiguously after level r - 1.  One workgroup per
+// tile, one thread per cell; only 4-byte writes.
+template <int TPD>
+__global__ __launch_bounds__(TPD) void k_dest(const uint32_t* __restrict__ offs, int64_t nkeys,
+                                              int64_t n, uint32_t* __restrict__ dest)
 {
     constexpr int NW = TPD / 64;
     __shared__ uint32_t wsum[NW];
@@ -184,7 +167,6 @@ __global__ __launch_bounds__(TPD) void k_interleave(PartArrays src, PartArrays d
     const int64_t ce = key + 1 < nkeys ? (int64_t)offs[key + 1] : n;
     const uint32_t cnt = (uint32_t)(ce - cb);
     const int64_t base = offs[(int64_t)blockIdx.x * TPD];
-    // workgroup maximum of the cell counts
     uint32_t m = cnt;
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
     if (lane == 0) wmax[wv] = m;
@@ -203,20 +185,36 @@ __global__ __launch_bounds__(TPD) void k_interleave(PartArrays src, PartArrays d
             pre += w < wv ? wsum[w] : 0u;
             tot += wsum[w];
         }
-        if (flag) {
-            const int64_t from = cb + r;
-            const int64_t to = level_base + pre + below;
-            for (int ax = 0; ax < 3; ++ax) {
-                ((R*)dst.pos[ax])[to] = ((const R*)src.pos[ax])[from];
-                ((R*)dst.mom[ax])[to] = ((const R*)src.mom[ax])[from];
-            }
-            ((R*)dst.weight)[to] = ((const R*)src.weight)[from];
-            if (sizeof(R) == 4) dst.cell[to] = src.cell[from];
-            dst.id[to] = src.id[from];
-        }
+        if (flag) dest[cb + r] = (uint32_t)(level_base + pre + below);
         level_base += tot;
         __syncthreads();
     }
+}
+
+// Move every particle straight to its final slot.  Consecutive particles are
+// (nearly) tile-ordered from the previous sort, so each XCD takes a contiguous
+// run of them: a tile's writes then gather in one XCD's L2.
+template <class R>
+__global__ __launch_bounds__(kSortThreads) void k_scatter_final(PartArrays src, PartArrays dst, int64_t n,
+                                                                const uint32_t* __restrict__ key,
+                                                                const uint32_t* __restrict__ rank,
+                                                                const uint32_t* __restrict__ offs,
+                                                                const uint32_t* __restrict__ dest)
+{
+    const int nb = gridDim.x;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+    const int blk = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    const int64_t p = (int64_t)blk * kSortThreads + threadIdx.x;
+    if (p >= n) return;
+    const int64_t q = dest[(int64_t)offs[key[p]] + rank[p]];
+    for (int ax = 0; ax < 3; ++ax) {
+        ((R*)dst.pos[ax])[q] = ((const R*)src.pos[ax])[p];
+        ((R*)dst.mom[ax])[q] = ((const R*)src.mom[ax])[p];
+    }
+    ((R*)dst.weight)[q] = ((const R*)src.weight)[p];
+    if (sizeof(R) == 4) dst.cell[q] = src.cell[p];
+    dst.id[q] = src.id[p];
 }
 
 template <int TPD>
@@ -247,11 +245,14 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
                        c.scan_part);
     constexpr int TPD = D == 3 ? T * T * T : T * T;
     if (n > 0) {
-        // cell-sorted into the spare copy, then rank-interleaved back
-        hipLaunchKernelGGL((k_scatter<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur, sp.alt,
-                           n, sp.key, sp.rank, c.hist);
-        hipLaunchKernelGGL((k_interleave<R, TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, sp.alt, sp.cur,
-                           c.hist, nk, n);
+        // final slots, then one scatter into the spare copy, which becomes current
+        hipLaunchKernelGGL((k_dest<TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n, sp.dest);
+        hipLaunchKernelGGL((k_scatter_final<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur,
+                           sp.alt, n, sp.key, sp.rank, c.hist, sp.dest);
+        const PartArrays t = sp.cur;
+        sp.cur = sp.alt;
+        sp.alt = t;
+        sp.swapped ^= 1;
     }
     hipLaunchKernelGGL((k_tile_start<TPD>), dim3(nblk(c.k.ntiles + 1)), dim3(kSortThreads), 0, s,
                        c.hist, c.k.ntiles, n, sp.tile_start);

@@ -211,7 +211,8 @@ class Sim:
                          "buffer": None if s.buffer is None else s.buffer.clone()}
                         for s in self.species],
             "host": {"step": hs.step, "since_sort": hs.since_sort, "r0_valid": hs.r0_valid,
-                     "nsp": hs.nsp, "n": list(hs.n), "sorted": list(hs.sorted)},
+                     "nsp": hs.nsp, "n": list(hs.n), "sorted": list(hs.sorted),
+                     "copy": list(hs.copy)},
         }
 
     @classmethod
@@ -234,7 +235,7 @@ class Sim:
         hs = L.HostState()
         hs.step, hs.since_sort, hs.r0_valid, hs.nsp = h["step"], h["since_sort"], h["r0_valid"], h["nsp"]
         for i in range(4):
-            hs.n[i], hs.sorted[i] = h["n"][i], h["sorted"][i]
+            hs.n[i], hs.sorted[i], hs.copy[i] = h["n"][i], h["sorted"][i], h["copy"][i]
         torch.cuda.synchronize()
         sim._check(sim.lib.pic_set_host_state(sim.ctx, ctypes.byref(hs)))
         return sim
