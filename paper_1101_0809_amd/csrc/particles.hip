@@ -500,9 +500,13 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 {
     constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
     constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
-    constexpr int NF = D == 3 ? LF * LF * LF : LF * LF;
+    // In 3D the field rows are padded to the current tile's row stride LJ: the
+    // sort places the 16 particles of one LDS pass in cells whose index
+    // lx + LJ ly differs modulo 16, so the gather reads of such a pass then
+    // fall in 16 different 8-byte bank pairs, as the current atomics do.
+    constexpr int SFY = D == 3 ? LJ : LF, SFZ = SFY * LF;
+    constexpr int NF = D == 3 ? SFZ * LF : LF * LF;  // padded plane size per component
     constexpr int NJ = D == 3 ? LJ * LJ * LJ : LJ * LJ;
-    constexpr int SFY = LF, SFZ = LF * LF;
     constexpr int SJY = LJ, SJZ = LJ * LJ;
     __shared__ R sf[6 * NF];
     __shared__ LdsJ<R, 3 * NJ> sj;
@@ -523,16 +527,17 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
 
     // 1. stage E^n, B^n (+ guard cells) into LDS
-    for (int e = threadIdx.x; e < 6 * NF; e += NT) {
-        const int comp = e / NF;
-        const int r = e - comp * NF;
+    constexpr int NV = D == 3 ? LF * LF * LF : LF * LF;  // values per component
+    for (int e = threadIdx.x; e < 6 * NV; e += NT) {
+        const int comp = e / NV;
+        const int r = e - comp * NV;
         const int lx = r % LF;
         const int ly = (r / LF) % LF;
         const int lz = D == 3 ? r / (LF * LF) : 0;
         const int gx = wr(T0[0] - 1 - M + lx, nx);
         const int gy = wr(T0[1] - 1 - M + ly, ny);
         const int gz = D == 3 ? wr(T0[2] - 1 - M + lz, nz) : 0;
-        sf[e] = (R)fields[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
+        sf[comp * NF + lx + ly * SFY + lz * SFZ] = (R)fields[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
     }
     // 2. clear the LDS current tile
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
