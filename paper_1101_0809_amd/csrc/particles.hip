@@ -351,6 +351,11 @@ struct StepArgs {
     // start offsets qd0[a] and one packed word per entry
     void* qd0[3];
     int64_t* qword;
+    // 3D: queue of the tile's displaced particles (32-bit slot offsets), in
+    // the spare copy's first momentum array, and the class map of the
+    // crossing queue (32-bit entry offsets), in its weight array
+    void* qdisp;
+    void* qmap;
 };
 
 __device__ __forceinline__ int wrapi(int v, int n)
@@ -492,26 +497,23 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles)
 }
 
 // ---------------------------------------------------------------------------
-// The particle-step kernel.
+// The 2D3V particle-step kernel (tile kTile2^2, margin kMargin2); every
+// particle deposits its window at once.
 // ---------------------------------------------------------------------------
 template <class R, int D, int T, int M, int NT>
 __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const double* __restrict__ fields,
                                                      double* __restrict__ Jg)
 {
+    static_assert(D == 2, "the 3D step is k_particle_step3");
     constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
     constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
-    // In 3D the field rows are padded to the current tile's row stride LJ: the
-    // sort places the 16 particles of one LDS pass in cells whose index
-    // lx + LJ ly differs modulo 16, so the gather reads of such a pass then
-    // fall in 16 different 8-byte bank pairs, as the current atomics do.
-    constexpr int SFY = D == 3 ? LJ : LF, SFZ = SFY * LF;
-    constexpr int NF = D == 3 ? SFZ * LF : LF * LF;  // padded plane size per component
+    constexpr int SFY = LF, SFZ = SFY * LF;
+    constexpr int NF = D == 3 ? SFZ * LF : LF * LF;
     constexpr int NJ = D == 3 ? LJ * LJ * LJ : LJ * LJ;
     constexpr int SJY = LJ, SJZ = LJ * LJ;
     __shared__ R sf[6 * NF];
     __shared__ LdsJ<R, 3 * NJ> sj;
     __shared__ unsigned int n_fallback;
-    __shared__ unsigned int n_queue;
 
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     const int tx = tile % g.nt[0];
@@ -541,10 +543,7 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     }
     // 2. clear the LDS current tile
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
-    if (threadIdx.x == 0) {
-        n_fallback = 0;
-        n_queue = 0;
-    }
+    if (threadIdx.x == 0) n_fallback = 0;
     __syncthreads();
 
     const R c = (R)g.c;
@@ -620,47 +619,6 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
         // deposit
         R jfac[3];
         for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
-        if (D == 3) {
-            // 3D: a particle inside the tile region that stays in its cell takes
-            // the compact deposit now; one that crosses a face is queued for a
-            // dense pass after the loop (a mixed wave would otherwise issue both
-            // the compact and the full set of atomics)
-            const bool still = (delta[0] | delta[1] | delta[2]) == 0;
-            const bool enq = inside && !still;
-            const unsigned long long mask = __ballot(enq);
-            if (mask) {
-                const int lane = threadIdx.x & 63;
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned int qbase = 0;
-                if (lane == leader) qbase = atomicAdd(&n_queue, (unsigned int)__popcll(mask));
-                qbase = __shfl(qbase, leader, 64);
-                if (enq) {
-                    const int64_t e = begin + qbase + __popcll(mask & ((1ull << lane) - 1ull));
-                    for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[e] = d0[ax];
-                    int64_t word = p - begin;
-                    for (int ax = 0; ax < 3; ++ax) {
-                        word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
-                        word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
-                    }
-                    a.qword[e] = word;
-                }
-            }
-            if (inside) {
-                if (still) {
-                    R s1[3][3], s0[3][3];
-                    for (int ax = 0; ax < 3; ++ax) {
-                        cell_weights<R>(d1[ax], s1[ax]);
-                        for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
-                    }
-                    const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
-                    auto S = [&](int comp, int ix, int iy, int iz, R v) {
-                        sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
-                    };
-                    deposit3_still<R>(s0, s1, jfac, S);
-                }
-                continue;
-            }
-        }
         R dm[3][4], dp[3][4];
         for (int ax = 0; ax < D; ++ax) {
             R s1[3];
@@ -696,11 +654,317 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     if (my_fallback) atomicAdd(&n_fallback, my_fallback);
     __syncthreads();
 
-    // 3b. (3D) the queued cell-crossing particles, densely: the full window
-    if (D == 3) {
-        const unsigned int nq = n_queue;
-        for (unsigned int q = threadIdx.x; q < nq; q += NT) {
-            const int64_t e = begin + q;
+    // 4. flush the LDS current tile
+    for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
+        const double v = sj.get(e);
+        if (v == 0.0) continue;
+        const int comp = e / NJ;
+        const int r = e - comp * NJ;
+        const int lx = r % LJ;
+        const int ly = (r / LJ) % LJ;
+        const int lz = D == 3 ? r / (LJ * LJ) : 0;
+        const int gx = wr(T0[0] - 2 - M + lx, nx);
+        const int gy = wr(T0[1] - 2 - M + ly, ny);
+        const int gz = D == 3 ? wr(T0[2] - 2 - M + lz, nz) : 0;
+        global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
+    }
+    if (threadIdx.x == 0 && a.counters) {
+        atomicAdd(&a.counters[1], (unsigned long long)n_fallback);
+        atomicAdd(&a.counters[2], (unsigned long long)(end - begin));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The 3D particle-step kernel (tile kTile3^3, margin kMargin3).
+//
+// LDS: the field tile holds E^n and B^n on the cells T0-2 .. T0+9 of each axis
+// (12 values), rows padded to kFieldRow3 values and planes to kFieldPlane3;
+// the components that are node-centred in z (E^z, B^x, B^y) never read the
+// first plane and store planes 1..11 only.  The FP64 current tile covers
+// T0-3 .. T0+10 (14 cells per axis) with plane stride kJPlane3.  A cell's
+// field and current base indices then share their residue modulo 32, and that
+// residue modulo C (16 in FP64, 32 in FP32) is the cell's lane class.  The
+// sort puts a particle of class s mod C in slot s of the tile's range wherever
+// the class counts allow, so that the LDS reads and atomics of 16 consecutive
+// lanes (one LDS pass for 8-byte values) fall in 16 distinct bank pairs.
+//
+// Passes over the tile:
+//   1. every slot: a particle in a cell of its lane's class is advanced and,
+//      if it stays in its cell, deposits its 54 non-zero contributions; one
+//      in a cell of another class (it has moved since the sort) is queued in
+//      the displaced queue, column = its class;
+//   2. the displaced queue, row by row: the same advance;
+//   3. particles of passes 1 and 2 that crossed a cell face were queued in the
+//      crossing queue, column = class of their window's first cell; each
+//      deposits its full 4x4x4 window (144 contributions).
+// Queue entry (row r, column k) is slot k + C r of the tile's range in the
+// spare particle copy, idle between sorts, so the lanes of one pass again
+// hold distinct classes.  A column that would run past the tile's range is
+// not queued: such a particle is processed at once (displaced) or deposits
+// with global atomics (crossing); correct, only slower.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a field component
+{
+    return comp < 2 ? 12 * comp : (comp < 5 ? 24 + 11 * (comp - 2) : 57);
+}
+__host__ __device__ constexpr int fnodez(int comp) { return comp >= 2 && comp <= 4 ? 1 : 0; }
+constexpr int kFieldPlanes3 = 69;  // 12 + 12 + 11 + 11 + 11 + 12
+constexpr int64_t kUnmapped = (int64_t)1 << 62;  // crossing entry not in the class map
+
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, const double* __restrict__ fields,
+                                                      double* __restrict__ Jg)
+{
+    constexpr int T = kTile3, M = kMargin3;
+    constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
+    constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
+    constexpr int SFY = kFieldRow3, SFZ = kFieldPlane3;
+    constexpr int SJY = LJ, SJZ = kJPlane3;
+    constexpr int NJ = LJ * SJZ;  // per current component
+    constexpr int C = lane_classes<R>();
+    constexpr int CJ = 16;  // classes of the FP64 current tile
+    static_assert(NT % C == 0 && NT % CJ == 0, "slots of one lane keep their class");
+    static_assert(LF == 12 && LJ == 14 && fplane0(5) + 12 == kFieldPlanes3, "layout of the 3D tile");
+    __shared__ R sf[kFieldPlanes3 * SFZ];
+    __shared__ LdsJ<R, 3 * NJ> sj;
+    __shared__ unsigned int qd_n[C];
+    __shared__ unsigned int qc_n[CJ];
+    __shared__ unsigned int qc_total, qc_unmapped;
+    __shared__ unsigned int n_fallback;
+
+    const int tile = xcd_tile(blockIdx.x, g.ntiles);
+    const int tx = tile % g.nt[0];
+    const int ty = (tile / g.nt[0]) % g.nt[1];
+    const int tz = tile / (g.nt[0] * g.nt[1]);
+    const int T0[3] = {tx * T, ty * T, tz * T};
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const bool small = nx < LJ || ny < LJ || nz < LJ;
+    auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
+
+    // 1. stage E^n, B^n into LDS, with SK loads of a thread in flight before
+    //    their stores (one load at a time would wait out the memory latency
+    //    once per value)
+    {
+        constexpr int NV = kFieldPlanes3 * LF * LF;
+        constexpr int SK = 7;
+        for (int e0 = threadIdx.x; e0 < NV; e0 += SK * NT) {
+            double v[SK];
+            int li[SK];
+#pragma unroll
+            for (int u = 0; u < SK; ++u) {
+                const int e = e0 + u * NT;
+                li[u] = -1;
+                if (e < NV) {
+                    const int pl = e / (LF * LF);
+                    const int rr = e - pl * (LF * LF);
+                    const int ly = rr / LF;
+                    const int lx = rr - ly * LF;
+                    const int comp = pl < 12 ? 0 : (pl < 24 ? 1 : (pl < 35 ? 2 : (pl < 46 ? 3 : (pl < 57 ? 4 : 5))));
+                    const int lz = pl - fplane0(comp) + fnodez(comp);
+                    const int gx = wr(T0[0] - 1 - M + lx, nx);
+                    const int gy = wr(T0[1] - 1 - M + ly, ny);
+                    const int gz = wr(T0[2] - 1 - M + lz, nz);
+                    v[u] = fields[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
+                    li[u] = pl * SFZ + ly * SFY + lx;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SK; ++u)
+                if (li[u] >= 0) sf[li[u]] = (R)v[u];
+        }
+    }
+    // 2. clear the LDS current tile and the queue counters
+    for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
+    if (threadIdx.x < C) qd_n[threadIdx.x] = 0;
+    if (threadIdx.x < CJ) qc_n[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        n_fallback = 0;
+        qc_total = 0;
+        qc_unmapped = 0;
+    }
+    __syncthreads();
+
+    const R c = (R)g.c;
+    const R c2 = c * c;
+    const R qmdt2 = (R)(0.5 * a.qm * g.dt);
+    const R cfl[3] = {(R)g.cfl[0], (R)g.cfl[1], (R)g.cfl[2]};
+    const R bext[3] = {(R)g.bext[0], (R)g.bext[1], (R)g.bext[2]};
+    const int64_t begin = a.tile_start[tile], end = a.tile_start[tile + 1];
+    const int nt = (int)(end - begin);
+    const unsigned capd = (unsigned)(nt / C), capc = (unsigned)(nt / CJ);
+    uint32_t* qdisp = (uint32_t*)a.qdisp + begin;
+    uint32_t* qmap = (uint32_t*)a.qmap + begin;
+    const int lane_cls = threadIdx.x & (C - 1);
+    unsigned int my_fallback = 0;
+
+    // 3. passes 1 and 2
+    for (int pass = 0; pass < 2; ++pass) {
+        int nslot = nt;
+        if (pass == 1) {
+            unsigned rows = 0;
+            for (int k = 0; k < C; ++k) rows = max(rows, min(qd_n[k], capd));
+            nslot = (int)rows * C;
+        }
+        for (int sl = threadIdx.x; sl < nslot; sl += NT) {
+            int64_t p = begin + sl;
+            if (pass == 1) {
+                if ((unsigned)(sl / C) >= min(qd_n[sl & (C - 1)], capd)) continue;
+                p = begin + qdisp[sl];
+            }
+            int i0[3];
+            R d0[3];
+            PosIO<R, 3>::load(a, p, i0, d0);
+            // position relative to the tile, periodic-corrected
+            int rel[3];
+            bool inside = true;
+            for (int ax = 0; ax < 3; ++ax) {
+                int r = i0[ax] - T0[ax];
+                const int n = g.n[ax];
+                if (r > n / 2) r -= n;
+                if (r < -(n / 2)) r += n;
+                rel[ax] = r;
+                inside = inside && (r >= -M) && (r <= T - 1 + M);
+            }
+            if (pass == 0 && inside) {
+                const int cls = cell_class3(rel[0], rel[1], rel[2], C);
+                if (cls != lane_cls) {
+                    const unsigned r = atomicAdd(&qd_n[cls], 1u);
+                    if (r < capd) {
+                        qdisp[cls + C * r] = (uint32_t)sl;
+                        continue;
+                    }
+                }
+            }
+
+            R w[3];
+            for (int ax = 0; ax < 3; ++ax) w[ax] = ((const R*)a.mom[ax])[p];
+            const R qp = (R)a.q * ((const R*)a.weight)[p];
+            Axis<R> ax0[3];
+            for (int ax = 0; ax < 3; ++ax) ax0[ax] = form_factor<R>(d0[ax]);
+
+            R E[3], B[3];
+            if (inside) {
+                const int base = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SFY + (rel[2] + 1 + M) * SFZ;
+                auto F = [&](int comp, int da, int db, int dc) -> R {
+                    return sf[(fplane0(comp) - fnodez(comp)) * SFZ + base + da + db * SFY + dc * SFZ];
+                };
+                gather3<R>(ax0, F, E, B);
+            } else {
+                ++my_fallback;
+                int xi[3], yj[3];
+                int64_t zk[3];
+                for (int o = 0; o < 3; ++o) {
+                    xi[o] = wrapi(i0[0] + o - 1, nx);
+                    yj[o] = wrapi(i0[1] + o - 1, ny) * nx;
+                    zk[o] = (int64_t)wrapi(i0[2] + o - 1, nz) * nx * ny;
+                }
+                auto F = [&](int comp, int da, int db, int dc) -> R {
+                    return (R)fields[comp * N + zk[dc + 1] + yj[db + 1] + xi[da + 1]];
+                };
+                gather3<R>(ax0, F, E, B);
+            }
+            for (int ax = 0; ax < 3; ++ax) B[ax] += bext[ax];
+
+            push<R>(qmdt2, c2, E, B, w);
+            for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
+
+            const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
+            R disp[3];
+            for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * cfl[ax];
+            R d1[3];
+            int delta[3] = {0, 0, 0};
+            PosIO<R, 3>::move(a, p, g, i0, d0, disp, d1, delta, true);
+
+            R jfac[3];
+            for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+            int s[3];
+            for (int ax = 0; ax < 3; ++ax) s[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
+            // a crossing particle inside the tile region is queued: its entry
+            // densely, in arrival order, and its place in the class map
+            const bool still = (delta[0] | delta[1] | delta[2]) == 0;
+            const bool enq = inside && !still;
+            const unsigned long long mask = __ballot(enq);
+            if (mask) {
+                const int lane = threadIdx.x & 63;
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned int qbase = 0;
+                if (lane == leader) qbase = atomicAdd(&qc_total, (unsigned int)__popcll(mask));
+                qbase = __shfl(qbase, leader, 64);
+                if (enq) {
+                    const unsigned e = qbase + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+                    for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
+                    int64_t word = p - begin;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
+                        word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
+                    }
+                    const int jw = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
+                    const int col = jw & (CJ - 1);
+                    const unsigned r = atomicAdd(&qc_n[col], 1u);
+                    if (r < capc) {
+                        qmap[col + CJ * r] = e;
+                    } else {
+                        word |= kUnmapped;
+                        atomicAdd(&qc_unmapped, 1u);
+                    }
+                    a.qword[begin + e] = word;
+                }
+            }
+            if (inside) {
+                if (still) {
+                    R s1[3][3], s0[3][3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        cell_weights<R>(d1[ax], s1[ax]);
+                        for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
+                    }
+                    const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
+                    auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                        sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
+                    };
+                    deposit3_still<R>(s0, s1, jfac, S);
+                }
+                continue;
+            }
+            // outside the tile region: global atomics
+            R dm[3][4], dp[3][4];
+            for (int ax = 0; ax < 3; ++ax) {
+                R s1[3];
+                cell_weights<R>(d1[ax], s1);
+                window<R>(ax0[ax].s, s1, delta[ax], dm[ax], dp[ax]);
+            }
+            int xi[4], yj[4];
+            int64_t zk[4];
+            for (int o = 0; o < 4; ++o) {
+                xi[o] = wrapi(T0[0] + s[0] + o, nx);
+                yj[o] = wrapi(T0[1] + s[1] + o, ny) * nx;
+                zk[o] = (int64_t)wrapi(T0[2] + s[2] + o, nz) * nx * ny;
+            }
+            auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
+            };
+            deposit3<R>(dm, dp, jfac, S);
+        }
+        __syncthreads();
+    }
+    if (my_fallback) atomicAdd(&n_fallback, my_fallback);
+
+    // 4. pass 3: the crossing queue, full windows -- the class map row by row,
+    //    then (only if a column was full) the unmapped entries in arrival order
+    {
+        unsigned rows = 0;
+        for (int k = 0; k < CJ; ++k) rows = max(rows, min(qc_n[k], capc));
+        const int nmap = (int)rows * CJ;
+        const int nq = nmap + (qc_unmapped ? (int)qc_total : 0);
+        for (int sl = threadIdx.x; sl < nq; sl += NT) {
+            int64_t e;
+            if (sl < nmap) {
+                if ((unsigned)(sl / CJ) >= min(qc_n[sl & (CJ - 1)], capc)) continue;
+                e = begin + qmap[sl];
+            } else {
+                e = begin + (sl - nmap);
+                if (!(a.qword[e] & kUnmapped)) continue;
+            }
             const int64_t word = a.qword[e];
             const int64_t p = begin + (word & 0xffffffffll);
             int rel[3], delta[3];
@@ -737,18 +1001,19 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
         __syncthreads();
     }
 
-    // 4. flush the LDS current tile
+    // 5. flush the LDS current tile (the plane padding is never written)
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
         const double v = sj.get(e);
         if (v == 0.0) continue;
         const int comp = e / NJ;
         const int r = e - comp * NJ;
-        const int lx = r % LJ;
-        const int ly = (r / LJ) % LJ;
-        const int lz = D == 3 ? r / (LJ * LJ) : 0;
+        const int lz = r / SJZ;
+        const int rr = r - lz * SJZ;
+        const int ly = rr / LJ;
+        const int lx = rr - ly * LJ;
         const int gx = wr(T0[0] - 2 - M + lx, nx);
         const int gy = wr(T0[1] - 2 - M + ly, ny);
-        const int gz = D == 3 ? wr(T0[2] - 2 - M + lz, nz) : 0;
+        const int gz = wr(T0[2] - 2 - M + lz, nz);
         global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
     }
     if (threadIdx.x == 0 && a.counters) {
@@ -1043,18 +1308,16 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
     a.counters = counters;
     for (int ax = 0; ax < 3; ++ax) a.qd0[ax] = sp.alt.pos[ax];
     a.qword = sp.alt.id;
+    a.qdisp = sp.alt.mom[0];
+    a.qmap = (void*)sp.alt.weight;
     return a;
 }
 
-// Tile and threads per workgroup of each instantiation.  The bank order of
-// the sort (plane_order in sort.hip) assumes the 3D LDS current row stride
-// kTile3 + 4 + 2 * kMargin3 = 14.
+// Threads per workgroup of each instantiation.
 constexpr int kThreads3 = 768;    // FP64: 3 waves per SIMD, <= 170 VGPRs
 constexpr int kThreads3f = 1024;  // FP32: 4 waves per SIMD
 constexpr int kThreads2 = 256;
-constexpr int kMargin3 = 1;
 constexpr int kMargin2 = 2;
-static_assert(kTile3 + 4 + 2 * kMargin3 == 14, "plane_order in sort.hip assumes a row stride of 14");
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -1068,16 +1331,16 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
     if (c.g.precision == PIC_FP64) {
         StepArgs a = step_args<double>(sp, c.counters);
         if (c.k.dims == 3)
-            hipLaunchKernelGGL((k_particle_step<double, 3, kTile3, kMargin3, kThreads3>), grid,
-                               dim3(kThreads3), 0, s, c.k, a, c.fields, J);
+            hipLaunchKernelGGL((k_particle_step3<double, kThreads3>), grid, dim3(kThreads3), 0, s, c.k, a,
+                               c.fields, J);
         else
             hipLaunchKernelGGL((k_particle_step<double, 2, kTile2, kMargin2, kThreads2>), grid,
                                dim3(kThreads2), 0, s, c.k, a, c.fields, J);
     } else {
         StepArgs a = step_args<float>(sp, c.counters);
         if (c.k.dims == 3)
-            hipLaunchKernelGGL((k_particle_step<float, 3, kTile3, kMargin3, kThreads3f>), grid,
-                               dim3(kThreads3f), 0, s, c.k, a, c.fields, J);
+            hipLaunchKernelGGL((k_particle_step3<float, kThreads3f>), grid, dim3(kThreads3f), 0, s, c.k, a,
+                               c.fields, J);
         else
             hipLaunchKernelGGL((k_particle_step<float, 2, kTile2, kMargin2, kThreads2>), grid,
                                dim3(kThreads2), 0, s, c.k, a, c.fields, J);

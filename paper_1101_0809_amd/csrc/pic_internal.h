@@ -19,6 +19,35 @@ constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its o
 constexpr int kTile3 = 8;
 constexpr int kTile2 = 16;
 
+// 3D particle kernel LDS layout.  A particle inside a tile's region may sit up
+// to kMargin3 cells outside the tile.  The field tile (E^n, B^n on 12 cells
+// per axis) has rows of kFieldRow3 values and planes of kFieldPlane3; the FP64
+// current tile (14 cells per axis) has rows of 14 and planes of kJPlane3
+// doubles.  The strides agree modulo 32, so the field base index and the
+// current base index of a cell have the same residue: the cell's lane class,
+// shared by the sort (which places particles by class) and the kernel.
+constexpr int kMargin3 = 1;
+constexpr int kFieldRow3 = 14;
+constexpr int kFieldPlane3 = 168;
+constexpr int kJPlane3 = 200;
+static_assert(kFieldRow3 >= kTile3 + 2 + 2 * kMargin3 && kFieldRow3 == kTile3 + 4 + 2 * kMargin3,
+              "field rows are padded to the current tile's row stride");
+static_assert(kFieldPlane3 >= 11 * kFieldRow3 + 12 && kJPlane3 >= 14 * 14, "planes hold their rows");
+static_assert((kJPlane3 - kFieldPlane3) % 32 == 0, "field and current plane strides agree mod 32");
+
+// Lane classes: LDS serves 128 bytes per clock, 16 lanes of 8-byte values (FP64
+// fields and the current tile) or 32 lanes of 4-byte values (FP32 fields).
+template <class R>
+constexpr int lane_classes() { return sizeof(R) == 8 ? 16 : 32; }
+
+// Class of a cell at offset rel (each in [-kMargin3, kTile3 - 1 + kMargin3])
+// from its tile's first cell: its field-tile base index modulo C.
+__host__ __device__ inline int cell_class3(int rx, int ry, int rz, int C)
+{
+    return ((rx + 1 + kMargin3) + (ry + 1 + kMargin3) * kFieldRow3 + (rz + 1 + kMargin3) * kFieldPlane3) &
+           (C - 1);
+}
+
 // Particle arrays of one copy (the library keeps two for out-of-place sorts).
 // FP64 mode: pos[a] are double absolute positions in [0, N_a).
 // FP32 mode: cell packs (i | j << 11 | k << 22), pos[a] are float offsets in [0, 1).

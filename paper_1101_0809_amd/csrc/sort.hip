@@ -1,13 +1,18 @@
 // sort.hip -- periodic counting sort of a species by cell, in tile-major cell
 // order, so that the particles of one tile (the unit of work of the particle
-// kernel) are contiguous, and rank-interleaved inside each tile: the particle
-// of rank 0 of every cell of the tile (cells in the tile's cell order), then
-// those of rank 1, and so on, so that the 64 lanes of a wave that take
-// consecutive particles work in distinct cells.  Histogram with atomics (the
-// returned slot is the particle's rank in its cell), exclusive scan of the
-// counts, a per-tile pass computing every particle's final slot, and one
-// scatter of the particle arrays into the spare copy, which becomes current.
-// Not part of the paper's method; it only fixes the memory order.
+// kernel) are contiguous.  Inside a tile the order serves the particle
+// kernel's LDS banks:
+//   3D: the cells are grouped by lane class (see cell_class3) and slot s of
+//       the tile's range holds a particle of class s mod C wherever the class
+//       counts allow (round g of the tile = one particle of each class); the
+//       particles left over by the fuller classes fill the empty places;
+//   2D: rank-interleaved -- the particle of rank 0 of every cell, then those
+//       of rank 1, and so on, so that consecutive lanes work in distinct cells.
+// Histogram with atomics (the returned slot is the particle's rank in its
+// cell), exclusive scan of the counts, a per-tile pass computing every
+// particle's final slot, and one scatter of the particle arrays into the spare
+// copy, which becomes current.  Not part of the paper's method; it only fixes
+// the memory order.
 #include "pic_internal.h"
 
 namespace pic {
@@ -24,19 +29,23 @@ __device__ __forceinline__ void unpack(uint32_t c, int i[3])
     i[2] = (int)(c >> 22);
 }
 
-// Order of the 64 cells of one z-plane of a 3D tile (T = 8).  The particle
-// kernel's LDS current tile has a row stride of 14 doubles, so cell (lx, ly)
-// of a plane sits in 8-byte bank pair r = (lx + 14 ly) mod 16.  Each r is
-// taken by exactly four cells of the plane; ordering the plane as (q, r) --
-// q the rank of the cell among those four -- makes any 16 consecutive cells
-// hit 16 distinct bank pairs, so a wave of rank-interleaved particles issues
-// its current atomics without bank conflicts.
-__device__ __forceinline__ uint32_t plane_order(uint32_t lx, uint32_t ly)
+// Tile-local key of a 3D cell (T = kTile3): class-major, class k owning keys
+// k * T^3 / C .. (k + 1) * T^3 / C - 1.  Each row (ly, lz) of the tile holds at
+// most one cell of a class (T < C consecutive x offsets), so the cell's index
+// inside its class is the number of earlier rows, in (lz, ly) order, that
+// hold a cell of that class.
+template <int C>
+__device__ __forceinline__ uint32_t class_major_local(int lx, int ly, int lz)
 {
-    const uint32_t r = (lx + 14u * ly) & 15u;
-    uint32_t q = 0;
-    for (uint32_t y = 0; y < ly; ++y) q += ((r + 2u * y) & 15u) < 8u ? 1u : 0u;
-    return q * 16u + r;
+    constexpr int T = kTile3;
+    static_assert(T < C && (T * T * T) % C == 0, "one cell of a class per row, equal classes");
+    const int cls = cell_class3(lx, ly, lz, C);
+    uint32_t idx = 0;
+    for (int row = 0; row < ly + lz * T; ++row) {
+        const int b = cell_class3(0, row % T, row / T, C);
+        idx += ((cls - b) & (C - 1)) < T ? 1u : 0u;
+    }
+    return (uint32_t)cls * (T * T * T / C) + idx;
 }
 
 template <class R, int D, int T>
@@ -53,7 +62,7 @@ __device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, 
     const int tx = i[0] / T, ty = i[1] / T, tz = D == 3 ? i[2] / T : 0;
     const uint32_t tile = ((uint32_t)tz * g.nt[1] + ty) * g.nt[0] + tx;
     const uint32_t lx = i[0] - tx * T, ly = i[1] - ty * T, lz = D == 3 ? i[2] - tz * T : 0;
-    const uint32_t local = D == 3 ? lz * T * T + plane_order(lx, ly) : ly * T + lx;
+    const uint32_t local = D == 3 ? class_major_local<lane_classes<R>()>((int)lx, (int)ly, (int)lz) : ly * T + lx;
     return tile * (uint32_t)(D == 3 ? T * T * T : T * T) + local;
 }
 
@@ -191,6 +200,66 @@ __global__ __launch_bounds__(TPD) void k_dest(const uint32_t* __restrict__ offs,
     }
 }
 
+// 3D: final slot of every particle of one tile in the class-round order,
+// written per cell-sorted position as in k_dest.  With n_t particles in the
+// tile, slot s belongs to column s mod C, row s / C; column k has rows_k =
+// ceil((n_t - k) / C) rows.  The particle of class k and index g within its
+// class (cells of the class in key order, then rank) takes row g of column k
+// if g < rows_k; the others (classes with more particles than rows), in
+// (class, g) order, fill the empty rows of the poorer columns in (column,
+// row) order.  The two counts agree: both classes and columns sum to n_t.
+template <int C>
+__global__ __launch_bounds__(kTile3 * kTile3 * kTile3) void k_dest3(const uint32_t* __restrict__ offs,
+                                                                     int64_t nkeys, int64_t n,
+                                                                     uint32_t* __restrict__ dest)
+{
+    constexpr int TPD = kTile3 * kTile3 * kTile3;
+    constexpr int CPC = TPD / C;  // cells per class
+    __shared__ uint32_t ccnt[C], cbase[C], rows[C], hpre[C + 1], lpre[C + 1];
+    const int c = threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.x * TPD;
+    const int64_t key = k0 + c;
+    const int64_t cb = offs[key];
+    const int64_t ce = key + 1 < nkeys ? (int64_t)offs[key + 1] : n;
+    const int64_t tb = offs[k0];
+    const int64_t te = k0 + TPD < nkeys ? (int64_t)offs[k0 + TPD] : n;
+    const int64_t nt = te - tb;
+    if (c < C) {
+        const int64_t kc = k0 + (int64_t)c * CPC;
+        const int64_t b0 = offs[kc];
+        const int64_t b1 = kc + CPC < nkeys ? (int64_t)offs[kc + CPC] : n;
+        cbase[c] = (uint32_t)(b0 - tb);
+        ccnt[c] = (uint32_t)(b1 - b0);
+        rows[c] = nt > c ? (uint32_t)((nt - c + C - 1) / C) : 0u;
+    }
+    __syncthreads();
+    if (c == 0) {
+        hpre[0] = 0;
+        lpre[0] = 0;
+        for (int k = 0; k < C; ++k) {
+            hpre[k + 1] = hpre[k] + (rows[k] > ccnt[k] ? rows[k] - ccnt[k] : 0u);
+            lpre[k + 1] = lpre[k] + (ccnt[k] > rows[k] ? ccnt[k] - rows[k] : 0u);
+        }
+    }
+    __syncthreads();
+    const int cls = c / CPC;
+    const uint32_t cnt = (uint32_t)(ce - cb);
+    const uint32_t g0 = (uint32_t)(cb - tb) - cbase[cls];
+    for (uint32_t r = 0; r < cnt; ++r) {
+        const uint32_t gi = g0 + r;
+        uint32_t slot;
+        if (gi < rows[cls]) {
+            slot = gi * C + cls;
+        } else {
+            const uint32_t k = lpre[cls] + (gi - rows[cls]);
+            int lam = 0;
+            while (lam < C - 1 && hpre[lam + 1] <= k) ++lam;
+            slot = (ccnt[lam] + (k - hpre[lam])) * C + lam;
+        }
+        dest[cb + r] = (uint32_t)(tb + slot);
+    }
+}
+
 // Move every particle straight to its final slot.  Consecutive particles are
 // (nearly) tile-ordered from the previous sort, so each XCD takes a contiguous
 // run of them: a tile's writes then gather in one XCD's L2.
@@ -246,7 +315,11 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
     constexpr int TPD = D == 3 ? T * T * T : T * T;
     if (n > 0) {
         // final slots, then one scatter into the spare copy, which becomes current
-        hipLaunchKernelGGL((k_dest<TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n, sp.dest);
+        if (D == 3)
+            hipLaunchKernelGGL((k_dest3<lane_classes<R>()>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n,
+                               sp.dest);
+        else
+            hipLaunchKernelGGL((k_dest<TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n, sp.dest);
         hipLaunchKernelGGL((k_scatter_final<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur,
                            sp.alt, n, sp.key, sp.rank, c.hist, sp.dest);
         const PartArrays t = sp.cur;

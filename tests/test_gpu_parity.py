@@ -159,6 +159,37 @@ def test_3d_ragged_tiles_fp64_parity():
     _compare(sim, st, wl, 1e-12, 1e-12, 1e-12)
 
 
+@pytest.mark.parametrize("precision,tols", [("fp64", (1e-12, 1e-12, 1e-12)),
+                                             ("fp32c", (1e-3, 1e-5, 1e-6))])
+def test_3d_crowded_cell_parity(precision, tols):
+    """600 electrons packed in one cell, beamed along +x, among a uniform
+    background: one lane class holds far more particles than its column of
+    the tile, and the crowd's crossers share one window class, so both class
+    queues of the 3D kernel overflow (displaced particles processed in place,
+    crossing entries outside the class map) -- against the oracle, with
+    re-sorts inside the run."""
+    rng = np.random.Generator(np.random.PCG64(20260))
+    n = 16
+    crowd = 600
+    x = np.concatenate([5.0 + rng.random((3, crowd)), rng.random((3, 1000)) * n], axis=1)
+    beam = rng.normal(0.0, 0.05, (3, crowd))
+    beam[0] += 0.9  # crossers of the crowd share one window class
+    w = np.concatenate([beam, rng.normal(0.0, 0.1, (3, 1000))], axis=1)
+    weight = np.full(x.shape[1], 0.01)
+    sim = _sim(nx=n, ny=n, nz=n, dt=0.45, dims=3, precision=precision, sort_every=3)
+    se = sim.add_species(-1.0, 1.0, x.shape[1])
+    sim.load(se, x, w, weight)
+    si = sim.add_species(1.0, 100.0, 0, mobile=False)
+    sim.load(si, x, np.zeros_like(w), weight)
+    st = oracle.State(oracle.Grid(n, n, n, 0.45),
+                      [oracle.Species(x, w, weight, q=-1.0, m=1.0),
+                       oracle.Species(x, np.zeros_like(w), weight, q=1.0, m=100.0, mobile=False)])
+    sim.step(7)
+    st.step(7)
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=n, ny=n, nz=n)
+    _compare(sim, st, wl, *tols)
+
+
 @pytest.mark.parametrize("dims", [2, 3])
 def test_fp32c_against_fp64_oracle(dims):
     """FP32 mode vs the FP64 oracle: Gauss drift <= 1e-6 (hard), field and
@@ -284,12 +315,16 @@ def test_64cube_fullsize_sampled(precision):
     assert abs(d["charge"]) < 1e-9 * e.n * e.weight[0]
 
 
-@pytest.mark.parametrize("dims", [3, 2])
-def test_sort_order_is_tile_major_rank_interleaved(dims):
-    """After a sort, storage order is: tiles in order; inside a tile, rank
-    levels in order and, within a level, cells in the tile's cell order (3D:
-    z-planes in order, each plane in bank order).  The ids are a permutation
-    of the loaded ones."""
+@pytest.mark.parametrize("dims,precision", [(3, "fp64"), (3, "fp32c"), (2, "fp64")])
+def test_sort_order(dims, precision):
+    """After a sort, storage order is tile-major and the ids are a permutation
+    of the loaded ones.  Inside a 3D tile of n_t particles, slot s holds a
+    particle of lane class s mod C (C = 16 FP64, 32 FP32; the class of tile
+    cell l is ((lx+2) + 14 (ly+2) + 168 (lz+2)) mod C) in as many slots as the
+    class counts allow -- sum over classes of min(count, rows of the column) --
+    those slots form the first rows of each column, and down a column the
+    cells follow their (lz, ly) row order.  Inside a 2D tile: rank levels in
+    order, cells in row-major order within a level."""
     if dims == 3:
         wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=20, ny=16, nz=9, steps=0)
         T = 8
@@ -297,7 +332,7 @@ def test_sort_order_is_tile_major_rank_interleaved(dims):
         wl = picgen.WORKLOADS["2d3v_32x32_fp64"].scaled(nx=40, ny=20, ppc=6)
         T = 16
     e = picgen.electrons(wl)
-    sim = _sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=dims)
+    sim = _sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=dims, precision=precision)
     s = sim.add_species(e.q, e.m, e.n)
     sim.load(s, e.x, e.w, e.weight)
     sim.sort()
@@ -311,26 +346,38 @@ def test_sort_order_is_tile_major_rank_interleaved(dims):
     lz = cell[2] % T if dims == 3 else np.zeros_like(cell[0])
     lx, ly = cell[0] % T, cell[1] % T
     if dims == 3:
-        # in-plane bank order: r = (lx + 14 ly) mod 16, q = rank of the cell among
-        # the four cells of the plane with that r (in y order)
-        r = (lx + 14 * ly) % 16
-        q = np.zeros_like(r)
-        for y in range(T):
-            q += (y < ly) & (((r + 2 * y) % 16) < 8)
-        local = lz * T * T + q * 16 + r
+        C = 16 if precision == "fp64" else 32
+        cls = ((lx + 2) + 14 * (ly + 2) + 168 * (lz + 2)) % C
+        row_order = lz * T + ly
+        for t in np.unique(tile):
+            sel = np.flatnonzero(tile == t)
+            n_t = sel.size
+            k = cls[sel]
+            slot = np.arange(n_t)
+            counts = np.bincount(k, minlength=C)
+            rows = np.array([max(0, -(-(n_t - c) // C)) for c in range(C)])
+            home = k == slot % C
+            assert home.sum() == np.minimum(counts, rows).sum()
+            for c in range(C):
+                col = slot % C == c
+                h = home[col]
+                m = int(min(counts[c], rows[c]))
+                assert h[:m].all() and not h[m:].any()
+                ro = row_order[sel][col][:m]
+                assert np.all(np.diff(ro) >= 0)
     else:
         local = ly * T + lx
-    for t in np.unique(tile):
-        loc = local[tile == t]
-        # a new rank level starts exactly where the local cell index drops
-        level = np.concatenate([[0], np.cumsum(np.diff(loc) <= 0)])
-        for lv in np.unique(level):
-            cells = loc[level == lv]
-            assert np.all(np.diff(cells) > 0)
-        # level r holds one particle of every cell with more than r particles
-        counts = np.bincount(loc, minlength=T ** dims)
-        for lv in np.unique(level):
-            assert np.sum(level == lv) == np.sum(counts > lv)
+        for t in np.unique(tile):
+            loc = local[tile == t]
+            # a new rank level starts exactly where the local cell index drops
+            level = np.concatenate([[0], np.cumsum(np.diff(loc) <= 0)])
+            for lv in np.unique(level):
+                cells = loc[level == lv]
+                assert np.all(np.diff(cells) > 0)
+            # level r holds one particle of every cell with more than r particles
+            counts = np.bincount(loc, minlength=T ** dims)
+            for lv in np.unique(level):
+                assert np.sum(level == lv) == np.sum(counts > lv)
 
 
 def _sampled_step_check(sim, g, qm, dims, n_axis, tol, rng_seed=99, nsample=2000, species=0):
