@@ -5,9 +5,11 @@ the particle kernel and the FP64 CPU oracle timed on the host beside it.
 Workload (default): 3D3V, 64^3 periodic cells, 8 electrons per cell
 (2,097,152 electrons), Gaussian momenta w_th = 0.1 c, co-located immobile ions,
 dt = 0.45 dx/c, particles re-sorted by cell every 10 steps.  One "step" is the
-whole step: B half step, particle kernel (gather, push, deposit), second B
-half step and E update, plus the periodic sort when due.  Inputs are resident
-on the GPU before the timed region starts.
+whole step: both B half steps, particle kernel (gather, push, deposit) and E
+update, plus the periodic sort when due.  Inputs are resident on the GPU
+before the timed region starts.  The K timed steps carry no per-phase events;
+K further steps with HIP events around each phase give the per-kernel
+durations of the roofline and the phase breakdown.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 10]
 
@@ -65,13 +67,17 @@ def run_gpu(wl, precision: str, steps: int, warmup: int):
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    sim.timing_start(steps)
-    torch.cuda.synchronize()
+    # timed pass: whole steps only (per-phase events would add their own gaps)
     start.record(stream)
     sim.step(steps)
     stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
+    # second pass of as many steps with HIP events around every phase, on the
+    # stream the kernels run on: per-kernel durations for the roofline
+    sim.timing_start(steps)
+    sim.step(steps)
+    torch.cuda.synchronize()
     phases = sim.timing_stop()
     fallback = sim.fallback_fraction()
     d = sim.diagnostics()

@@ -90,7 +90,9 @@ typedef struct pic_grid_desc {
      * The incident wave is carried by an auxiliary 1D line of PIC_AUX cells with
      * the grid's own staggered operators along x; its E^y point at
      * x = src_plane - 2 + 1/2 is driven as src_amp * ramp(t) * sin(src_omega t),
-     * ramp = sin^2(pi t / (2 src_ramp)) for t < src_ramp and 1 after, t = n dt. */
+     * ramp = sin^2(pi t / (2 src_ramp)) for t < src_ramp and 1 after, t = n dt.
+     * The line is kept in the last 2 * PIC_AUX doubles of the grid workspace
+     * (E^y, then B^z, PIC_AUX each). */
     int32_t src_kind;
     int32_t src_plane;
     double src_amp, src_omega, src_ramp;

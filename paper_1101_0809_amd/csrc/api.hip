@@ -143,7 +143,8 @@ size_t workspace_bytes(const GridK& k, uint32_t nkeys)
     b += align_up(((size_t)nkeys / 1024 + 2) * 4, kAlign);               // scan partials
     b += align_up(diag_partials_doubles(kMaxSpecies) * 8, kAlign);       // reductions
     b += align_up(8 * sizeof(unsigned long long), kAlign);               // counters
-    b += align_up(2 * (size_t)PIC_AUX * 8, kAlign);                      // source line
+    b += align_up(3 * (size_t)k.ncell * 8, kAlign);                      // B^n for the particles
+    b += align_up(2 * (size_t)PIC_AUX * 8, kAlign);                      // source line (last)
     return b;
 }
 
@@ -159,7 +160,7 @@ size_t particle_copy_bytes(int precision, int64_t cap)
 size_t particle_bytes(const GridK& k, int precision, int64_t cap)
 {
     const size_t C = (size_t)cap;
-    return 2 * particle_copy_bytes(precision, cap) + 3 * align_up(C * 4, kAlign) +
+    return 2 * particle_copy_bytes(precision, cap) + 4 * align_up(C * 4, kAlign) +
            align_up(((size_t)k.ntiles + 1) * 8, kAlign);
 }
 
@@ -288,7 +289,8 @@ int pic_init_grid(const pic_grid_desc* g, void* fields, size_t field_bytes, void
     c.scan_part = (uint32_t*)take(((size_t)nkeys / 1024 + 2) * 4);
     c.red = (double*)take(diag_partials_doubles(kMaxSpecies) * 8);
     c.counters = (unsigned long long*)take(8 * sizeof(unsigned long long));
-    c.k.aux = (double*)take(2 * (size_t)PIC_AUX * 8);
+    c.bn = (double*)take(3 * (size_t)k.ncell * 8);
+    c.k.aux = (double*)take(2 * (size_t)PIC_AUX * 8);  // last: its place is documented
     hipError_t e = hipMemset(c.rho_bg, 0, (size_t)k.ncell * 8);
     if (e == hipSuccess) e = hipMemset(c.k.aux, 0, 2 * (size_t)PIC_AUX * 8);
     if (e == hipSuccess) e = hipMemset(c.counters, 0, 8 * sizeof(unsigned long long));
@@ -326,6 +328,8 @@ int pic_add_species(pic_ctx* ctx, const pic_species_desc* s, void* buffer, size_
         sp.rank = (uint32_t*)p;
         p += align_up((size_t)s->capacity * 4, kAlign);
         sp.dest = (uint32_t*)p;
+        p += align_up((size_t)s->capacity * 4, kAlign);
+        sp.src = (uint32_t*)p;
         p += align_up((size_t)s->capacity * 4, kAlign);
         sp.tile_start = (int64_t*)p;
     }
@@ -385,13 +389,14 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
         auto mark = [&](int k) {
             if (timed && e == hipSuccess) e = hipEventRecord(ev[k], s);
         };
+        // both B half steps use E^n: one kernel writes B^n (for the particles)
+        // to the workspace and B^{n+1/2} in place
         mark(0);
-        if (e == hipSuccess) e = launch_field_half_b(c, s);
+        if (e == hipSuccess) e = launch_field_half_b_pair(c, s);
         mark(1);
         for (int i = 0; i < c.nsp && e == hipSuccess; ++i)
             if (c.sp[i].d.mobile) e = launch_particle_step(c, c.sp[i], s);
         mark(2);
-        if (e == hipSuccess) e = launch_field_half_b(c, s);
         if (e == hipSuccess) e = launch_field_update_e(c, s, c.step);
         mark(3);
         if (e != hipSuccess) return hip_fail(&c, e, "step");

@@ -59,6 +59,49 @@ __global__ __launch_bounds__(kFieldThreads) void k_half_b(GridK g, double* __res
     Bz[p] = bz;
 }
 
+// Both B half steps of a time step at once (they use the same E^n): B^n =
+// B^{n-1/2} - (1/2) curl_h E^n to bn, then B^{n+1/2} = B^n - (1/2) curl_h E^n
+// in place, each half step with the same expression and rounding as k_half_b.
+__global__ __launch_bounds__(kFieldThreads) void k_half_b_pair(GridK g, double* __restrict__ f,
+                                                               double* __restrict__ bn)
+{
+    const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
+    if (p >= g.ncell) return;
+    const CellIdx c = cell_of(p, g);
+    const int64_t N = g.ncell;
+    const double* Ex = f;
+    const double* Ey = f + N;
+    const double* Ez = f + 2 * N;
+    double* Bx = f + 3 * N;
+    double* By = f + 4 * N;
+    double* Bz = f + 5 * N;
+    const int64_t sx = 1, sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t im = c.i == 0 ? p + (g.n[0] - 1) * sx : p - sx;
+    const int64_t jm = c.j == 0 ? p + (int64_t)(g.n[1] - 1) * sy : p - sy;
+    const int64_t km = c.k == 0 ? p + (int64_t)(g.n[2] - 1) * sz : p - sz;
+    const double ex = Ex[p], ey = Ey[p], ez = Ez[p];
+    const double hx = g.half_cfl[0], hy = g.half_cfl[1], hz = g.half_cfl[2];
+    const double cx = hy * (ez - Ez[jm]), dx = hz * (ey - Ey[km]);
+    const double cy = hz * (ex - Ex[km]), dy = hx * (ez - Ez[im]);
+    const double cz = hx * (ey - Ey[im]), dz = hy * (ex - Ex[jm]);
+    const bool src = g.src_kind == 1 && c.i == g.src_plane;
+    const double sc = hx * g.aux[2];
+    double bx = Bx[p] - cx + dx;
+    double by = By[p] - cy + dy;
+    double bz = Bz[p] - cz + dz;
+    if (src) bz += sc;
+    bn[p] = bx;
+    bn[N + p] = by;
+    bn[2 * N + p] = bz;
+    bx = bx - cx + dx;
+    by = by - cy + dy;
+    bz = bz - cz + dz;
+    if (src) bz += sc;
+    Bx[p] = bx;
+    By[p] = by;
+    Bz[p] = bz;
+}
+
 // The source's auxiliary line, advanced by a one-workgroup kernel after each
 // grid kernel: the grid's B correction uses the line's E^y of time n, its E
 // correction the line's B^z of time n + 1/2, the values before each advance.
@@ -87,6 +130,12 @@ __device__ void aux_update_e(const GridK& g, double t)
 }
 
 __global__ __launch_bounds__(kFieldThreads) void k_aux_half_b(GridK g) { aux_half_b(g); }
+__global__ __launch_bounds__(kFieldThreads) void k_aux_half_b_pair(GridK g)
+{
+    aux_half_b(g);
+    __syncthreads();
+    aux_half_b(g);
+}
 __global__ __launch_bounds__(kFieldThreads) void k_aux_update_e(GridK g, double t) { aux_update_e(g, t); }
 
 // E <- E - 4 pi dt J + curl_h B ; J <- 0
@@ -130,6 +179,15 @@ hipError_t launch_field_half_b(const Ctx& c, hipStream_t s)
     hipLaunchKernelGGL(k_half_b, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields);
     if (c.k.src_kind == 1)  // after the grid kernel, which reads the line's E^y only
         hipLaunchKernelGGL(k_aux_half_b, dim3(1), dim3(kFieldThreads), 0, s, c.k);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
+    hipLaunchKernelGGL(k_half_b_pair, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields, c.bn);
+    if (c.k.src_kind == 1)  // the line's two half steps, after the grid kernel read its E^y
+        hipLaunchKernelGGL(k_aux_half_b_pair, dim3(1), dim3(kFieldThreads), 0, s, c.k);
     return hipGetLastError();
 }
 

@@ -351,11 +351,12 @@ struct StepArgs {
     // start offsets qd0[a] and one packed word per entry
     void* qd0[3];
     int64_t* qword;
-    // 3D: queue of the tile's displaced particles (32-bit slot offsets), in
-    // the spare copy's first momentum array, and the class map of the
+    // 3D: class queue of the tile's particles (32-bit slot offsets), in the
+    // spare copy's first two momentum arrays, and the class map of the
     // crossing queue (32-bit entry offsets), in its weight array
     void* qdisp;
     void* qmap;
+    void* qdisp2;
 };
 
 __device__ __forceinline__ int wrapi(int v, int n)
@@ -502,7 +503,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles)
 // ---------------------------------------------------------------------------
 template <class R, int D, int T, int M, int NT>
 __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const double* __restrict__ fields,
-                                                     double* __restrict__ Jg)
+                                                     const double* __restrict__ bfield, double* __restrict__ Jg)
 {
     static_assert(D == 2, "the 3D step is k_particle_step3");
     constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
     const bool small = nx < LJ || ny < LJ || (D == 3 && nz < LJ);
     auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
 
-    // 1. stage E^n, B^n (+ guard cells) into LDS
+    // 1. stage E^n, B^n (+ guard cells) into LDS; B^n is in bfield
     constexpr int NV = D == 3 ? LF * LF * LF : LF * LF;  // values per component
     for (int e = threadIdx.x; e < 6 * NV; e += NT) {
         const int comp = e / NV;
@@ -539,7 +540,8 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
         const int gx = wr(T0[0] - 1 - M + lx, nx);
         const int gy = wr(T0[1] - 1 - M + ly, ny);
         const int gz = D == 3 ? wr(T0[2] - 1 - M + lz, nz) : 0;
-        sf[comp * NF + lx + ly * SFY + lz * SFZ] = (R)fields[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
+        sf[comp * NF + lx + ly * SFY + lz * SFZ] =
+            (R)(comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[((int64_t)gz * ny + gy) * nx + gx];
     }
     // 2. clear the LDS current tile
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
@@ -599,7 +601,7 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
                 zk[o] = D == 3 ? (int64_t)wrapi(i0[2] + o - 1, nz) * nx * ny : 0;
             }
             auto F = [&](int comp, int da, int db, int dc) -> R {
-                return (R)fields[comp * N + zk[dc + 1] + yj[db + 1] + xi[da + 1]];
+                return (R)(comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[zk[dc + 1] + yj[db + 1] + xi[da + 1]];
             };
             if (D == 3) gather3<R>(ax0, F, E, B);
             else gather2<R>(ax0, F, E, B);
@@ -684,24 +686,26 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 // T0-3 .. T0+10 (14 cells per axis) with plane stride kJPlane3.  A cell's
 // field and current base indices then share their residue modulo 32, and that
 // residue modulo C (16 in FP64, 32 in FP32) is the cell's lane class.  The
-// sort puts a particle of class s mod C in slot s of the tile's range wherever
-// the class counts allow, so that the LDS reads and atomics of 16 consecutive
-// lanes (one LDS pass for 8-byte values) fall in 16 distinct bank pairs.
+// kernel hands particles to lanes by class, so that the LDS reads and atomics
+// of 16 consecutive lanes (one LDS pass for 8-byte values) fall in 16
+// distinct bank pairs.
 //
 // Passes over the tile:
-//   1. every slot: a particle in a cell of its lane's class is advanced and,
-//      if it stays in its cell, deposits its 54 non-zero contributions; one
-//      in a cell of another class (it has moved since the sort) is queued in
-//      the displaced queue, column = its class;
-//   2. the displaced queue, row by row: the same advance;
-//   3. particles of passes 1 and 2 that crossed a cell face were queued in the
-//      crossing queue, column = class of their window's first cell; each
-//      deposits its full 4x4x4 window (144 contributions).
-// Queue entry (row r, column k) is slot k + C r of the tile's range in the
-// spare particle copy, idle between sorts, so the lanes of one pass again
-// hold distinct classes.  A column that would run past the tile's range is
-// not queued: such a particle is processed at once (displaced) or deposits
-// with global atomics (crossing); correct, only slower.
+//   1. every slot: the particle's position is read, its cell classified, and
+//      the particle appended to the class queue, column = its class;
+//   2. the class queue, row by row: each particle is advanced and, if it stays
+//      in its cell, deposits its 54 non-zero contributions; one that crosses
+//      a cell face is appended to the crossing queue;
+//   3. the crossing queue: full-window deposit (144 contributions), in the
+//      order of a class map, column = class of the window's first cell.
+// Class-queue entry (row r, column k) is slot k + C r of the tile's range in
+// one of two spare-copy arrays (rows below n_t / C in the first), so the lanes
+// of one pass hold distinct classes; particles of the tile that sit in cells
+// of their slot's class also sit in queue order close to their slot, which
+// keeps the pass-2 loads nearly coalesced.  A particle outside the tile
+// region, or one whose class column is full, is advanced at once in pass 1
+// with global atomics or uncoordinated LDS accesses (correct, only slower).
+// The spare copy is idle between sorts.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a field component
 {
@@ -713,7 +717,7 @@ constexpr int64_t kUnmapped = (int64_t)1 << 62;  // crossing entry not in the cl
 
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, const double* __restrict__ fields,
-                                                      double* __restrict__ Jg)
+                                                      const double* __restrict__ bfield, double* __restrict__ Jg)
 {
     constexpr int T = kTile3, M = kMargin3;
     constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
@@ -742,7 +746,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     const bool small = nx < LJ || ny < LJ || nz < LJ;
     auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
 
-    // 1. stage E^n, B^n into LDS, with SK loads of a thread in flight before
+    // 1. stage E^n and B^n (B^n from bfield) into LDS, with SK loads of a thread in flight before
     //    their stores (one load at a time would wait out the memory latency
     //    once per value)
     {
@@ -765,7 +769,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
                     const int gx = wr(T0[0] - 1 - M + lx, nx);
                     const int gy = wr(T0[1] - 1 - M + ly, ny);
                     const int gz = wr(T0[2] - 1 - M + lz, nz);
-                    v[u] = fields[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
+                    v[u] = (comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[((int64_t)gz * ny + gy) * nx + gx];
                     li[u] = pl * SFZ + ly * SFY + lx;
                 }
             }
@@ -794,23 +798,24 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     const int nt = (int)(end - begin);
     const unsigned capd = (unsigned)(nt / C), capc = (unsigned)(nt / CJ);
     uint32_t* qdisp = (uint32_t*)a.qdisp + begin;
+    uint32_t* qdisp2 = (uint32_t*)a.qdisp2 + begin;
     uint32_t* qmap = (uint32_t*)a.qmap + begin;
-    const int lane_cls = threadIdx.x & (C - 1);
     unsigned int my_fallback = 0;
 
-    // 3. passes 1 and 2
+    // 3. passes 1 and 2 (pass 1 advances only particles it cannot queue)
     for (int pass = 0; pass < 2; ++pass) {
         int nslot = nt;
         if (pass == 1) {
             unsigned rows = 0;
-            for (int k = 0; k < C; ++k) rows = max(rows, min(qd_n[k], capd));
+            for (int k = 0; k < C; ++k) rows = max(rows, min(qd_n[k], 2 * capd));
             nslot = (int)rows * C;
         }
         for (int sl = threadIdx.x; sl < nslot; sl += NT) {
             int64_t p = begin + sl;
             if (pass == 1) {
-                if ((unsigned)(sl / C) >= min(qd_n[sl & (C - 1)], capd)) continue;
-                p = begin + qdisp[sl];
+                const unsigned row = (unsigned)(sl / C);
+                if (row >= min(qd_n[sl & (C - 1)], 2 * capd)) continue;
+                p = begin + (row < capd ? qdisp[sl] : qdisp2[sl - C * (int)capd]);
             }
             int i0[3];
             R d0[3];
@@ -828,12 +833,11 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
             }
             if (pass == 0 && inside) {
                 const int cls = cell_class3(rel[0], rel[1], rel[2], C);
-                if (cls != lane_cls) {
-                    const unsigned r = atomicAdd(&qd_n[cls], 1u);
-                    if (r < capd) {
-                        qdisp[cls + C * r] = (uint32_t)sl;
-                        continue;
-                    }
+                const unsigned r = atomicAdd(&qd_n[cls], 1u);
+                if (r < 2 * capd) {
+                    if (r < capd) qdisp[cls + C * r] = (uint32_t)sl;
+                    else qdisp2[cls + C * (r - capd)] = (uint32_t)sl;
+                    continue;
                 }
             }
 
@@ -860,7 +864,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
                     zk[o] = (int64_t)wrapi(i0[2] + o - 1, nz) * nx * ny;
                 }
                 auto F = [&](int comp, int da, int db, int dc) -> R {
-                    return (R)fields[comp * N + zk[dc + 1] + yj[db + 1] + xi[da + 1]];
+                    return (R)(comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[zk[dc + 1] + yj[db + 1] + xi[da + 1]];
                 };
                 gather3<R>(ax0, F, E, B);
             }
@@ -1310,6 +1314,7 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
     a.qword = sp.alt.id;
     a.qdisp = sp.alt.mom[0];
     a.qmap = (void*)sp.alt.weight;
+    a.qdisp2 = sp.alt.mom[1];
     return a;
 }
 
@@ -1332,18 +1337,18 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
         StepArgs a = step_args<double>(sp, c.counters);
         if (c.k.dims == 3)
             hipLaunchKernelGGL((k_particle_step3<double, kThreads3>), grid, dim3(kThreads3), 0, s, c.k, a,
-                               c.fields, J);
+                               c.fields, c.bn, J);
         else
             hipLaunchKernelGGL((k_particle_step<double, 2, kTile2, kMargin2, kThreads2>), grid,
-                               dim3(kThreads2), 0, s, c.k, a, c.fields, J);
+                               dim3(kThreads2), 0, s, c.k, a, c.fields, c.bn, J);
     } else {
         StepArgs a = step_args<float>(sp, c.counters);
         if (c.k.dims == 3)
             hipLaunchKernelGGL((k_particle_step3<float, kThreads3f>), grid, dim3(kThreads3f), 0, s, c.k, a,
-                               c.fields, J);
+                               c.fields, c.bn, J);
         else
             hipLaunchKernelGGL((k_particle_step<float, 2, kTile2, kMargin2, kThreads2>), grid,
-                               dim3(kThreads2), 0, s, c.k, a, c.fields, J);
+                               dim3(kThreads2), 0, s, c.k, a, c.fields, c.bn, J);
     }
     return hipGetLastError();
 }

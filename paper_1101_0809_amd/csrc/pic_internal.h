@@ -68,6 +68,7 @@ struct Species {
     uint32_t* key = nullptr;   // sort key per particle
     uint32_t* rank = nullptr;  // rank within the key bucket (from the histogram atomics)
     uint32_t* dest = nullptr;  // final slot of each cell-sorted position (sort scratch)
+    uint32_t* src = nullptr;   // particle that moves to each final slot (sort scratch)
     int64_t* tile_start = nullptr;  // ntiles + 1 entries
     bool sorted = false;
     int swapped = 0;           // 1: cur is the buffer's second copy
@@ -109,6 +110,7 @@ struct Ctx {
     uint32_t* hist = nullptr;   // nkeys + 1 counts / offsets
     uint32_t* scan_part = nullptr;
     double* red = nullptr;      // reduction partials
+    double* bn = nullptr;       // B^n of the current step (3 planes), read by the particles
     unsigned long long* counters = nullptr;  // [0] range errors, [1] fallback particles,
                                              // [2] particles processed
     uint32_t nkeys = 0;
@@ -124,6 +126,7 @@ size_t align_up(size_t v, size_t a);
 
 // ---- launchers (stream = hipStream_t) ----
 hipError_t launch_field_half_b(const Ctx& c, hipStream_t s);
+hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s);
 hipError_t launch_field_update_e(const Ctx& c, hipStream_t s, int64_t step);
 hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_load(Ctx& c, Species& sp, int64_t n, const double* x, const double* w,

@@ -10,8 +10,9 @@
 //       of rank 1, and so on, so that consecutive lanes work in distinct cells.
 // Histogram with atomics (the returned slot is the particle's rank in its
 // cell), exclusive scan of the counts, a per-tile pass computing every
-// particle's final slot, and one scatter of the particle arrays into the spare
-// copy, which becomes current.  Not part of the paper's method; it only fixes
+// particle's final slot, the inverse map (which particle fills each slot), and
+// one gather of the particle arrays into the spare copy, which becomes
+// current.  Not part of the paper's method; it only fixes
 // the memory order.
 #include "pic_internal.h"
 
@@ -260,30 +261,41 @@ __global__ __launch_bounds__(kTile3 * kTile3 * kTile3) void k_dest3(const uint32
     }
 }
 
-// Move every particle straight to its final slot.  Consecutive particles are
-// (nearly) tile-ordered from the previous sort, so each XCD takes a contiguous
-// run of them: a tile's writes then gather in one XCD's L2.
+// Which particle fills each final slot: the inverse of the final-slot map, by
+// one 4-byte scatter, so that the move writes every slot once, in order.
+__global__ __launch_bounds__(kSortThreads) void k_final_src(int64_t n, const uint32_t* __restrict__ key,
+                                                            const uint32_t* __restrict__ rank,
+                                                            const uint32_t* __restrict__ offs,
+                                                            const uint32_t* __restrict__ dest,
+                                                            uint32_t* __restrict__ src)
+{
+    const int64_t p = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    if (p >= n) return;
+    src[dest[(int64_t)offs[key[p]] + rank[p]]] = (uint32_t)p;
+}
+
+// Move the particle arrays: slot q of the spare copy takes particle src[q].
+// Writes are coalesced; reads are local, since a particle's new slot is
+// mostly in or near the tile range it came from.  Each XCD takes a
+// contiguous run of slots, so a tile's reads gather in one XCD's L2.
 template <class R>
-__global__ __launch_bounds__(kSortThreads) void k_scatter_final(PartArrays src, PartArrays dst, int64_t n,
-                                                                const uint32_t* __restrict__ key,
-                                                                const uint32_t* __restrict__ rank,
-                                                                const uint32_t* __restrict__ offs,
-                                                                const uint32_t* __restrict__ dest)
+__global__ __launch_bounds__(kSortThreads) void k_gather_final(PartArrays from, PartArrays to, int64_t n,
+                                                               const uint32_t* __restrict__ src)
 {
     const int nb = gridDim.x;
     const int per = nb / kXcds, rem = nb % kXcds;
     const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
     const int blk = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
-    const int64_t p = (int64_t)blk * kSortThreads + threadIdx.x;
-    if (p >= n) return;
-    const int64_t q = dest[(int64_t)offs[key[p]] + rank[p]];
+    const int64_t q = (int64_t)blk * kSortThreads + threadIdx.x;
+    if (q >= n) return;
+    const int64_t p = src[q];
     for (int ax = 0; ax < 3; ++ax) {
-        ((R*)dst.pos[ax])[q] = ((const R*)src.pos[ax])[p];
-        ((R*)dst.mom[ax])[q] = ((const R*)src.mom[ax])[p];
+        ((R*)to.pos[ax])[q] = ((const R*)from.pos[ax])[p];
+        ((R*)to.mom[ax])[q] = ((const R*)from.mom[ax])[p];
     }
-    ((R*)dst.weight)[q] = ((const R*)src.weight)[p];
-    if (sizeof(R) == 4) dst.cell[q] = src.cell[p];
-    dst.id[q] = src.id[p];
+    ((R*)to.weight)[q] = ((const R*)from.weight)[p];
+    if (sizeof(R) == 4) to.cell[q] = from.cell[p];
+    to.id[q] = from.id[p];
 }
 
 template <int TPD>
@@ -314,14 +326,17 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
                        c.scan_part);
     constexpr int TPD = D == 3 ? T * T * T : T * T;
     if (n > 0) {
-        // final slots, then one scatter into the spare copy, which becomes current
+        // final slots, their inverse, and one gather into the spare copy, which
+        // becomes current
         if (D == 3)
             hipLaunchKernelGGL((k_dest3<lane_classes<R>()>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n,
                                sp.dest);
         else
             hipLaunchKernelGGL((k_dest<TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n, sp.dest);
-        hipLaunchKernelGGL((k_scatter_final<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur,
-                           sp.alt, n, sp.key, sp.rank, c.hist, sp.dest);
+        hipLaunchKernelGGL(k_final_src, dim3(nblk(n)), dim3(kSortThreads), 0, s, n, sp.key, sp.rank, c.hist,
+                           sp.dest, sp.src);
+        hipLaunchKernelGGL((k_gather_final<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur, sp.alt, n,
+                           sp.src);
         const PartArrays t = sp.cur;
         sp.cur = sp.alt;
         sp.alt = t;
