@@ -112,7 +112,8 @@ def roofline(res, precision, wl):
     bytes_launch = (res["n"] * particle_bytes(precision, wl.dims)
                     + wl.ncell * grid_bytes_particle_kernel())
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": "k_particle_step", "achieved": round(achieved, 1),
+    kernel = "k_particle_step3" if wl.dims == 3 else "k_particle_step"
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(precision, wl.name), "bytes_per_launch": bytes_launch,
             "avg_launch_ms": round(per_launch_ms, 5)}
