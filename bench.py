@@ -107,7 +107,27 @@ def measured_traffic(precision: str, workload: str):
     return info["traffic"].get(precision)
 
 
-def roofline(res, precision, wl):
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM bandwidth: a plain device-to-device copy of 1 GiB (larger
+    than the 256 MB Infinity Cache), read + write bytes over the mean time."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    del src, dst
+    return 2 * nbytes / sec / 1e9
+
+
+def roofline(res, precision, wl, copy_gbs=None):
     per_launch_ms = res["phases"]["particles"] / max(1, res["phases"]["steps"])
     bytes_launch = (res["n"] * particle_bytes(precision, wl.dims)
                     + wl.ncell * grid_bytes_particle_kernel())
@@ -116,7 +136,9 @@ def roofline(res, precision, wl):
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(precision, wl.name), "bytes_per_launch": bytes_launch,
-            "avg_launch_ms": round(per_launch_ms, 5)}
+            "avg_launch_ms": round(per_launch_ms, 5),
+            "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+            "frac_of_copy": None if copy_gbs is None else round(achieved / copy_gbs, 4)}
 
 
 def cpu_baseline(wl, sample_steps: int = 1):
@@ -181,6 +203,7 @@ def main(argv=None):
               f"{r['phases']['particles'] / max(1, r['phases']['steps']):.4f} ms, "
               f"gauss_rel {r['diag']['gauss_rel']:.2e}, fallback {r['fallback']:.4f}",
               file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth()
     main_p = precs[0]
     r = results[main_p]
     value = r["n"] * 1000.0 / r["ms_per_step"]
@@ -200,7 +223,7 @@ def main(argv=None):
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "particles": r["n"],
                    "ppc": wl.ppc, "dt": wl.dt, "sort_every": wl.sort_every,
                    "precision": main_p, "parallelism": "none (1 GPU)"},
-        "roofline": roofline(r, main_p, wl),
+        "roofline": roofline(r, main_p, wl, copy_gbs),
         "phases_ms_per_step": {k: round(v / max(1, r["phases"]["steps"]), 5)
                                for k, v in r["phases"].items() if k != "steps"},
         "checks": {"gauss_rel": r["diag"]["gauss_rel"], "nonfinite": r["diag"]["nonfinite"],
@@ -211,7 +234,7 @@ def main(argv=None):
         v32 = r32["n"] * 1000.0 / r32["ms_per_step"]
         line["fp32c"] = {"value": round(v32, 1), "ms_per_step": round(r32["ms_per_step"], 5),
                          "speedup_vs_fp64": round(v32 / value, 3),
-                         "roofline": roofline(r32, "fp32c", wl),
+                         "roofline": roofline(r32, "fp32c", wl, copy_gbs),
                          "gauss_rel": r32["diag"]["gauss_rel"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
