@@ -357,6 +357,7 @@ struct StepArgs {
     void* qdisp;
     void* qmap;
     void* qdisp2;
+    void* qother;  // the particles pass 1 could not class-queue, in the third momentum array
 };
 
 __device__ __forceinline__ int wrapi(int v, int n)
@@ -390,6 +391,10 @@ struct PosIO;
 
 template <int D>
 struct PosIO<double, D> {
+    static __device__ __forceinline__ void cell(const StepArgs& a, int64_t p, int i[3])
+    {
+        for (int ax = 0; ax < 3; ++ax) i[ax] = ax < D ? (int)floor(((const double*)a.pos[ax])[p]) : 0;
+    }
     static __device__ __forceinline__ void load(const StepArgs& a, int64_t p, int i[3], double d[3])
     {
         for (int ax = 0; ax < D; ++ax) {
@@ -429,6 +434,7 @@ struct PosIO<double, D> {
 
 template <int D>
 struct PosIO<float, D> {
+    static __device__ __forceinline__ void cell(const StepArgs& a, int64_t p, int i[3]) { unpack_cell(a.cell[p], i); }
     static __device__ __forceinline__ void load(const StepArgs& a, int64_t p, int i[3], float d[3])
     {
         unpack_cell(a.cell[p], i);
@@ -691,11 +697,13 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 // distinct bank pairs.
 //
 // Passes over the tile:
-//   1. every slot: the particle's position is read, its cell classified, and
-//      the particle appended to the class queue, column = its class;
-//   2. the class queue, row by row: each particle is advanced and, if it stays
-//      in its cell, deposits its 54 non-zero contributions; one that crosses
-//      a cell face is appended to the crossing queue;
+//   1. every slot: the particle's cell is read and classified (the loads of
+//      several slots of a thread in flight at once), and the particle
+//      appended to the class queue, column = its class;
+//   2. the class queue, row by row, then the particles pass 1 could not
+//      queue: each particle is advanced and, if it stays in its cell, deposits
+//      its 54 non-zero contributions; one that crosses a cell face is appended
+//      to the crossing queue;
 //   3. the crossing queue: full-window deposit (144 contributions), in the
 //      order of a class map, column = class of the window's first cell.
 // Class-queue entry (row r, column k) is slot k + C r of the tile's range in
@@ -703,9 +711,10 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 // of one pass hold distinct classes; particles of the tile that sit in cells
 // of their slot's class also sit in queue order close to their slot, which
 // keeps the pass-2 loads nearly coalesced.  A particle outside the tile
-// region, or one whose class column is full, is advanced at once in pass 1
-// with global atomics or uncoordinated LDS accesses (correct, only slower).
-// The spare copy is idle between sorts.
+// region, or one whose class column is full, goes to the list of the others
+// (the spare copy's third momentum array) and is advanced after the queue with
+// global memory or uncoordinated LDS accesses (correct, only slower).  The
+// spare copy is idle between sorts.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a field component
 {
@@ -734,6 +743,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     __shared__ unsigned int qd_n[C];
     __shared__ unsigned int qc_n[CJ];
     __shared__ unsigned int qc_total, qc_unmapped;
+    __shared__ unsigned int qo_n;  // particles of pass 1 not in the class queue
     __shared__ unsigned int n_fallback;
 
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
@@ -786,6 +796,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         n_fallback = 0;
         qc_total = 0;
         qc_unmapped = 0;
+        qo_n = 0;
     }
     __syncthreads();
 
@@ -800,46 +811,82 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     uint32_t* qdisp = (uint32_t*)a.qdisp + begin;
     uint32_t* qdisp2 = (uint32_t*)a.qdisp2 + begin;
     uint32_t* qmap = (uint32_t*)a.qmap + begin;
+    uint32_t* qother = (uint32_t*)a.qother + begin;
     unsigned int my_fallback = 0;
 
-    // 3. passes 1 and 2 (pass 1 advances only particles it cannot queue)
-    for (int pass = 0; pass < 2; ++pass) {
-        int nslot = nt;
-        if (pass == 1) {
-            unsigned rows = 0;
-            for (int k = 0; k < C; ++k) rows = max(rows, min(qd_n[k], 2 * capd));
-            nslot = (int)rows * C;
+    // position of a cell relative to the tile, periodic-corrected; inside the
+    // tile region if within M cells of the tile
+    auto relative = [&](const int i0[3], int rel[3]) {
+        bool in = true;
+        for (int ax = 0; ax < 3; ++ax) {
+            int r = i0[ax] - T0[ax];
+            const int n = g.n[ax];
+            if (r > n / 2) r -= n;
+            if (r < -(n / 2)) r += n;
+            rel[ax] = r;
+            in = in && (r >= -M) && (r <= T - 1 + M);
         }
-        for (int sl = threadIdx.x; sl < nslot; sl += NT) {
-            int64_t p = begin + sl;
-            if (pass == 1) {
-                const unsigned row = (unsigned)(sl / C);
-                if (row >= min(qd_n[sl & (C - 1)], 2 * capd)) continue;
-                p = begin + (row < capd ? qdisp[sl] : qdisp2[sl - C * (int)capd]);
+        return in;
+    };
+
+    // 3. pass 1: classify every particle, with the cell loads of PU slots of a
+    //    thread in flight at once, into the class queue -- or, outside the tile
+    //    region or with its column full, into the list of the others
+    {
+        constexpr int PU = 4;
+        for (int b0 = threadIdx.x; b0 < nt; b0 += PU * NT) {
+            int ci[PU][3];
+#pragma unroll
+            for (int u = 0; u < PU; ++u)
+                if (b0 + u * NT < nt) PosIO<R, 3>::cell(a, begin + b0 + u * NT, ci[u]);
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int sl = b0 + u * NT;
+                if (sl >= nt) continue;
+                int rel[3];
+                bool queued = false;
+                if (relative(ci[u], rel)) {
+                    const int cls = cell_class3(rel[0], rel[1], rel[2], C);
+                    const unsigned r = atomicAdd(&qd_n[cls], 1u);
+                    if (r < 2 * capd) {
+                        if (r < capd) qdisp[cls + C * r] = (uint32_t)sl;
+                        else qdisp2[cls + C * (r - capd)] = (uint32_t)sl;
+                        queued = true;
+                    }
+                }
+                if (!queued) qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
             }
+        }
+        __syncthreads();
+    }
+
+    // 4. pass 2: the class queue row by row, then the others
+    {
+        unsigned rows = 0;
+        for (int k = 0; k < C; ++k) rows = max(rows, min(qd_n[k], 2 * capd));
+        const int nclass = (int)rows * C;
+        const int nslot = nclass + (int)qo_n;
+        // slot offset of the particle at queue position q, or -1 for a hole
+        auto entry = [&](int q) -> int {
+            if (q >= nslot) return -1;
+            if (q < nclass) {
+                const unsigned row = (unsigned)(q / C);
+                if (row >= min(qd_n[q & (C - 1)], 2 * capd)) return -1;
+                return (int)(row < capd ? qdisp[q] : qdisp2[q - C * (int)capd]);
+            }
+            return (int)qother[q - nclass];
+        };
+        int next = entry(threadIdx.x);  // read one round ahead
+        for (int sl = threadIdx.x; sl < nslot; sl += NT) {
+            const int off = next;
+            next = entry(sl + NT);
+            if (off < 0) continue;
+            const int64_t p = begin + off;
             int i0[3];
             R d0[3];
             PosIO<R, 3>::load(a, p, i0, d0);
-            // position relative to the tile, periodic-corrected
             int rel[3];
-            bool inside = true;
-            for (int ax = 0; ax < 3; ++ax) {
-                int r = i0[ax] - T0[ax];
-                const int n = g.n[ax];
-                if (r > n / 2) r -= n;
-                if (r < -(n / 2)) r += n;
-                rel[ax] = r;
-                inside = inside && (r >= -M) && (r <= T - 1 + M);
-            }
-            if (pass == 0 && inside) {
-                const int cls = cell_class3(rel[0], rel[1], rel[2], C);
-                const unsigned r = atomicAdd(&qd_n[cls], 1u);
-                if (r < 2 * capd) {
-                    if (r < capd) qdisp[cls + C * r] = (uint32_t)sl;
-                    else qdisp2[cls + C * (r - capd)] = (uint32_t)sl;
-                    continue;
-                }
-            }
+            const bool inside = relative(i0, rel);
 
             R w[3];
             for (int ax = 0; ax < 3; ++ax) w[ax] = ((const R*)a.mom[ax])[p];
@@ -953,7 +1000,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     }
     if (my_fallback) atomicAdd(&n_fallback, my_fallback);
 
-    // 4. pass 3: the crossing queue, full windows -- the class map row by row,
+    // 5. pass 3: the crossing queue, full windows -- the class map row by row,
     //    then (only if a column was full) the unmapped entries in arrival order
     {
         unsigned rows = 0;
@@ -1005,7 +1052,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         __syncthreads();
     }
 
-    // 5. flush the LDS current tile (the plane padding is never written)
+    // 6. flush the LDS current tile (the plane padding is never written)
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
         const double v = sj.get(e);
         if (v == 0.0) continue;
@@ -1315,6 +1362,7 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
     a.qdisp = sp.alt.mom[0];
     a.qmap = (void*)sp.alt.weight;
     a.qdisp2 = sp.alt.mom[1];
+    a.qother = sp.alt.mom[2];
     return a;
 }
 
