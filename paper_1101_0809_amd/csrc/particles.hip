@@ -305,6 +305,39 @@ __device__ __forceinline__ void deposit3_still(const R (&s0)[3][3], const R (&s1
     }
 }
 
+// A particle that crosses a cell face along axis A only (shift 0 on the other
+// two axes): on those axes the window's fourth cell and the face s+3 carry
+// exactly zero, leaving 3 x 3 x 3 contributions for the component along A and
+// 2 x 4 x 3 for each other component (75 in all).  The values are those of
+// deposit3 on the same window.
+template <int A, class R, class Sink>
+__device__ __forceinline__ void deposit3_axis(const R (&dm)[3][4], const R (&dp)[3][4], const R jfac[3],
+                                              Sink S)
+{
+    const R third = R(1) / R(3);
+    for (int comp = 0; comp < 3; ++comp) {
+        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
+        const int nt = comp == A ? 3 : 2;
+        const int nb = u == A ? 4 : 3, nc = v == A ? 4 : 3;
+        R P[3];
+        P[0] = dm[comp][0];
+        P[1] = dm[comp][0] + dm[comp][1];
+        P[2] = -dm[comp][3];
+        for (int t = 0; t < 3; ++t) P[t] *= jfac[comp];
+        for (int b = 0; b < nb; ++b)
+            for (int c = 0; c < nc; ++c) {
+                const R tr = dp[u][b] * dp[v][c] + (dm[u][b] * third) * dm[v][c];
+                for (int t = 0; t < nt; ++t) {
+                    int ijk[3];
+                    ijk[comp] = t + 1;
+                    ijk[u] = b;
+                    ijk[v] = c;
+                    S(comp, ijk[0], ijk[1], ijk[2], P[t] * tr);
+                }
+            }
+    }
+}
+
 // 2D3V: the z sums collapse (sum of dp_z = 2, sum of dm_z = 0, sum over the
 // z faces of P_z = z0 - z1), leaving 12 + 12 + 16 contributions.  jz is the
 // J^z factor per unit transverse weight: (q/V) u_z / 4.
@@ -704,8 +737,10 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 //      queue: each particle is advanced and, if it stays in its cell, deposits
 //      its 54 non-zero contributions; one that crosses a cell face is appended
 //      to the crossing queue;
-//   3. the crossing queue: full-window deposit (144 contributions), in the
-//      order of a class map, column = class of the window's first cell.
+//   3. the crossing queue, in the order of a class map (column = class of the
+//      window's first cell), in sections by crossing axis: a particle that
+//      crossed along one axis deposits the 75 non-zero contributions of its
+//      window, one that crossed along several all 144.
 // Class-queue entry (row r, column k) is slot k + C r of the tile's range in
 // one of two spare-copy arrays (rows below n_t / C in the first), so the lanes
 // of one pass hold distinct classes; particles of the tile that sit in cells
@@ -741,7 +776,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     __shared__ R sf[kFieldPlanes3 * SFZ];
     __shared__ LdsJ<R, 3 * NJ> sj;
     __shared__ unsigned int qd_n[C];
-    __shared__ unsigned int qc_n[CJ];
+    __shared__ unsigned int qc_n[4 * CJ];  // crossing map: 4 sections (axis 0, 1, 2, several) x CJ classes
     __shared__ unsigned int qc_total, qc_unmapped;
     __shared__ unsigned int qo_n;  // particles of pass 1 not in the class queue
     __shared__ unsigned int n_fallback;
@@ -791,7 +826,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     // 2. clear the LDS current tile and the queue counters
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
     if (threadIdx.x < C) qd_n[threadIdx.x] = 0;
-    if (threadIdx.x < CJ) qc_n[threadIdx.x] = 0;
+    if (threadIdx.x < 4 * CJ) qc_n[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         n_fallback = 0;
         qc_total = 0;
@@ -807,7 +842,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     const R bext[3] = {(R)g.bext[0], (R)g.bext[1], (R)g.bext[2]};
     const int64_t begin = a.tile_start[tile], end = a.tile_start[tile + 1];
     const int nt = (int)(end - begin);
-    const unsigned capd = (unsigned)(nt / C), capc = (unsigned)(nt / CJ);
+    const unsigned capd = (unsigned)(nt / C), capc = (unsigned)(nt / (4 * CJ));
     uint32_t* qdisp = (uint32_t*)a.qdisp + begin;
     uint32_t* qdisp2 = (uint32_t*)a.qdisp2 + begin;
     uint32_t* qmap = (uint32_t*)a.qmap + begin;
@@ -950,11 +985,14 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
                         word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
                         word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
                     }
+                    // map section: the crossing axis if there is one, 3 if several
+                    const int nax = (delta[0] != 0) + (delta[1] != 0) + (delta[2] != 0);
+                    const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
                     const int jw = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
-                    const int col = jw & (CJ - 1);
+                    const int col = sec * CJ + (jw & (CJ - 1));
                     const unsigned r = atomicAdd(&qc_n[col], 1u);
                     if (r < capc) {
-                        qmap[col + CJ * r] = e;
+                        qmap[col + 4 * CJ * r] = e;
                     } else {
                         word |= kUnmapped;
                         atomicAdd(&qc_unmapped, 1u);
@@ -1000,22 +1038,12 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     }
     if (my_fallback) atomicAdd(&n_fallback, my_fallback);
 
-    // 5. pass 3: the crossing queue, full windows -- the class map row by row,
-    //    then (only if a column was full) the unmapped entries in arrival order
+    // 5. pass 3: the crossing queue -- the class map's four sections (a
+    //    particle that crossed along one axis deposits its 75 non-zero
+    //    contributions, one that crossed along several its full window), then,
+    //    only if a map column was full, the unmapped entries in arrival order
     {
-        unsigned rows = 0;
-        for (int k = 0; k < CJ; ++k) rows = max(rows, min(qc_n[k], capc));
-        const int nmap = (int)rows * CJ;
-        const int nq = nmap + (qc_unmapped ? (int)qc_total : 0);
-        for (int sl = threadIdx.x; sl < nq; sl += NT) {
-            int64_t e;
-            if (sl < nmap) {
-                if ((unsigned)(sl / CJ) >= min(qc_n[sl & (CJ - 1)], capc)) continue;
-                e = begin + qmap[sl];
-            } else {
-                e = begin + (sl - nmap);
-                if (!(a.qword[e] & kUnmapped)) continue;
-            }
+        auto cross = [&](int64_t e, int sec) {
             const int64_t word = a.qword[e];
             const int64_t p = begin + (word & 0xffffffffll);
             int rel[3], delta[3];
@@ -1047,7 +1075,34 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
             auto S = [&](int comp, int ix, int iy, int iz, R v) {
                 sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
             };
-            deposit3<R>(dm, dp, jfac, S);
+            if (sec == 0) deposit3_axis<0, R>(dm, dp, jfac, S);
+            else if (sec == 1) deposit3_axis<1, R>(dm, dp, jfac, S);
+            else if (sec == 2) deposit3_axis<2, R>(dm, dp, jfac, S);
+            else deposit3<R>(dm, dp, jfac, S);
+        };
+        // the sections run side by side, one group of waves each, so that every
+        // wave runs a single deposit variant
+        {
+            constexpr int NG = NT / 64 / 4;  // waves per group
+            static_assert(NT % 256 == 0, "four equal groups of waves");
+            const int wv = threadIdx.x >> 6;
+            const int sec = wv & 3;
+            const int gt = (wv >> 2) * 64 + (threadIdx.x & 63);
+            unsigned rows = 0;
+            for (int k = 0; k < CJ; ++k) rows = max(rows, min(qc_n[sec * CJ + k], capc));
+            const int nmap = (int)rows * CJ;
+            for (int sl = gt; sl < nmap; sl += NG * 64) {
+                const int col = sec * CJ + (sl & (CJ - 1));
+                const unsigned row = (unsigned)(sl / CJ);
+                if (row >= min(qc_n[col], capc)) continue;
+                cross(begin + qmap[col + 4 * CJ * row], sec);
+            }
+        }
+        if (qc_unmapped) {
+            for (int q = threadIdx.x; q < (int)qc_total; q += NT) {
+                const int64_t e = begin + q;
+                if (a.qword[e] & kUnmapped) cross(e, 3);
+            }
         }
         __syncthreads();
     }

@@ -86,6 +86,51 @@ __global__ __launch_bounds__(kSortThreads) void k_histogram(GridK g, PartArrays 
     rank[p] = atomicAdd(&hist[k], 1u);
 }
 
+// Histogram of a species that is still grouped by the tiles of its previous
+// sort (particles move at most one cell per step): one workgroup per old tile
+// range counts the particles that are still in that tile in LDS (the local
+// rank comes from the LDS atomic) and then reserves each cell's rank range in
+// the global histogram with one atomic; a particle now in another tile takes
+// its rank from a global atomic directly.  Ranks stay unique per cell.
+constexpr uint32_t kLocalRank = 1u << 31;
+
+template <class R, int D, int T>
+__global__ __launch_bounds__(1024) void k_histogram_tiled(GridK g, PartArrays a, const int64_t* __restrict__ ts,
+                                                          uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
+                                                          uint32_t* __restrict__ hist)
+{
+    constexpr int TPD = D == 3 ? T * T * T : T * T;
+    constexpr int NTH = 1024, U = 4;  // threads, particles of a thread in flight
+    __shared__ uint32_t cnt[TPD];
+    const int t = blockIdx.x;
+    const int64_t b = ts[t], e = ts[t + 1];
+    const uint32_t k0 = (uint32_t)t * TPD;
+    for (int c = threadIdx.x; c < TPD; c += NTH) cnt[c] = 0;
+    __syncthreads();
+    for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += U * NTH) {
+        uint32_t k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (p0 + u * NTH < e) k[u] = key_of<R, D, T>(g, a, p0 + u * NTH);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = p0 + u * NTH;
+            if (p >= e) continue;
+            key[p] = k[u];
+            rank[p] = k[u] - k0 < (uint32_t)TPD ? (kLocalRank | atomicAdd(&cnt[k[u] - k0], 1u))
+                                                : atomicAdd(&hist[k[u]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < TPD; c += NTH)
+        if (cnt[c]) cnt[c] = atomicAdd(&hist[k0 + c], cnt[c]);
+    __syncthreads();
+    for (int64_t p = b + threadIdx.x; p < e; p += NTH) {
+        const uint32_t r = rank[p];
+        if (r & kLocalRank) rank[p] = cnt[key[p] - k0] + (r & ~kLocalRank);
+    }
+}
+
 // Exclusive scan of a block's 1024 counts; returns the block total.
 __device__ uint32_t block_scan(uint32_t (&v)[kScanItems], uint32_t* sh)
 {
@@ -165,7 +210,8 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_apply(uint32_t* __restric
 // tile, one thread per cell; only 4-byte writes.
 template <int TPD>
 __global__ __launch_bounds__(TPD) void k_dest(const uint32_t* __restrict__ offs, int64_t nkeys,
-                                              int64_t n, uint32_t* __restrict__ dest)
+                                              int64_t n, uint32_t* __restrict__ dest,
+                                              int64_t* __restrict__ ts)
 {
     constexpr int NW = TPD / 64;
     __shared__ uint32_t wsum[NW];
@@ -177,6 +223,8 @@ __global__ __launch_bounds__(TPD) void k_dest(const uint32_t* __restrict__ offs,
     const int64_t ce = key + 1 < nkeys ? (int64_t)offs[key + 1] : n;
     const uint32_t cnt = (uint32_t)(ce - cb);
     const int64_t base = offs[(int64_t)blockIdx.x * TPD];
+    if (c == 0) ts[blockIdx.x] = base;  // the tile table of the new order
+    if (c == 0 && blockIdx.x == gridDim.x - 1) ts[gridDim.x] = n;
     uint32_t m = cnt;
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, 64));
     if (lane == 0) wmax[wv] = m;
@@ -212,7 +260,8 @@ __global__ __launch_bounds__(TPD) void k_dest(const uint32_t* __restrict__ offs,
 template <int C>
 __global__ __launch_bounds__(kTile3 * kTile3 * kTile3) void k_dest3(const uint32_t* __restrict__ offs,
                                                                      int64_t nkeys, int64_t n,
-                                                                     uint32_t* __restrict__ dest)
+                                                                     uint32_t* __restrict__ dest,
+                                                                     int64_t* __restrict__ ts)
 {
     constexpr int TPD = kTile3 * kTile3 * kTile3;
     constexpr int CPC = TPD / C;  // cells per class
@@ -225,6 +274,8 @@ __global__ __launch_bounds__(kTile3 * kTile3 * kTile3) void k_dest3(const uint32
     const int64_t tb = offs[k0];
     const int64_t te = k0 + TPD < nkeys ? (int64_t)offs[k0 + TPD] : n;
     const int64_t nt = te - tb;
+    if (c == 0) ts[blockIdx.x] = tb;  // the tile table of the new order
+    if (c == 0 && blockIdx.x == gridDim.x - 1) ts[gridDim.x] = n;
     if (c < C) {
         const int64_t kc = k0 + (int64_t)c * CPC;
         const int64_t b0 = offs[kc];
@@ -315,7 +366,10 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
     const int64_t n = sp.n;
     const int64_t nk = c.nkeys;
     hipLaunchKernelGGL(k_zero_u32, dim3(nblk(nk)), dim3(kSortThreads), 0, s, c.hist, nk);
-    if (n > 0)
+    if (n > 0 && sp.sorted)  // still grouped by the tiles of the previous sort
+        hipLaunchKernelGGL((k_histogram_tiled<R, D, T>), dim3(c.k.ntiles), dim3(1024), 0, s, c.k,
+                           sp.cur, sp.tile_start, sp.key, sp.rank, c.hist);
+    else if (n > 0)
         hipLaunchKernelGGL((k_histogram<R, D, T>), dim3(nblk(n)), dim3(kSortThreads), 0, s, c.k,
                            sp.cur, n, sp.key, sp.rank, c.hist);
     const int64_t nb = (nk + kScanChunk - 1) / kScanChunk;
@@ -330,9 +384,10 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
         // becomes current
         if (D == 3)
             hipLaunchKernelGGL((k_dest3<lane_classes<R>()>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n,
-                               sp.dest);
+                               sp.dest, sp.tile_start);
         else
-            hipLaunchKernelGGL((k_dest<TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n, sp.dest);
+            hipLaunchKernelGGL((k_dest<TPD>), dim3(c.k.ntiles), dim3(TPD), 0, s, c.hist, nk, n, sp.dest,
+                               sp.tile_start);
         hipLaunchKernelGGL(k_final_src, dim3(nblk(n)), dim3(kSortThreads), 0, s, n, sp.key, sp.rank, c.hist,
                            sp.dest, sp.src);
         hipLaunchKernelGGL((k_gather_final<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur, sp.alt, n,
@@ -341,9 +396,10 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
         sp.cur = sp.alt;
         sp.alt = t;
         sp.swapped ^= 1;
+    } else {
+        hipLaunchKernelGGL((k_tile_start<TPD>), dim3(nblk(c.k.ntiles + 1)), dim3(kSortThreads), 0, s,
+                           c.hist, c.k.ntiles, n, sp.tile_start);
     }
-    hipLaunchKernelGGL((k_tile_start<TPD>), dim3(nblk(c.k.ntiles + 1)), dim3(kSortThreads), 0, s,
-                       c.hist, c.k.ntiles, n, sp.tile_start);
     sp.sorted = true;
     return hipGetLastError();
 }
