@@ -184,6 +184,33 @@ int pic_field_solve(pic_ctx* ctx, int what, void* stream);
 /* Compute pic_diag in FP64 on the GPU.  Synchronizes the stream. */
 int pic_diagnostics(pic_ctx* ctx, pic_diag* out, void* stream);
 
+/* Adjoint (reverse-mode derivative) of the time step, for gradients of a
+ * loss with respect to the initial momenta and the external field (FP64 mode,
+ * no plane-wave source; PIC_EINVAL otherwise).  An adjoint field buffer holds
+ * 6 planes of N FP64 in the layout of the field buffer's first six (dL/dE then
+ * dL/dB); a particle adjoint holds [3][count] FP64 indexed by particle id
+ * (load order), dL/dx (cell units) and dL/dw.  The caller owns all of them.
+ *
+ * pic_adjoint_seed_field_energy: write into lam_fields the derivative of the
+ * field energy V/(8 pi) sum E^2 + (B^n)^2 of the current state (E^n,
+ * B^{n-1/2}; B^n advanced a half step, Section 4.1) with respect to E^n and
+ * B^{n-1/2}.  Asynchronous.
+ *
+ * pic_adjoint_step: the context must hold the state a step was taken from
+ * (E^n, B^{n-1/2}, x^n, w^{n-1/2}), e.g. restored from a copy of its buffers
+ * and pic_set_host_state; it is not changed (the workspace is).  On entry
+ * lam_fields, lam_x[s], lam_w[s] hold the adjoint of the state after the step
+ * (E^{n+1}, B^{n+1/2}, x^{n+1}, w^{n+1/2}); on return the adjoint of the state
+ * before it, by the chain rule through the Appendix step: both B half steps
+ * (Eq. updateB), gather (Eqs. alphax, betax), push (Eq. p2), position advance
+ * (Eq. coordscheme), current (Eq. current) and E update (Eq. escheme).  The
+ * derivative of the loss with respect to the uniform external field is added
+ * into lam_bext[3].  lam_x and lam_w are host arrays with one device pointer
+ * per species (ignored for immobile species).  Asynchronous. */
+int pic_adjoint_seed_field_energy(pic_ctx* ctx, double* lam_fields, void* stream);
+int pic_adjoint_step(pic_ctx* ctx, double* lam_fields, double* const* lam_x, double* const* lam_w,
+                     double* lam_bext, void* stream);
+
 /* Number of particles currently held by a species (host-side count). */
 int64_t pic_particle_count(const pic_ctx* ctx, int species);
 

@@ -144,6 +144,7 @@ size_t workspace_bytes(const GridK& k, uint32_t nkeys)
     b += align_up(diag_partials_doubles(kMaxSpecies) * 8, kAlign);       // reductions
     b += align_up(8 * sizeof(unsigned long long), kAlign);               // counters
     b += align_up(3 * (size_t)k.ncell * 8, kAlign);                      // B^n for the particles
+    b += align_up(3 * (size_t)k.ncell * 8, kAlign);                      // adjoint scratch
     b += align_up(2 * (size_t)PIC_AUX * 8, kAlign);                      // source line (last)
     return b;
 }
@@ -290,6 +291,7 @@ int pic_init_grid(const pic_grid_desc* g, void* fields, size_t field_bytes, void
     c.red = (double*)take(diag_partials_doubles(kMaxSpecies) * 8);
     c.counters = (unsigned long long*)take(8 * sizeof(unsigned long long));
     c.bn = (double*)take(3 * (size_t)k.ncell * 8);
+    c.adj = (double*)take(3 * (size_t)k.ncell * 8);
     c.k.aux = (double*)take(2 * (size_t)PIC_AUX * 8);  // last: its place is documented
     hipError_t e = hipMemset(c.rho_bg, 0, (size_t)k.ncell * 8);
     if (e == hipSuccess) e = hipMemset(c.k.aux, 0, 2 * (size_t)PIC_AUX * 8);
@@ -442,6 +444,41 @@ int pic_field_solve(pic_ctx* ctx, int what, void* stream)
         return fail(&c, PIC_EINVAL, "what must be PIC_B_HALF or PIC_E_FULL");
     }
     if (e != hipSuccess) return hip_fail(&c, e, "field_solve");
+    return PIC_OK;
+}
+
+static int adjoint_ready(Ctx& c)
+{
+    if (c.g.precision != PIC_FP64) return fail(&c, PIC_EINVAL, "the adjoint is FP64 only");
+    if (c.k.src_kind != 0) return fail(&c, PIC_EINVAL, "the adjoint does not cover the plane-wave source");
+    return PIC_OK;
+}
+
+int pic_adjoint_seed_field_energy(pic_ctx* ctx, double* lam_fields, void* stream)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    if (!lam_fields) return fail(&c, PIC_EINVAL, "null adjoint field buffer");
+    const int r = adjoint_ready(c);
+    if (r != PIC_OK) return r;
+    hipError_t e = launch_adjoint_seed(c, lam_fields, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(&c, e, "adjoint_seed_field_energy");
+    return PIC_OK;
+}
+
+int pic_adjoint_step(pic_ctx* ctx, double* lam_fields, double* const* lam_x, double* const* lam_w,
+                     double* lam_bext, void* stream)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    if (!lam_fields || !lam_bext || !lam_x || !lam_w) return fail(&c, PIC_EINVAL, "null adjoint buffer");
+    const int r = adjoint_ready(c);
+    if (r != PIC_OK) return r;
+    for (int i = 0; i < c.nsp; ++i)
+        if (c.sp[i].d.mobile && c.sp[i].n > 0 && (!lam_x[i] || !lam_w[i]))
+            return fail(&c, PIC_EINVAL, "null particle adjoint of a mobile species");
+    hipError_t e = launch_adjoint_step(c, lam_fields, lam_x, lam_w, lam_bext, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(&c, e, "adjoint_step");
     return PIC_OK;
 }
 

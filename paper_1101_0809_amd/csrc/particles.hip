@@ -19,491 +19,10 @@
 // Precision R = double (FP64 mode: absolute FP64 positions) or float (FP32
 // mode: packed int cell + FP32 offset, FP32 gather, push and current
 // contributions); the LDS current tile is FP64 in both.
-#include "pic_internal.h"
+#include "pic_math.h"
 
 namespace pic {
 namespace {
-
-// ---------------------------------------------------------------------------
-// Order-1 1/2 alternating form factor of one axis (Section 4.5): with
-// i = floor(x), d = x - i, node weights (1-d; d) at nodes i, i+1 and cell
-// weights ((1-d)^2/2; 3/4 - (1/2-d)^2; d^2/2) at cells i-1, i, i+1.
-// ---------------------------------------------------------------------------
-template <class R>
-struct Axis {
-    R f[2];
-    R s[3];
-};
-
-template <class R>
-__device__ __forceinline__ Axis<R> form_factor(R d)
-{
-    Axis<R> a;
-    const R e = R(1) - d;
-    const R h = R(0.5) - d;
-    a.f[0] = e;
-    a.f[1] = d;
-    a.s[0] = R(0.5) * e * e;
-    a.s[1] = R(0.75) - h * h;
-    a.s[2] = R(0.5) * d * d;
-    return a;
-}
-
-// Cell weights only (the end point of the move).
-template <class R>
-__device__ __forceinline__ void cell_weights(R d, R s[3])
-{
-    const R e = R(1) - d;
-    const R h = R(0.5) - d;
-    s[0] = R(0.5) * e * e;
-    s[1] = R(0.75) - h * h;
-    s[2] = R(0.5) * d * d;
-}
-
-// ---------------------------------------------------------------------------
-// Gather (Eqs. alphax, betax).  F(comp, a, b, c) returns the grid value of
-// component comp (0..2 = Ex..Ez, 3..5 = Bx..Bz) at offset (a, b, c) from the
-// particle cell (a, b, c in {-1, 0, 1}; node factors use 0, 1).
-// ---------------------------------------------------------------------------
-template <class R, class Acc>
-__device__ __forceinline__ void gather3(const Axis<R> (&w)[3], Acc F, R E[3], R B[3])
-{
-    const Axis<R>& X = w[0];
-    const Axis<R>& Y = w[1];
-    const Axis<R>& Z = w[2];
-    // E^x: f_x(node) S_y S_z
-    {
-        R acc = 0;
-        for (int a = 0; a < 2; ++a) {
-            R sa = 0;
-            for (int b = -1; b <= 1; ++b) {
-                R sb = 0;
-                for (int c = -1; c <= 1; ++c) sb += Z.s[c + 1] * F(0, a, b, c);
-                sa += Y.s[b + 1] * sb;
-            }
-            acc += X.f[a] * sa;
-        }
-        E[0] = acc;
-    }
-    // E^y: S_x f_y S_z
-    {
-        R acc = 0;
-        for (int a = -1; a <= 1; ++a) {
-            R sa = 0;
-            for (int b = 0; b < 2; ++b) {
-                R sb = 0;
-                for (int c = -1; c <= 1; ++c) sb += Z.s[c + 1] * F(1, a, b, c);
-                sa += Y.f[b] * sb;
-            }
-            acc += X.s[a + 1] * sa;
-        }
-        E[1] = acc;
-    }
-    // E^z: S_x S_y f_z
-    {
-        R acc = 0;
-        for (int a = -1; a <= 1; ++a) {
-            R sa = 0;
-            for (int b = -1; b <= 1; ++b) {
-                R sb = Z.f[0] * F(2, a, b, 0) + Z.f[1] * F(2, a, b, 1);
-                sa += Y.s[b + 1] * sb;
-            }
-            acc += X.s[a + 1] * sa;
-        }
-        E[2] = acc;
-    }
-    // B^x: S_x f_y f_z
-    {
-        R acc = 0;
-        for (int a = -1; a <= 1; ++a) {
-            R sa = 0;
-            for (int b = 0; b < 2; ++b) {
-                R sb = Z.f[0] * F(3, a, b, 0) + Z.f[1] * F(3, a, b, 1);
-                sa += Y.f[b] * sb;
-            }
-            acc += X.s[a + 1] * sa;
-        }
-        B[0] = acc;
-    }
-    // B^y: f_x S_y f_z
-    {
-        R acc = 0;
-        for (int a = 0; a < 2; ++a) {
-            R sa = 0;
-            for (int b = -1; b <= 1; ++b) {
-                R sb = Z.f[0] * F(4, a, b, 0) + Z.f[1] * F(4, a, b, 1);
-                sa += Y.s[b + 1] * sb;
-            }
-            acc += X.f[a] * sa;
-        }
-        B[1] = acc;
-    }
-    // B^z: f_x f_y S_z
-    {
-        R acc = 0;
-        for (int a = 0; a < 2; ++a) {
-            R sa = 0;
-            for (int b = 0; b < 2; ++b) {
-                R sb = 0;
-                for (int c = -1; c <= 1; ++c) sb += Z.s[c + 1] * F(5, a, b, c);
-                sa += Y.f[b] * sb;
-            }
-            acc += X.f[a] * sa;
-        }
-        B[2] = acc;
-    }
-}
-
-// 2D3V: nothing depends on z, so every z sum of a partition of unity is 1.
-template <class R, class Acc>
-__device__ __forceinline__ void gather2(const Axis<R> (&w)[3], Acc F, R E[3], R B[3])
-{
-    const Axis<R>& X = w[0];
-    const Axis<R>& Y = w[1];
-    R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
-    for (int a = 0; a < 2; ++a) {
-        R s = 0;
-        for (int b = -1; b <= 1; ++b) s += Y.s[b + 1] * F(0, a, b, 0);
-        ex += X.f[a] * s;
-    }
-    for (int a = -1; a <= 1; ++a) {
-        ey += X.s[a + 1] * (Y.f[0] * F(1, a, 0, 0) + Y.f[1] * F(1, a, 1, 0));
-        R s = 0;
-        for (int b = -1; b <= 1; ++b) s += Y.s[b + 1] * F(2, a, b, 0);
-        ez += X.s[a + 1] * s;
-        bx += X.s[a + 1] * (Y.f[0] * F(3, a, 0, 0) + Y.f[1] * F(3, a, 1, 0));
-    }
-    for (int a = 0; a < 2; ++a) {
-        R s = 0;
-        for (int b = -1; b <= 1; ++b) s += Y.s[b + 1] * F(4, a, b, 0);
-        by += X.f[a] * s;
-        bz += X.f[a] * (Y.f[0] * F(5, a, 0, 0) + Y.f[1] * F(5, a, 1, 0));
-    }
-    E[0] = ex;
-    E[1] = ey;
-    E[2] = ez;
-    B[0] = bx;
-    B[1] = by;
-    B[2] = bz;
-}
-
-// ---------------------------------------------------------------------------
-// Momentum advance (Appendix): e = q dt E/(2m); w~ = w + e;
-// b = q dt B / (2 m sqrt(w~^2 + c^2)); w' = w~ + w~ x b;
-// w_new = w~ + e + 2 (w' x b)/(1 + b^2).
-// ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ void push(R qmdt2, R c2, const R E[3], const R B[3], R w[3])
-{
-    R e[3], wt[3], b[3];
-    for (int a = 0; a < 3; ++a) e[a] = qmdt2 * E[a];
-    for (int a = 0; a < 3; ++a) wt[a] = w[a] + e[a];
-    const R g = sqrt(wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2] + c2);
-    const R k = qmdt2 / g;
-    for (int a = 0; a < 3; ++a) b[a] = k * B[a];
-    const R wp0 = wt[0] + (wt[1] * b[2] - wt[2] * b[1]);
-    const R wp1 = wt[1] + (wt[2] * b[0] - wt[0] * b[2]);
-    const R wp2 = wt[2] + (wt[0] * b[1] - wt[1] * b[0]);
-    const R s = R(2) / (R(1) + b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-    w[0] = wt[0] + e[0] + s * (wp1 * b[2] - wp2 * b[1]);
-    w[1] = wt[1] + e[1] + s * (wp2 * b[0] - wp0 * b[2]);
-    w[2] = wt[2] + e[2] + s * (wp0 * b[1] - wp1 * b[0]);
-}
-
-// ---------------------------------------------------------------------------
-// Current of one particle (Eq. current, one-quarter form).  Per axis the
-// start and end cell weights are placed on a common window of 4 cells
-// starting at s = min(i0, i1) - 1; dm = S1 - S0, dp = S1 + S0 on the window;
-// the cumulative difference at face s+t+1 is P_t = sum_{t' <= t} dm_t'
-// (t = 0..2; the face s+4 gets sum of all dm = 0).  The last prefix is taken
-// as -dm_3, which is the same value and exactly zero whenever the window's
-// last cell is empty.
-// ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ void window(const R s0[3], const R s1[3], int delta, R dm[4], R dp[4])
-{
-    const bool o0 = delta < 0;  // start weights shifted one cell right in the window
-    const bool o1 = delta > 0;  // end weights shifted one cell right
-    const R a0 = o0 ? R(0) : s0[0], a1 = o0 ? s0[0] : s0[1], a2 = o0 ? s0[1] : s0[2],
-            a3 = o0 ? s0[2] : R(0);
-    const R b0 = o1 ? R(0) : s1[0], b1 = o1 ? s1[0] : s1[1], b2 = o1 ? s1[1] : s1[2],
-            b3 = o1 ? s1[2] : R(0);
-    dm[0] = b0 - a0;
-    dm[1] = b1 - a1;
-    dm[2] = b2 - a2;
-    dm[3] = b3 - a3;
-    dp[0] = b0 + a0;
-    dp[1] = b1 + a1;
-    dp[2] = b2 + a2;
-    dp[3] = b3 + a3;
-}
-
-// Sink(comp, ix, iy, iz, v) adds v to component comp at window position
-// (ix, iy, iz), each in 0..3 (window cells s..s+3; the face s+t+1 of the
-// component's own axis is position t+1).
-template <class R, class Sink>
-__device__ __forceinline__ void deposit3(const R (&dm)[3][4], const R (&dp)[3][4],
-                                         const R jfac[3], Sink S)
-{
-    const R third = R(1) / R(3);
-    R m3[3][4];
-    for (int a = 0; a < 3; ++a)
-        for (int t = 0; t < 4; ++t) m3[a][t] = dm[a][t] * third;
-    for (int comp = 0; comp < 3; ++comp) {
-        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
-        R P[3];
-        P[0] = dm[comp][0];
-        P[1] = dm[comp][0] + dm[comp][1];
-        P[2] = -dm[comp][3];
-        for (int t = 0; t < 3; ++t) P[t] *= jfac[comp];
-        for (int b = 0; b < 4; ++b)
-            for (int c = 0; c < 4; ++c) {
-                const R tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
-                for (int t = 0; t < 3; ++t) {
-                    int ijk[3];
-                    ijk[comp] = t + 1;
-                    ijk[u] = b;
-                    ijk[v] = c;
-                    S(comp, ijk[0], ijk[1], ijk[2], P[t] * tr);
-                }
-            }
-    }
-}
-
-// A particle that stays in its cell (shift 0 on every axis) has start and end
-// weights on the same three cells per axis, so the window's fourth cell and
-// the face s+3 carry exactly zero: only faces s+1, s+2 and cells s..s+2 remain,
-// 2 x 3 x 3 = 18 contributions per component.  The values are those of
-// deposit3 on the same window.
-template <class R, class Sink>
-__device__ __forceinline__ void deposit3_still(const R (&s0)[3][3], const R (&s1)[3][3],
-                                               const R jfac[3], Sink S)
-{
-    const R third = R(1) / R(3);
-    R dm[3][3], dp[3][3], m3[3][3];
-    for (int a = 0; a < 3; ++a)
-        for (int k = 0; k < 3; ++k) {
-            dm[a][k] = s1[a][k] - s0[a][k];
-            dp[a][k] = s1[a][k] + s0[a][k];
-            m3[a][k] = dm[a][k] * third;
-        }
-    for (int comp = 0; comp < 3; ++comp) {
-        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
-        const R P0 = dm[comp][0] * jfac[comp];
-        const R P1 = (dm[comp][0] + dm[comp][1]) * jfac[comp];
-        for (int b = 0; b < 3; ++b)
-            for (int c = 0; c < 3; ++c) {
-                const R tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
-                int ijk[3];
-                ijk[u] = b;
-                ijk[v] = c;
-                ijk[comp] = 1;
-                S(comp, ijk[0], ijk[1], ijk[2], P0 * tr);
-                ijk[comp] = 2;
-                S(comp, ijk[0], ijk[1], ijk[2], P1 * tr);
-            }
-    }
-}
-
-// A particle that crosses a cell face along axis A only (shift 0 on the other
-// two axes): on those axes the window's fourth cell and the face s+3 carry
-// exactly zero, leaving 3 x 3 x 3 contributions for the component along A and
-// 2 x 4 x 3 for each other component (75 in all).  The values are those of
-// deposit3 on the same window.
-template <int A, class R, class Sink>
-__device__ __forceinline__ void deposit3_axis(const R (&dm)[3][4], const R (&dp)[3][4], const R jfac[3],
-                                              Sink S)
-{
-    const R third = R(1) / R(3);
-    for (int comp = 0; comp < 3; ++comp) {
-        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
-        const int nt = comp == A ? 3 : 2;
-        const int nb = u == A ? 4 : 3, nc = v == A ? 4 : 3;
-        R P[3];
-        P[0] = dm[comp][0];
-        P[1] = dm[comp][0] + dm[comp][1];
-        P[2] = -dm[comp][3];
-        for (int t = 0; t < 3; ++t) P[t] *= jfac[comp];
-        for (int b = 0; b < nb; ++b)
-            for (int c = 0; c < nc; ++c) {
-                const R tr = dp[u][b] * dp[v][c] + (dm[u][b] * third) * dm[v][c];
-                for (int t = 0; t < nt; ++t) {
-                    int ijk[3];
-                    ijk[comp] = t + 1;
-                    ijk[u] = b;
-                    ijk[v] = c;
-                    S(comp, ijk[0], ijk[1], ijk[2], P[t] * tr);
-                }
-            }
-    }
-}
-
-// 2D3V: the z sums collapse (sum of dp_z = 2, sum of dm_z = 0, sum over the
-// z faces of P_z = z0 - z1), leaving 12 + 12 + 16 contributions.  jz is the
-// J^z factor per unit transverse weight: (q/V) u_z / 4.
-template <class R, class Sink>
-__device__ __forceinline__ void deposit2(const R (&dm)[3][4], const R (&dp)[3][4],
-                                         const R jfac[3], R jz, Sink S)
-{
-    const R third = R(1) / R(3);
-    for (int comp = 0; comp < 2; ++comp) {
-        const int u = 1 - comp;
-        R P[3];
-        P[0] = dm[comp][0];
-        P[1] = dm[comp][0] + dm[comp][1];
-        P[2] = -dm[comp][3];
-        for (int t = 0; t < 3; ++t) P[t] *= R(2) * jfac[comp];
-        for (int b = 0; b < 4; ++b)
-            for (int t = 0; t < 3; ++t) {
-                int ij[2];
-                ij[comp] = t + 1;
-                ij[u] = b;
-                S(comp, ij[0], ij[1], 0, P[t] * dp[u][b]);
-            }
-    }
-    for (int a = 0; a < 4; ++a) {
-        const R mx = dm[0][a] * third;
-        for (int b = 0; b < 4; ++b) S(2, a, b, 0, jz * (dp[0][a] * dp[1][b] + mx * dm[1][b]));
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Particle representations.
-// ---------------------------------------------------------------------------
-struct StepArgs {
-    void* pos[3];
-    void* mom[3];
-    const void* weight;
-    uint32_t* cell;
-    const int64_t* tile_start;
-    double q;        // charge per unit weight
-    double qm;       // q / m
-    unsigned long long* counters;
-    // queue of the tile's cell-crossing particles, kept in the spare copy of
-    // the particle arrays (idle between sorts) at the tile's own index range:
-    // start offsets qd0[a] and one packed word per entry
-    void* qd0[3];
-    int64_t* qword;
-    // 3D: class queue of the tile's particles (32-bit slot offsets), in the
-    // spare copy's first two momentum arrays, and the class map of the
-    // crossing queue (32-bit entry offsets), in its weight array
-    void* qdisp;
-    void* qmap;
-    void* qdisp2;
-    void* qother;  // the particles pass 1 could not class-queue, in the third momentum array
-};
-
-__device__ __forceinline__ int wrapi(int v, int n)
-{
-    int r = v % n;
-    return r < 0 ? r + n : r;
-}
-
-// Periodic wrap of v in [-n, 2n): one compare-and-add instead of a modulo.
-__device__ __forceinline__ int wrap1(int v, int n)
-{
-    v = v < 0 ? v + n : v;
-    return v >= n ? v - n : v;
-}
-
-__device__ __forceinline__ uint32_t pack_cell(int i, int j, int k)
-{
-    return (uint32_t)i | ((uint32_t)j << 11) | ((uint32_t)k << 22);
-}
-
-__device__ __forceinline__ void unpack_cell(uint32_t c, int i[3])
-{
-    i[0] = (int)(c & 2047u);
-    i[1] = (int)((c >> 11) & 2047u);
-    i[2] = (int)(c >> 22);
-}
-
-// Load the start state: cell index i[a], offset d[a] in [0,1).
-template <class R, int D>
-struct PosIO;
-
-template <int D>
-struct PosIO<double, D> {
-    static __device__ __forceinline__ void cell(const StepArgs& a, int64_t p, int i[3])
-    {
-        for (int ax = 0; ax < 3; ++ax) i[ax] = ax < D ? (int)floor(((const double*)a.pos[ax])[p]) : 0;
-    }
-    static __device__ __forceinline__ void load(const StepArgs& a, int64_t p, int i[3], double d[3])
-    {
-        for (int ax = 0; ax < D; ++ax) {
-            const double x = ((const double*)a.pos[ax])[p];
-            const double fl = floor(x);
-            i[ax] = (int)fl;
-            d[ax] = x - fl;
-        }
-        if (D == 2) {
-            i[2] = 0;
-            d[2] = 0.0;
-        }
-    }
-    // Advance by disp (cell units), wrap, store; return the end offsets d1 and
-    // the cell shift delta in {-1, 0, 1} consistent with the stored position.
-    static __device__ __forceinline__ void move(const StepArgs& a, int64_t p, const GridK& g,
-                                                const int i0[3], const double d0[3],
-                                                const double disp[3], double d1[3], int delta[3],
-                                                bool store)
-    {
-        for (int ax = 0; ax < D; ++ax) {
-            const double N = (double)g.n[ax];
-            double x = ((double)i0[ax] + d0[ax]) + disp[ax];
-            if (x >= N) x -= N;
-            if (x < 0.0) x += N;
-            if (x >= N) x -= N;  // a tiny negative value can round up to N
-            const double fl = floor(x);
-            d1[ax] = x - fl;
-            // in {-1, 0, 1} for any finite move shorter than a cell; the clamp
-            // keeps window indices in range for non-finite input
-            const double dd = rint((d0[ax] + disp[ax]) - d1[ax]);
-            delta[ax] = dd > 0.5 ? 1 : (dd < -0.5 ? -1 : 0);
-            if (store) ((double*)a.pos[ax])[p] = x;
-        }
-    }
-};
-
-template <int D>
-struct PosIO<float, D> {
-    static __device__ __forceinline__ void cell(const StepArgs& a, int64_t p, int i[3]) { unpack_cell(a.cell[p], i); }
-    static __device__ __forceinline__ void load(const StepArgs& a, int64_t p, int i[3], float d[3])
-    {
-        unpack_cell(a.cell[p], i);
-        for (int ax = 0; ax < D; ++ax) d[ax] = ((const float*)a.pos[ax])[p];
-        if (D == 2) d[2] = 0.0f;
-    }
-    static __device__ __forceinline__ void move(const StepArgs& a, int64_t p, const GridK& g,
-                                                const int i0[3], const float d0[3],
-                                                const float disp[3], float d1[3], int delta[3],
-                                                bool store)
-    {
-        int i1[3] = {i0[0], i0[1], i0[2]};
-        for (int ax = 0; ax < D; ++ax) {
-            float o = d0[ax] + disp[ax];
-            int dl = 0;
-            if (o >= 1.0f) {
-                o -= 1.0f;  // exact: o is in [1, 2)
-                dl = 1;
-            } else if (o < 0.0f) {
-                o += 1.0f;
-                dl = -1;
-                if (o >= 1.0f) {  // |o| below half an ulp of 1: the position is the node
-                    o = 0.0f;
-                    dl = 0;
-                }
-            }
-            d1[ax] = o;
-            delta[ax] = dl;
-            int c = i0[ax] + dl;
-            c = c < 0 ? c + g.n[ax] : (c >= g.n[ax] ? c - g.n[ax] : c);
-            i1[ax] = c;
-            if (store) ((float*)a.pos[ax])[p] = o;
-        }
-        if (store) a.cell[p] = pack_cell(i1[0], i1[1], i1[2]);
-    }
-};
 
 // ---------------------------------------------------------------------------
 // LDS current storage.  Both precisions accumulate in FP64: an FP32

@@ -111,6 +111,7 @@ struct Ctx {
     uint32_t* scan_part = nullptr;
     double* red = nullptr;      // reduction partials
     double* bn = nullptr;       // B^n of the current step (3 planes), read by the particles
+    double* adj = nullptr;      // adjoint scratch (3 planes): lambda_J of a reverse step
     unsigned long long* counters = nullptr;  // [0] range errors, [1] fallback particles,
                                              // [2] particles processed
     uint32_t nkeys = 0;
@@ -141,5 +142,8 @@ hipError_t launch_rho_raw(const Ctx& c, const double* x, const double* weight, d
 hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s);
 hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
+hipError_t launch_adjoint_seed(const Ctx& c, double* lam, hipStream_t s);
+hipError_t launch_adjoint_step(const Ctx& c, double* lam, double* const* lam_x, double* const* lam_w,
+                               double* lam_bext, hipStream_t s);
 
 }  // namespace pic

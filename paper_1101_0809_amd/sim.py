@@ -240,6 +240,52 @@ class Sim:
         sim._check(sim.lib.pic_set_host_state(sim.ctx, ctypes.byref(hs)))
         return sim
 
+    # -- adjoint ---------------------------------------------------------
+    def snapshot(self) -> dict:
+        """Device copies of the caller buffers and the host state, for
+        restore() on this same context (no host round trip)."""
+        hs = L.HostState()
+        self._check(self.lib.pic_get_host_state(self.ctx, ctypes.byref(hs)))
+        return {"fields": self.fields_t.clone(), "workspace": self.workspace.clone(),
+                "buffers": [None if s.buffer is None else s.buffer.clone() for s in self.species],
+                "host": hs}
+
+    def restore(self, snap: dict):
+        """Put the context back into the state snapshot() recorded."""
+        self.fields_t.copy_(snap["fields"])
+        self.workspace.copy_(snap["workspace"])
+        for s, b in zip(self.species, snap["buffers"]):
+            if b is not None:
+                s.buffer.copy_(b)
+        hs = L.HostState.from_buffer_copy(snap["host"])
+        self._check(self.lib.pic_set_host_state(self.ctx, ctypes.byref(hs)))
+
+    def adjoint_seed_field_energy(self, lam_fields: torch.Tensor):
+        """Write d(field energy)/d(E^n, B^{n-1/2}) into lam_fields (6 N FP64)."""
+        assert lam_fields.dtype == torch.float64 and lam_fields.numel() == 6 * self.ncell
+        self._check(self.lib.pic_adjoint_seed_field_energy(
+            self.ctx, ctypes.c_void_p(lam_fields.data_ptr()), _stream()))
+
+    def adjoint_step(self, lam_fields: torch.Tensor, lam_x: list, lam_w: list, lam_bext: torch.Tensor):
+        """One reverse step (include/pic.h): the context holds the state the
+        step was taken from; lam_* hold the adjoint of the state after it and
+        are replaced by the adjoint of the state before it.  lam_x[s] and
+        lam_w[s] are (3, count) FP64 device tensors in particle-id order (None
+        for immobile species); lam_bext (3,) accumulates dL/dB_ext."""
+        nsp = len(self.species)
+        px = (ctypes.c_void_p * nsp)()
+        pw = (ctypes.c_void_p * nsp)()
+        for i, s in enumerate(self.species):
+            if s.mobile:
+                n = self.count(i)
+                for t in (lam_x[i], lam_w[i]):
+                    assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == 3 * n
+                px[i], pw[i] = lam_x[i].data_ptr(), lam_w[i].data_ptr()
+        assert lam_fields.numel() == 6 * self.ncell and lam_bext.numel() == 3
+        self._check(self.lib.pic_adjoint_step(
+            self.ctx, ctypes.c_void_p(lam_fields.data_ptr()), px, pw,
+            ctypes.c_void_p(lam_bext.data_ptr()), _stream()))
+
     # -- fields ----------------------------------------------------------
     def aux_line(self) -> np.ndarray:
         """The source's auxiliary line (E^y then B^z, PIC_AUX each) from the workspace."""

@@ -162,6 +162,24 @@ def random_moves(n: int, seed: int, box=(16, 16, 16), max_step=0.9):
     return x0, x0 + dx
 
 
+def beams(box, n: int, seed: int, w_th: float = 0.1, drift: float = 0.0, dims: int = 3):
+    """Small differentiable test plasma: n electrons at uniform random
+    positions in box = (nx, ny, nz), Gaussian momenta of spread w_th per axis,
+    +drift / -drift along x on the two halves, weights giving
+    omega_pe = w_th at the mean density.  dims == 2 puts every particle on
+    z = 0.  Returns (x, w, weight)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.stack([rng.uniform(0, box[a], n) for a in range(3)])
+    w = rng.normal(0.0, w_th, (3, n))
+    w[0, : n // 2] += drift
+    w[0, n // 2:] -= drift
+    ppc = n / (box[0] * box[1] * box[2])
+    weight = np.full(n, w_th ** 2 / (4 * math.pi * ppc))
+    if dims == 2:
+        x[2] = 0.0
+    return x, w, weight
+
+
 def device_chunks(wl: Workload, device, chunk: int = 1 << 26, ions: bool = False):
     """Yield (x, w, weight) torch float64 tensors on ``device`` covering the
     whole species in chunks of ``chunk`` particles, drawn with

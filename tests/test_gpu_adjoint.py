@@ -1,0 +1,194 @@
+"""GPU adjoint (pic_adjoint_seed_field_energy, pic_adjoint_step) against the
+reference gradient of oracle/adjoint.py (torch autograd through a CPU FP64
+restatement of the step, itself pinned to the C oracle and to its central
+differences).
+
+Tolerance.  The GPU forward agrees with the oracle to ~1e-15 relative per
+step; the adjoint evaluates the same derivatives in another order (forward-
+mode dual numbers per particle against reverse-mode autograd), so each
+gradient component is compared with a bar of 1e-9 of the largest component
+of its array, far above rounding and far below any dropped or mis-signed
+term (those move components by O(1) of the scale).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle.adjoint as ad
+import picgen
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _gpu_grad(box, dims, dt, x, w, weight, bext, steps, every, sort_every=3, ions=False):
+    from paper_1101_0809_amd import Sim
+    from paper_1101_0809_amd.adjoint import field_energy_grad
+    sim = Sim(nx=box[0], ny=box[1], nz=box[2], dt=dt, dims=dims, sort_every=sort_every, bext=bext)
+    sim.add_species(-1.0, 1.0, capacity=weight.size)
+    sim.load(0, x, w, weight)
+    if ions:
+        sim.add_species(1.0, 1836.0, capacity=weight.size, mobile=False)
+        sim.load(1, x, np.zeros_like(w), weight)
+    L, gx, gw, gb = field_energy_grad(sim, steps, every=every)
+    torch.cuda.synchronize()
+    out = (L, gx[0].cpu().numpy(), gw[0].cpu().numpy(), gb.cpu().numpy())
+    sim.close()
+    return out
+
+
+def _close(a, b, tol=TOL):
+    scale = np.max(np.abs(b))
+    err = np.max(np.abs(a - b))
+    assert err <= tol * scale, (err, scale)
+
+
+def _fields(shape, seed, amp):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = np.zeros((9,) + shape)
+    f[:6] = rng.normal(0.0, amp, (6,) + shape)
+    return f
+
+
+def test_seed_matches_reference():
+    """pic_adjoint_seed_field_energy on random fields (ragged 11 x 7 x 5)."""
+    from paper_1101_0809_amd import Sim
+    nx, ny, nz = 11, 7, 5
+    f = _fields((nz, ny, nx), 71, 0.3)
+    sim = Sim(nx=nx, ny=ny, nz=nz, dt=0.45, dims=3, fields=f)
+    lam = torch.empty(6 * sim.ncell, dtype=torch.float64, device="cuda:0")
+    sim.adjoint_seed_field_energy(lam)
+    got = lam.cpu().numpy().reshape(6, nz, ny, nx)
+    gE, gB = ad.field_energy_grad_fields(ad.Grid(nx, ny, nz, 0.45), f[:3], f[3:6])
+    _close(got[:3], gE, 1e-13)
+    _close(got[3:], gB, 1e-13)
+    sim.close()
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_step_vjp_matches_reference(dims):
+    """One pic_adjoint_step with random adjoints, random fields and particles
+    spanning several tiles (ragged counts and grid) against the oracle's
+    one-step vector-Jacobian product; ids are permuted by a sort first."""
+    from paper_1101_0809_amd import Sim
+    box = (21, 18, 1) if dims == 2 else (10, 9, 11)
+    dt = 0.5 if dims == 2 else 0.45
+    n = 1501 if dims == 2 else 1303
+    x, w, weight = picgen.beams(box, n, 80 + dims, w_th=0.3, drift=0.2, dims=dims)
+    shape = (box[2], box[1], box[0])
+    f = _fields(shape, 90 + dims, 0.05)
+    bext = (0.03, -0.02, 0.05)
+    rng = np.random.Generator(np.random.PCG64(100 + dims))
+    lam = [rng.normal(size=(3,) + shape), rng.normal(size=(3,) + shape),
+           rng.normal(size=(3, n)), rng.normal(size=(3, n))]
+    if dims == 2:
+        lam[2][2] = 0.0
+    ref = ad.step_vjp(ad.Grid(*box, dt), f[:3], f[3:6], x, w, weight, -1.0, 1.0, bext, *lam)
+    sim = Sim(nx=box[0], ny=box[1], nz=box[2], dt=dt, dims=dims, bext=bext, fields=f)
+    sim.add_species(-1.0, 1.0, capacity=n)
+    sim.load(0, x, w, weight)
+    sim.sort()
+    dev = torch.device("cuda:0")
+    lf = torch.tensor(np.concatenate([lam[0], lam[1]]).reshape(-1), device=dev)
+    lx = torch.tensor(lam[2], device=dev)
+    lw = torch.tensor(lam[3], device=dev)
+    lb = torch.zeros(3, dtype=torch.float64, device=dev)
+    sim.adjoint_step(lf, [lx], [lw], lb)
+    got = lf.cpu().numpy().reshape((6,) + shape)
+    _close(got[:3], ref[0], 1e-12)
+    _close(got[3:], ref[1], 1e-12)
+    _close(lx.cpu().numpy()[:dims], ref[2][:dims], 1e-12)
+    _close(lw.cpu().numpy(), ref[3], 1e-12)
+    _close(lb.cpu().numpy(), ref[4], 1e-12)
+    sim.close()
+
+
+CASES = {
+    # 2D3V beams in B_z, several sorts and checkpoint segments
+    "2d_8x8": dict(box=(8, 8, 1), dims=2, dt=0.5, n=64, seed=17, w_th=0.05, drift=0.2,
+                   bext=(0.0, 0.0, 0.05), steps=10, every=4),
+    # 3D with every component of B_ext non-zero
+    "3d_6x5x4": dict(box=(6, 5, 4), dims=3, dt=0.45, n=48, seed=8, w_th=0.2, drift=0.0,
+                     bext=(0.02, -0.03, 0.05), steps=8, every=3),
+    # several 8x8 tiles and a ragged tail of particles
+    "2d_32x24": dict(box=(32, 24, 1), dims=2, dt=0.5, n=3001, seed=21, w_th=0.1, drift=0.15,
+                     bext=(0.01, 0.0, 0.08), steps=12, every=5),
+    "3d_12x10x9": dict(box=(12, 10, 9), dims=3, dt=0.45, n=2161, seed=22, w_th=0.1, drift=0.1,
+                       bext=(0.0, 0.04, 0.02), steps=6, every=4),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_matches_reference_gradient(name):
+    c = CASES[name]
+    x, w, weight = picgen.beams(c["box"], c["n"], c["seed"], w_th=c["w_th"], drift=c["drift"],
+                                dims=c["dims"])
+    g = ad.Grid(*c["box"], c["dt"])
+    L_ref, gw_ref, gb_ref, gx_ref = ad.loss_and_grad(g, x, w, weight, -1.0, 1.0, c["bext"], c["steps"])
+    L, gx, gw, gb = _gpu_grad(c["box"], c["dims"], c["dt"], x, w, weight, c["bext"], c["steps"],
+                              c["every"])
+    assert abs(L - L_ref) <= 1e-12 * L_ref
+    _close(gw, gw_ref)
+    _close(gx[: c["dims"]], gx_ref[: c["dims"]])
+    if c["dims"] == 2:
+        assert np.max(np.abs(gx[2])) == 0.0
+    _close(gb, gb_ref)
+
+
+def test_adjoint_with_immobile_ions_and_checkpoint_spacing():
+    """An immobile neutralising species adds charge but no adjoint; the
+    gradient does not depend on the checkpoint spacing (one copy per step vs
+    one for the whole run)."""
+    c = CASES["2d_8x8"]
+    x, w, weight = picgen.beams(c["box"], c["n"], c["seed"], w_th=c["w_th"], drift=c["drift"], dims=2)
+    g = ad.Grid(*c["box"], c["dt"])
+    ref = ad.loss_and_grad(g, x, w, weight, -1.0, 1.0, c["bext"], c["steps"])
+    a = _gpu_grad(c["box"], 2, c["dt"], x, w, weight, c["bext"], c["steps"], every=1, ions=True)
+    b = _gpu_grad(c["box"], 2, c["dt"], x, w, weight, c["bext"], c["steps"], every=100, ions=True,
+                  sort_every=0)
+    for got in (a, b):
+        assert abs(got[0] - ref[0]) <= 1e-12 * ref[0]
+        _close(got[2], ref[1])
+        _close(got[3], ref[2])
+        _close(got[1][:2], ref[3][:2])
+
+
+def test_autograd_function_and_central_difference_of_gpu_forward():
+    """torch.autograd through paper_1101_0809_amd.adjoint.field_energy gives
+    the driver's gradient; dL/dB_ext,z matches central differences of the
+    GPU forward itself."""
+    from paper_1101_0809_amd.adjoint import field_energy
+    c = CASES["2d_8x8"]
+    x, w, weight = picgen.beams(c["box"], c["n"], c["seed"], w_th=c["w_th"], drift=c["drift"], dims=2)
+    grid = dict(nx=8, ny=8, nz=1, dt=c["dt"], dims=2, sort_every=3)
+    dev = torch.device("cuda:0")
+    xt = torch.tensor(x, device=dev, requires_grad=True)
+    wt = torch.tensor(w, device=dev, requires_grad=True)
+    bt = torch.tensor(c["bext"], dtype=torch.float64, requires_grad=True)
+    L = field_energy(xt, wt, torch.tensor(weight, device=dev), bt, grid, c["steps"], every=4)
+    gx, gw, gb = torch.autograd.grad(3.0 * L, (xt, wt, bt))
+    L0, gx0, gw0, gb0 = _gpu_grad(c["box"], 2, c["dt"], x, w, weight, c["bext"], c["steps"], 4)
+    assert abs(float(L) - L0) <= 1e-13 * L0
+    _close(gw.cpu().numpy(), 3.0 * gw0)
+    _close(gx.cpu().numpy()[:2], 3.0 * gx0[:2])
+    _close(gb.numpy(), 3.0 * gb0)
+    h = 1e-6
+    Lp = float(field_energy(xt.detach(), wt.detach(), torch.tensor(weight, device=dev),
+                            bt.detach() + torch.tensor([0.0, 0.0, h], dtype=torch.float64),
+                            grid, c["steps"]))
+    Lm = float(field_energy(xt.detach(), wt.detach(), torch.tensor(weight, device=dev),
+                            bt.detach() - torch.tensor([0.0, 0.0, h], dtype=torch.float64),
+                            grid, c["steps"]))
+    fd = (Lp - Lm) / (2 * h)
+    assert abs(gb0[2] - fd) <= 1e-6 * abs(fd), (gb0[2], fd)
+
+
+def test_adjoint_rejects_fp32_mode():
+    from paper_1101_0809_amd import Sim
+    from paper_1101_0809_amd._lib import PicError
+    sim = Sim(nx=8, ny=8, nz=1, dt=0.5, dims=2, precision="fp32c")
+    lam = torch.zeros(6 * 64, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(PicError):
+        sim.adjoint_seed_field_energy(lam)
+    sim.close()
