@@ -87,6 +87,97 @@ def run_gpu(wl, precision: str, steps: int, warmup: int):
             "fallback": fallback}
 
 
+def adjoint_bytes(dims: int):
+    """Algorithmic HBM bytes of one reverse step (FP64): per particle, the state
+    read once (x 8*dims, w 24, weight 8, id 8) and its adjoint read and written
+    once (dL/dx 8*dims read, 24 written; dL/dw 24 + 24); per cell, the grid
+    planes each of the five kernels must touch: B^n from E, B (6 read, 3
+    written), lambda_J and lambda_B from lambda_E' (3 read, 3 + 3 read-write
+    for lambda_B, 3 written), two curl passes (3 read, 3 read-write each), the
+    particle pass (E, B^n, lambda_J read; lambda_E, lambda_B read-write)."""
+    per_particle = 8 * dims + 24 + 8 + 8 + (8 * dims + 24) + (24 + 24)
+    per_cell = 8 * (9 + 12 + 2 * 9 + 21)
+    return per_particle, per_cell
+
+
+def run_adjoint(wl, every: int):
+    """Field-energy gradient of wl (FP64): forward time of wl.steps steps, the
+    whole gradient (forward pass with its records or checkpoints, reverse
+    steps), one reverse step and one record on their own."""
+    import torch
+
+    import picgen
+    from paper_1101_0809_amd import Sim
+    from paper_1101_0809_amd.adjoint import field_energy_grad
+
+    e = picgen.electrons(wl)
+    sim = Sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=wl.dims, precision="fp64",
+              sort_every=wl.sort_every, bext=wl.bext)
+    s = sim.add_species(e.q, e.m, e.n)
+    sim.load(s, e.x, e.w, e.weight)
+    n = e.n
+    del e
+    init = sim.snapshot()
+    field_energy_grad(sim, 4, every=2)       # warm-up of every kernel and copy
+    sim.restore(init)
+    field_energy_grad(sim, 2)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+
+    sim.restore(init)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    sim.step(wl.steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = a.elapsed_time(b)
+
+    sim.restore(init)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, gx, gw, gb = field_energy_grad(sim, wl.steps, every=every)
+    torch.cuda.synchronize()
+    grad_ms = (time.perf_counter() - t0) * 1e3
+
+    # one reverse step from a record of a sorted state (as every step after
+    # the first), repeated, and the record copy alone
+    sim.restore(init)
+    sim.step(1)
+    rec = torch.empty(sim.adjoint_record_bytes(), dtype=torch.uint8, device=sim.device)
+    sim.adjoint_record(rec)
+    lam_f = torch.zeros(6 * sim.ncell, dtype=torch.float64, device=sim.device)
+    sim.adjoint_seed_field_energy(lam_f)
+    lx = [torch.zeros((3, n), dtype=torch.float64, device=sim.device)]
+    lw = [torch.zeros((3, n), dtype=torch.float64, device=sim.device)]
+    lb = torch.zeros(3, dtype=torch.float64, device=sim.device)
+    reps = 20
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    for _ in range(reps):
+        sim.adjoint_step_record(rec, lam_f, lx, lw, lb)
+    b.record(stream)
+    torch.cuda.synchronize()
+    adj_ms = a.elapsed_time(b) / reps
+    a, b = ev(), ev()
+    a.record(stream)
+    for _ in range(reps):
+        sim.adjoint_record(rec)
+    b.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = a.elapsed_time(b) / reps
+    record_bytes = rec.numel()
+    sim.close()
+    pp, pc = adjoint_bytes(wl.dims)
+    nbytes = n * pp + wl.ncell * pc
+    achieved = nbytes / (adj_ms * 1e-3) / 1e9
+    return {"n": n, "forward_ms": fwd_ms, "grad_ms": grad_ms, "adjoint_step_ms": adj_ms,
+            "record_ms": copy_ms, "record_bytes": record_bytes, "loss": L,
+            "dL_dbext": gb.cpu().tolist(),
+            "bytes_per_reverse_step": nbytes, "achieved_gbs": achieved}
+
+
 def measured_traffic(precision: str, workload: str):
     """HBM bytes per particle-kernel launch from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or
@@ -174,7 +265,45 @@ def main(argv=None):
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB (5 times), the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters to bytes")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the throughput line, time the checkpointed field-energy "
+                         "gradient of the 2D3V 256x256 beams workload (FP64) against its forward "
+                         "pass and print that as the one JSON line")
+    ap.add_argument("--every", type=int, default=None,
+                    help="checkpoint spacing of --adjoint (default: record every step when the "
+                         "tape fits in half the free device memory)")
     args = ap.parse_args(argv)
+    if args.adjoint and args.gpus == 1:
+        import picgen
+        name = args.workload if args.workload != "3d_64cube_8ppc" else "2d3v_256sq_beams"
+        wl = picgen.WORKLOADS[name]
+        r = run_adjoint(wl, args.every)
+        fwd_step = r["forward_ms"] / wl.steps
+        line = {
+            "metric": "field-energy gradient time / forward time (adjoint, FP64)",
+            "value": round(r["grad_ms"] / r["forward_ms"], 3),
+            "unit": "x forward",
+            "n_gpus": 1, "steps": wl.steps, "warmup": 4,
+            "ms_per_step": round(r["grad_ms"] / wl.steps, 5),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "particles": r["n"],
+                       "dt": wl.dt, "sort_every": wl.sort_every,
+                       "checkpoint_every": args.every or "none (tape of every step)",
+                       "bext": list(wl.bext), "parallelism": "none (1 GPU)"},
+            "forward_ms_per_step": round(fwd_step, 5),
+            "forward_particle_steps_per_s": round(r["n"] * 1e3 / fwd_step, 1),
+            "reverse_step_ms": round(r["adjoint_step_ms"], 5),
+            "record_ms": round(r["record_ms"], 5), "record_bytes": r["record_bytes"],
+            "roofline": {"bound": "hbm", "kernel": "reverse step (k_adj_* kernels)",
+                         "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                         "traffic": None, "bytes_per_launch": r["bytes_per_reverse_step"],
+                         "avg_launch_ms": round(r["adjoint_step_ms"], 5)},
+            "loss": r["loss"], "dL_dbext": r["dL_dbext"],
+        }
+        print(json.dumps(line), flush=True)
+        return 0
     if args.copy_probe:
         import torch
         n = 256 * 1024 * 1024 // 8

@@ -211,6 +211,28 @@ int pic_adjoint_seed_field_energy(pic_ctx* ctx, double* lam_fields, void* stream
 int pic_adjoint_step(pic_ctx* ctx, double* lam_fields, double* const* lam_x, double* const* lam_w,
                      double* lam_bext, void* stream);
 
+/* Records for a reverse sweep without restoring the context.  A record holds
+ * what one reverse step reads of the state a step starts from: E^n and
+ * B^{n-1/2} (6 N FP64) and, per mobile species, its particles in the
+ * library's storage order (positions, momenta, weights, ids) with the tile
+ * table of its last sort, in a layout private to the library.
+ *
+ * pic_adjoint_record_bytes: size of one record for the context's current
+ * particle counts (PIC_EINVAL on a null argument).
+ * pic_adjoint_record: copy the context's current state into record (caller-
+ * owned device memory of at least that size; PIC_ESIZE if smaller).  Taken
+ * before each pic_step(ctx, 1) of a forward pass, the records are the tape of
+ * that pass.  Asynchronous.
+ * pic_adjoint_step_record: pic_adjoint_step with the state before the step
+ * read from a record written on this context while its particle counts were
+ * what they are now; the context's fields and particles are not read (its
+ * workspace is used).  Same adjoint arguments and errors as pic_adjoint_step,
+ * plus PIC_ESIZE for a record smaller than pic_adjoint_record_bytes. */
+int pic_adjoint_record_bytes(const pic_ctx* ctx, size_t* bytes);
+int pic_adjoint_record(pic_ctx* ctx, void* record, size_t bytes, void* stream);
+int pic_adjoint_step_record(pic_ctx* ctx, const void* record, size_t bytes, double* lam_fields,
+                            double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream);
+
 /* Number of particles currently held by a species (host-side count). */
 int64_t pic_particle_count(const pic_ctx* ctx, int species);
 

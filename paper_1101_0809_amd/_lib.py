@@ -23,7 +23,8 @@ EXPORTS = (
     "pic_deposit_J", "pic_field_solve", "pic_diagnostics", "pic_particle_count",
     "pic_get_particles", "pic_sort", "pic_last_fallback_fraction", "pic_timing_start",
     "pic_timing_stop", "pic_get_host_state", "pic_set_host_state", "pic_destroy",
-    "pic_adjoint_seed_field_energy", "pic_adjoint_step",
+    "pic_adjoint_seed_field_energy", "pic_adjoint_step", "pic_adjoint_record_bytes",
+    "pic_adjoint_record", "pic_adjoint_step_record",
     "pic_last_error", "pic_version",
 )
 
@@ -111,6 +112,10 @@ def load(path: str = LIB_PATH):
         "pic_set_host_state": (I, [P, ctypes.POINTER(HostState)]),
         "pic_adjoint_seed_field_energy": (I, [P, P, P]),
         "pic_adjoint_step": (I, [P, P, ctypes.POINTER(P), ctypes.POINTER(P), P, P]),
+        "pic_adjoint_record_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "pic_adjoint_record": (I, [P, P, ctypes.c_size_t, P]),
+        "pic_adjoint_step_record": (I, [P, P, ctypes.c_size_t, P, ctypes.POINTER(P), ctypes.POINTER(P),
+                                        P, P]),
         "pic_destroy": (None, [P]),
         "pic_last_error": (ctypes.c_char_p, [P]),
         "pic_version": (ctypes.c_char_p, []),

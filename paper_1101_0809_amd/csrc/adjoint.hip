@@ -23,6 +23,8 @@
 // numbers.  The particle part adds alpha lambda_Ep into lambda_E and beta
 // lambda_Bp into lambda_B (atomics) and sums lambda_Bp into the external-field
 // gradient.
+#include <algorithm>
+
 #include "pic_math.h"
 
 namespace pic {
@@ -259,13 +261,191 @@ struct AdjArgs {
     double* lam_bext;    // 3, accumulated
 };
 
-// Add w * lam at the stencil points of one field component: per axis the node
-// weights f (offsets 0, 1) or the cell weights s (offsets -1, 0, 1); in 2D the
-// z axis is collapsed onto the single plane.
-template <int D, bool NX, bool NY, bool NZ>
-__device__ __forceinline__ void scatter_comp(double* dst, const Axis<double> (&w)[3], const int xi[3],
-                                             const int yj[3], const int64_t zk[3], double lam)
+// Reverse of the momentum advance (Appendix, Eq. p2): recompute the forward
+// intermediates, then carry lw1 = dL/dw^{n+1/2} back to dL/dw^{n-1/2} (lw0),
+// dL/dE_p (lE) and dL/dB_p (lB).  For f = m . (u x v): df/du = v x m and
+// df/dv = m x u.
+__device__ __forceinline__ void cross(const double u[3], const double v[3], double r[3])
 {
+    r[0] = u[1] * v[2] - u[2] * v[1];
+    r[1] = u[2] * v[0] - u[0] * v[2];
+    r[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+__device__ __forceinline__ void push_reverse(double qmdt2, double c2, const double E[3], const double B[3],
+                                             const double w[3], const double lw1[3], double lw0[3],
+                                             double lE[3], double lB[3])
+{
+    double e[3], wt[3], b[3], wp[3], cr[3];
+    for (int a = 0; a < 3; ++a) e[a] = qmdt2 * E[a];
+    for (int a = 0; a < 3; ++a) wt[a] = w[a] + e[a];
+    const double g = ::sqrt(wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2] + c2);
+    const double k = qmdt2 / g;
+    for (int a = 0; a < 3; ++a) b[a] = k * B[a];
+    cross(wt, b, cr);
+    for (int a = 0; a < 3; ++a) wp[a] = wt[a] + cr[a];
+    const double s = 2.0 / (1.0 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    // w1 = wt + e + s (wp x b)
+    cross(wp, b, cr);
+    const double ls = lw1[0] * cr[0] + lw1[1] * cr[1] + lw1[2] * cr[2];
+    double m[3], lwp[3], lb[3], lwt[3], t[3];
+    for (int a = 0; a < 3; ++a) m[a] = s * lw1[a];
+    cross(b, m, lwp);
+    cross(m, wp, lb);
+    for (int a = 0; a < 3; ++a) lb[a] -= s * s * ls * b[a];  // ds/db = -s^2 b
+    // wp = wt + wt x b
+    cross(b, lwp, t);
+    for (int a = 0; a < 3; ++a) lwt[a] = lw1[a] + lwp[a] + t[a];
+    cross(lwp, wt, t);
+    for (int a = 0; a < 3; ++a) lb[a] += t[a];
+    // b = (qmdt2 / g) B, g = sqrt(wt^2 + c^2)
+    const double lk = lb[0] * B[0] + lb[1] * B[1] + lb[2] * B[2];
+    const double lg = -lk * k / g;
+    for (int a = 0; a < 3; ++a) {
+        lB[a] = k * lb[a];
+        lwt[a] += lg * wt[a] / g;
+        lw0[a] = lwt[a];
+        lE[a] = qmdt2 * (lw1[a] + lwt[a]);  // e enters w1 directly and through wt
+    }
+}
+
+// Reverse of the quarter-form current (Eq. current as in deposit3 and
+// deposit2): L(comp, ix, iy, iz) returns lambda_J at a window position; the
+// derivatives of sum lambda_J J with respect to the window differences dm and
+// sums dp are added into ldm, ldp (and, in 2D, with respect to the J^z factor
+// into ljz).
+template <int D, class LJ>
+__device__ __forceinline__ void deposit_reverse(const double (&dm)[3][4], const double (&dp)[3][4],
+                                                const double jfac[3], double jz, LJ L,
+                                                double (&ldm)[3][4], double (&ldp)[3][4], double& ljz)
+{
+    const double third = 1.0 / 3.0;
+    if (D == 3) {
+        for (int comp = 0; comp < 3; ++comp) {
+            const int u = (comp + 1) % 3, v = (comp + 2) % 3;
+            const double P[3] = {dm[comp][0], dm[comp][0] + dm[comp][1], -dm[comp][3]};
+            double lP[3] = {0.0, 0.0, 0.0};
+            for (int b = 0; b < 4; ++b)
+                for (int c = 0; c < 4; ++c) {
+                    const double tr = dp[u][b] * dp[v][c] + third * dm[u][b] * dm[v][c];
+                    double ltr = 0.0;
+                    for (int t = 0; t < 3; ++t) {
+                        int ijk[3];
+                        ijk[comp] = t + 1;
+                        ijk[u] = b;
+                        ijk[v] = c;
+                        const double l = L(comp, ijk[0], ijk[1], ijk[2]);
+                        lP[t] += l * tr;
+                        ltr += l * P[t];
+                    }
+                    ltr *= jfac[comp];
+                    ldp[u][b] += ltr * dp[v][c];
+                    ldp[v][c] += ltr * dp[u][b];
+                    ldm[u][b] += third * ltr * dm[v][c];
+                    ldm[v][c] += third * ltr * dm[u][b];
+                }
+            ldm[comp][0] += jfac[comp] * (lP[0] + lP[1]);
+            ldm[comp][1] += jfac[comp] * lP[1];
+            ldm[comp][3] -= jfac[comp] * lP[2];
+        }
+    } else {
+        for (int comp = 0; comp < 2; ++comp) {
+            const int u = 1 - comp;
+            const double K = 2.0 * jfac[comp];
+            const double P[3] = {dm[comp][0], dm[comp][0] + dm[comp][1], -dm[comp][3]};
+            double lP[3] = {0.0, 0.0, 0.0};
+            for (int b = 0; b < 4; ++b) {
+                double lb = 0.0;
+                for (int t = 0; t < 3; ++t) {
+                    int ij[2];
+                    ij[comp] = t + 1;
+                    ij[u] = b;
+                    const double l = L(comp, ij[0], ij[1], 0);
+                    lP[t] += l * dp[u][b];
+                    lb += l * P[t];
+                }
+                ldp[u][b] += K * lb;
+            }
+            ldm[comp][0] += K * (lP[0] + lP[1]);
+            ldm[comp][1] += K * lP[1];
+            ldm[comp][3] -= K * lP[2];
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                const double l = L(2, a, b, 0);
+                ljz += l * (dp[0][a] * dp[1][b] + third * dm[0][a] * dm[1][b]);
+                const double lj = jz * l;
+                ldp[0][a] += lj * dp[1][b];
+                ldp[1][b] += lj * dp[0][a];
+                ldm[0][a] += third * lj * dm[1][b];
+                ldm[1][b] += third * lj * dm[0][a];
+            }
+    }
+}
+
+// d/dd of the cell weights (1/2 (1-d)^2, 3/4 - (1/2-d)^2, 1/2 d^2), contracted
+// with their adjoints.
+__device__ __forceinline__ double cell_weights_reverse(double d, const double ls[3])
+{
+    return ls[0] * (d - 1.0) + ls[1] * (1.0 - 2.0 * d) + ls[2] * d;
+}
+
+// Where a particle's reverse step reads and writes grid values.  Field
+// component comp (0..2 = E, 3..5 = B^n) at offset (da, db, dc) in {-1, 0, 1}
+// from the particle cell (F reads, add accumulates the adjoint); lambda_J at
+// window position (ix, iy, iz) in 0..3 from the window start (L).
+template <int D>
+struct GlobalAcc {
+    const GridK& g;
+    const AdjArgs& a;
+    int xi[3], yj[3], cx[4], cy[4];
+    int64_t zk[3], cz[4];
+    __device__ GlobalAcc(const GridK& g_, const AdjArgs& a_) : g(g_), a(a_) {}
+    __device__ void at(const int i0[3])
+    {
+        for (int o = 0; o < 3; ++o) {
+            xi[o] = wrapi(i0[0] + o - 1, g.n[0]);
+            yj[o] = wrapi(i0[1] + o - 1, g.n[1]) * g.n[0];
+            zk[o] = D == 3 ? (int64_t)wrapi(i0[2] + o - 1, g.n[2]) * g.n[0] * g.n[1] : 0;
+        }
+    }
+    __device__ void window(const int i0[3], const int delta[3])
+    {
+        const int sx = i0[0] + (delta[0] < 0 ? -1 : 0) - 1;
+        const int sy = i0[1] + (delta[1] < 0 ? -1 : 0) - 1;
+        const int sz = i0[2] + (delta[2] < 0 ? -1 : 0) - 1;
+        for (int o = 0; o < 4; ++o) {
+            cx[o] = wrapi(sx + o, g.n[0]);
+            cy[o] = wrapi(sy + o, g.n[1]) * g.n[0];
+            cz[o] = D == 3 ? (int64_t)wrapi(sz + o, g.n[2]) * g.n[0] * g.n[1] : 0;
+        }
+    }
+    __device__ double F(int comp, int da, int db, int dc) const
+    {
+        const int64_t cell = zk[dc + 1] + yj[db + 1] + xi[da + 1];
+        return comp < 3 ? a.E[comp * g.ncell + cell] : a.Bn[(comp - 3) * g.ncell + cell];
+    }
+    __device__ double L(int comp, int ix, int iy, int iz) const
+    {
+        return a.lamJ[comp * g.ncell + cz[iz] + cy[iy] + cx[ix]];
+    }
+    __device__ void add(int comp, int da, int db, int dc, double v) const
+    {
+        const int64_t cell = zk[dc + 1] + yj[db + 1] + xi[da + 1];
+        grid_add(comp < 3 ? &a.lamE[comp * g.ncell + cell] : &a.lamB[(comp - 3) * g.ncell + cell], v);
+    }
+};
+
+// Add w * lam at the stencil points of field component comp (Eqs. alphax,
+// betax: per axis the node weights f at offsets 0, 1 or the cell weights s
+// at -1, 0, 1; in 2D the z axis is the single plane).
+template <int D, int comp, class Acc>
+__device__ __forceinline__ void scatter_comp(Acc& acc, const Axis<double> (&w)[3], double lam)
+{
+    // node axes of each component: E^x x, E^y y, E^z z, B^x y z, B^y x z, B^z x y
+    constexpr bool NX = comp == 0 || comp == 4 || comp == 5;
+    constexpr bool NY = comp == 1 || comp == 3 || comp == 5;
+    constexpr bool NZ = comp == 2 || comp == 3 || comp == 4;
     constexpr int ZLO = D == 3 ? (NZ ? 0 : -1) : 0, ZHI = D == 3 ? 1 : 0;
     for (int c = ZLO; c <= ZHI; ++c) {
         const double wz = D == 3 ? (NZ ? w[2].f[c] : w[2].s[c + 1]) : 1.0;
@@ -273,12 +453,155 @@ __device__ __forceinline__ void scatter_comp(double* dst, const Axis<double> (&w
             const double wy = NY ? w[1].f[b] : w[1].s[b + 1];
             for (int a = NX ? 0 : -1; a <= 1; ++a) {
                 const double wx = NX ? w[0].f[a] : w[0].s[a + 1];
-                grid_add(&dst[zk[c + 1] + yj[b + 1] + xi[a + 1]], wx * wy * wz * lam);
+                acc.add(comp, a, b, c, wx * wy * wz * lam);
             }
         }
     }
 }
 
+// The particle's part of the reverse step: recompute its gather, push and
+// move, take lambda_J over its current window back to its start and end
+// offsets and new momentum, then through the push to its old momentum and the
+// fields it gathered; add those into lambda_E, lambda_B (acc) and lbp.
+template <int D, class Acc>
+__device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, Acc& acc, const int i0[3],
+                                             const double d0[3], const double w0[3], double qp, int64_t id,
+                                             double lbp[3])
+{
+    const double c = g.c, c2 = c * c;
+    acc.at(i0);
+    // gather, with the derivatives in the start offsets d0
+    using DG = Dual<D>;
+    Axis<DG> ax0[3];
+    for (int ax = 0; ax < D; ++ax) ax0[ax] = form_factor<DG>(DG::var(d0[ax], ax));
+    if (D == 2) ax0[2] = form_factor<DG>(DG(0.0));
+    auto F = [&](int comp, int da, int db, int dc) -> double { return acc.F(comp, da, db, dc); };
+    DG Eg[3], Bg[3];
+    if (D == 3) gather3<DG>(ax0, F, Eg, Bg);
+    else gather2<DG>(ax0, F, Eg, Bg);
+    double Ep[3], Bp[3];
+    for (int k = 0; k < 3; ++k) {
+        Ep[k] = Eg[k].v;
+        Bp[k] = Bg[k].v + g.bext[k];
+    }
+
+    // forward push and position advance, values only
+    const double qmdt2 = 0.5 * a.qm * g.dt;
+    double w1[3] = {w0[0], w0[1], w0[2]};
+    push<double>(qmdt2, c2, Ep, Bp, w1);
+    const double inv = 1.0 / ::sqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2] + c2);
+    double disp[3];
+    for (int ax = 0; ax < 3; ++ax) disp[ax] = w1[ax] * inv * g.cfl[ax];
+    double d1[3] = {0.0, 0.0, 0.0};
+    int delta[3] = {0, 0, 0};
+    StepArgs none{};
+    PosIO<double, D>::move(none, 0, g, i0, d0, disp, d1, delta, false);
+
+    // reverse of the current: lambda_J over the particle's window
+    double dm[3][4], dp[3][4], ldm[3][4], ldp[3][4];
+    for (int ax = 0; ax < 3; ++ax)
+        for (int t = 0; t < 4; ++t) {
+            dm[ax][t] = dp[ax][t] = 0.0;
+            ldm[ax][t] = ldp[ax][t] = 0.0;
+        }
+    for (int ax = 0; ax < D; ++ax) {
+        double s0[3], s1[3];
+        cell_weights<double>(d0[ax], s0);
+        cell_weights<double>(d1[ax], s1);
+        window<double>(s0, s1, delta[ax], dm[ax], dp[ax]);
+    }
+    double jfac[3];
+    for (int k = 0; k < 3; ++k) jfac[k] = g.jscale[k] * qp;
+    const double jzc = qp * 0.25 * g.inv_vol * c;  // J^z factor per unit u_z = w_z / gamma
+    const double jz = D == 2 ? jzc * w1[2] * inv : 0.0;
+    acc.window(i0, delta);
+    double ljz = 0.0;
+    auto L = [&](int comp, int ix, int iy, int iz) -> double { return acc.L(comp, ix, iy, iz); };
+    deposit_reverse<D>(dm, dp, jfac, jz, L, ldm, ldp, ljz);
+
+    // back through the window to the start and end offsets
+    double gd0[3] = {0.0, 0.0, 0.0}, gd1[3] = {0.0, 0.0, 0.0};
+    for (int ax = 0; ax < D; ++ax) {
+        const int o0 = delta[ax] < 0 ? 1 : 0, o1 = delta[ax] > 0 ? 1 : 0;
+        double ls0[3], ls1[3];
+        for (int k = 0; k < 3; ++k) {
+            ls0[k] = ldp[ax][k + o0] - ldm[ax][k + o0];
+            ls1[k] = ldp[ax][k + o1] + ldm[ax][k + o1];
+        }
+        gd0[ax] = cell_weights_reverse(d0[ax], ls0);
+        gd1[ax] = cell_weights_reverse(d1[ax], ls1);
+    }
+
+    // x^{n+1} = x^n + V(w^{n+1/2}): d1 = d0 + disp - delta
+    double ld1[3] = {0.0, 0.0, 0.0}, ld0[3] = {0.0, 0.0, 0.0};
+    for (int ax = 0; ax < D; ++ax) {
+        ld1[ax] = a.lam_x[ax * a.count + id] + gd1[ax];
+        ld0[ax] = gd0[ax] + ld1[ax];
+    }
+    const double inv3 = inv * inv * inv;
+    double lw1[3];
+    for (int k = 0; k < 3; ++k) {
+        lw1[k] = a.lam_w[k * a.count + id];
+        if (D == 2) lw1[k] += ljz * jzc * ((k == 2 ? inv : 0.0) - w1[2] * w1[k] * inv3);
+        for (int ax = 0; ax < D; ++ax)
+            lw1[k] += ld1[ax] * g.cfl[ax] * ((ax == k ? inv : 0.0) - w1[ax] * w1[k] * inv3);
+    }
+
+    // push
+    double lw0[3], lE[3], lB[3];
+    push_reverse(qmdt2, c2, Ep, Bp, w0, lw1, lw0, lE, lB);
+
+    // gather: offsets, and alpha lambda_Ep into lambda_E, beta lambda_Bp
+    // into lambda_B
+    for (int ax = 0; ax < D; ++ax)
+        for (int k = 0; k < 3; ++k) ld0[ax] += lE[k] * Eg[k].d[ax] + lB[k] * Bg[k].d[ax];
+    Axis<double> wv0[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        for (int k = 0; k < 2; ++k) wv0[ax].f[k] = ax0[ax].f[k].v;
+        for (int k = 0; k < 3; ++k) wv0[ax].s[k] = ax0[ax].s[k].v;
+    }
+    scatter_comp<D, 0>(acc, wv0, lE[0]);
+    scatter_comp<D, 1>(acc, wv0, lE[1]);
+    scatter_comp<D, 2>(acc, wv0, lE[2]);
+    scatter_comp<D, 3>(acc, wv0, lB[0]);
+    scatter_comp<D, 4>(acc, wv0, lB[1]);
+    scatter_comp<D, 5>(acc, wv0, lB[2]);
+    for (int k = 0; k < 3; ++k) lbp[k] += lB[k];
+
+    for (int ax = 0; ax < 3; ++ax) a.lam_x[ax * a.count + id] = ax < D ? ld0[ax] : 0.0;
+    for (int k = 0; k < 3; ++k) a.lam_w[k * a.count + id] = lw0[k];
+}
+
+template <int D>
+__device__ __forceinline__ void load_particle(const AdjArgs& a, int64_t p, int i0[3], double d0[3],
+                                              double w0[3], double& qp, int64_t& id)
+{
+    for (int ax = 0; ax < 3; ++ax) {
+        i0[ax] = 0;
+        d0[ax] = 0.0;
+    }
+    for (int ax = 0; ax < D; ++ax) {
+        const double x = a.pos[ax][p];
+        const double fl = floor(x);
+        i0[ax] = (int)fl;
+        d0[ax] = x - fl;
+    }
+    id = a.id[p];
+    for (int k = 0; k < 3; ++k) w0[k] = a.mom[k][p];
+    qp = a.q * a.weight[p];
+}
+
+// Sum lbp over the block into lam_bext.
+__device__ __forceinline__ void flush_bext(double* sb, const double lbp[3], double* lam_bext)
+{
+    for (int k = 0; k < 3; ++k)
+        if (lbp[k] != 0.0) atomicAdd(&sb[k], lbp[k]);
+    __syncthreads();
+    if (threadIdx.x < 3) grid_add(&lam_bext[threadIdx.x], sb[threadIdx.x]);
+}
+
+// One thread per particle, every grid access in global memory (any order of
+// the particles; 3D, and 2D before the first sort).
 template <int D>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_particles(GridK g, AdjArgs a)
 {
@@ -288,145 +611,122 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_particles(GridK g, AdjArgs 
     const int64_t p = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
     double lbp[3] = {0.0, 0.0, 0.0};
     if (p < a.n) {
-        const int64_t N = g.ncell;
-        const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-        const double c = g.c, c2 = c * c;
-        int i0[3] = {0, 0, 0};
-        double d0[3] = {0.0, 0.0, 0.0};
-        for (int ax = 0; ax < D; ++ax) {
-            const double x = a.pos[ax][p];
-            const double fl = floor(x);
-            i0[ax] = (int)fl;
-            d0[ax] = x - fl;
-        }
-        const int64_t id = a.id[p];
-        double w0[3];
-        for (int k = 0; k < 3; ++k) w0[k] = a.mom[k][p];
-        const double qp = a.q * a.weight[p];
-
-        // gather, with the derivatives in the start offsets d0
-        using DG = Dual<D>;
-        Axis<DG> ax0[3];
-        for (int ax = 0; ax < D; ++ax) ax0[ax] = form_factor<DG>(DG::var(d0[ax], ax));
-        if (D == 2) ax0[2] = form_factor<DG>(DG(0.0));
-        int xi[3], yj[3];
-        int64_t zk[3];
-        for (int o = 0; o < 3; ++o) {
-            xi[o] = wrapi(i0[0] + o - 1, nx);
-            yj[o] = wrapi(i0[1] + o - 1, ny) * nx;
-            zk[o] = D == 3 ? (int64_t)wrapi(i0[2] + o - 1, nz) * nx * ny : 0;
-        }
-        auto F = [&](int comp, int da, int db, int dc) -> double {
-            const int64_t cell = zk[dc + 1] + yj[db + 1] + xi[da + 1];
-            return comp < 3 ? a.E[comp * N + cell] : a.Bn[(comp - 3) * N + cell];
-        };
-        DG Eg[3], Bg[3];
-        if (D == 3) gather3<DG>(ax0, F, Eg, Bg);
-        else gather2<DG>(ax0, F, Eg, Bg);
-
-        // push, with the derivatives in (w, E_p, B_p)
-        using DP = Dual<9>;
-        DP wv[3], Ev[3], Bv[3];
-        for (int k = 0; k < 3; ++k) {
-            wv[k] = DP::var(w0[k], k);
-            Ev[k] = DP::var(Eg[k].v, 3 + k);
-            Bv[k] = DP::var(Bg[k].v + g.bext[k], 6 + k);
-        }
-        push<DP>(DP(0.5 * a.qm * g.dt), DP(c2), Ev, Bv, wv);
-        double w1[3];
-        for (int k = 0; k < 3; ++k) w1[k] = wv[k].v;
-
-        // position advance: values only (d1 = d0 + disp - delta)
-        const double inv = 1.0 / ::sqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2] + c2);
-        double disp[3];
-        for (int ax = 0; ax < 3; ++ax) disp[ax] = w1[ax] * inv * g.cfl[ax];
-        double d1[3] = {0.0, 0.0, 0.0};
-        int delta[3] = {0, 0, 0};
-        StepArgs none{};
-        PosIO<double, D>::move(none, p, g, i0, d0, disp, d1, delta, false);
-
-        // current, with the derivatives in (d0, d1[, w^{n+1/2} in 2D]), each
-        // contribution weighted by lambda_J at its cell
-        constexpr int NV = D == 3 ? 6 : 7;
-        using DD = Dual<NV>;
-        DD dm[3][4], dp[3][4];
-        for (int ax = 0; ax < D; ++ax) {
-            DD s0[3], s1[3];
-            cell_weights<DD>(DD::var(d0[ax], ax), s0);
-            cell_weights<DD>(DD::var(d1[ax], D + ax), s1);
-            window<DD>(s0, s1, delta[ax], dm[ax], dp[ax]);
-        }
-        DD jfac[3];
-        for (int k = 0; k < 3; ++k) jfac[k] = DD(g.jscale[k] * qp);
-        DD jz2(0.0);
-        if (D == 2) {
-            DD wz[3];
-            for (int k = 0; k < 3; ++k) wz[k] = DD::var(w1[k], 2 * D + k);
-            const DD invd = DD(1.0) / sqrt(wz[0] * wz[0] + wz[1] * wz[1] + wz[2] * wz[2] + DD(c2));
-            jz2 = DD(qp) * DD(0.25 * g.inv_vol) * DD(c) * wz[2] * invd;
-        }
-        int cxs[4], cys[4];
-        int64_t czs[4];
-        for (int o = 0; o < 4; ++o) {
-            const int sx = i0[0] + (delta[0] < 0 ? -1 : 0) - 1;
-            const int sy = i0[1] + (delta[1] < 0 ? -1 : 0) - 1;
-            const int sz = i0[2] + (delta[2] < 0 ? -1 : 0) - 1;
-            cxs[o] = wrapi(sx + o, nx);
-            cys[o] = wrapi(sy + o, ny) * nx;
-            czs[o] = D == 3 ? (int64_t)wrapi(sz + o, nz) * nx * ny : 0;
-        }
-        double gd[NV];
-        for (int k = 0; k < NV; ++k) gd[k] = 0.0;
-        auto S = [&](int comp, int ix, int iy, int iz, const DD& v) {
-            const double lj = a.lamJ[comp * N + czs[iz] + cys[iy] + cxs[ix]];
-            for (int k = 0; k < NV; ++k) gd[k] += lj * v.d[k];
-        };
-        if (D == 3) deposit3<DD>(dm, dp, jfac, S);
-        else deposit2<DD>(dm, dp, jfac, jz2, S);
-
-        // reverse assembly
-        double lx1[3] = {0.0, 0.0, 0.0}, lw1[3];
-        for (int ax = 0; ax < D; ++ax) lx1[ax] = a.lam_x[ax * a.count + id];
-        for (int k = 0; k < 3; ++k) lw1[k] = a.lam_w[k * a.count + id];
-        double ld1[3] = {0.0, 0.0, 0.0}, ld0[3] = {0.0, 0.0, 0.0};
-        for (int ax = 0; ax < D; ++ax) ld1[ax] = lx1[ax] + gd[D + ax];
-        const double inv3 = inv * inv * inv;
-        double lw[3];
-        for (int k = 0; k < 3; ++k) {
-            lw[k] = lw1[k] + (D == 2 ? gd[2 * D + k] : 0.0);
-            for (int ax = 0; ax < D; ++ax)
-                lw[k] += ld1[ax] * g.cfl[ax] * ((ax == k ? inv : 0.0) - w1[ax] * w1[k] * inv3);
-        }
-        for (int ax = 0; ax < D; ++ax) ld0[ax] = gd[ax] + ld1[ax];
-        double l9[9];
-        for (int j = 0; j < 9; ++j) {
-            l9[j] = 0.0;
-            for (int k = 0; k < 3; ++k) l9[j] += lw[k] * wv[k].d[j];
-        }
-        for (int ax = 0; ax < D; ++ax)
-            for (int k = 0; k < 3; ++k) ld0[ax] += l9[3 + k] * Eg[k].d[ax] + l9[6 + k] * Bg[k].d[ax];
-
-        // fields: alpha lambda_Ep into lambda_E, beta lambda_Bp into lambda_B
-        Axis<double> wv0[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            for (int k = 0; k < 2; ++k) wv0[ax].f[k] = ax0[ax].f[k].v;
-            for (int k = 0; k < 3; ++k) wv0[ax].s[k] = ax0[ax].s[k].v;
-        }
-        scatter_comp<D, true, false, false>(a.lamE, wv0, xi, yj, zk, l9[3]);
-        scatter_comp<D, false, true, false>(a.lamE + N, wv0, xi, yj, zk, l9[4]);
-        scatter_comp<D, false, false, true>(a.lamE + 2 * N, wv0, xi, yj, zk, l9[5]);
-        scatter_comp<D, false, true, true>(a.lamB, wv0, xi, yj, zk, l9[6]);
-        scatter_comp<D, true, false, true>(a.lamB + N, wv0, xi, yj, zk, l9[7]);
-        scatter_comp<D, true, true, false>(a.lamB + 2 * N, wv0, xi, yj, zk, l9[8]);
-        for (int k = 0; k < 3; ++k) lbp[k] = l9[6 + k];
-
-        for (int ax = 0; ax < 3; ++ax) a.lam_x[ax * a.count + id] = ax < D ? ld0[ax] : 0.0;
-        for (int k = 0; k < 3; ++k) a.lam_w[k * a.count + id] = l9[k];
+        int i0[3];
+        double d0[3], w0[3], qp;
+        int64_t id;
+        load_particle<D>(a, p, i0, d0, w0, qp, id);
+        GlobalAcc<D> acc(g, a);
+        adj_particle<D>(g, a, acc, i0, d0, w0, qp, id, lbp);
     }
-    for (int k = 0; k < 3; ++k)
-        if (lbp[k] != 0.0) atomicAdd(&sb[k], lbp[k]);
+    flush_bext(sb, lbp, a.lam_bext);
+}
+
+// 2D tile kernel.  The particles are grouped by the tiles of the last sort
+// (tile_start); kAdjSplit blocks share a tile's particles.  Each block stages
+// E, B^n (cells T0-1-M .. T0+T+M) and lambda_J (T0-2-M .. T0+T+1+M) of its
+// tile in LDS and accumulates lambda_E, lambda_B over the field region in LDS,
+// added to the grid once at the end; a particle more than M cells outside its
+// tile (it moved since the sort) uses the global-memory accessor instead.
+constexpr int kAdjT2 = kTile2;
+constexpr int kAdjM2 = 2;
+constexpr int kAdjLF2 = kAdjT2 + 2 + 2 * kAdjM2;
+constexpr int kAdjLJ2 = kAdjT2 + 4 + 2 * kAdjM2;
+constexpr int kAdjNF2 = kAdjLF2 * kAdjLF2;
+constexpr int kAdjNJ2 = kAdjLJ2 * kAdjLJ2;
+
+struct LdsAcc2 {
+    const double* sf;  // 6 x kAdjNF2
+    const double* sj;  // 3 x kAdjNJ2
+    double* sacc;      // 6 x kAdjNF2
+    int r0, r1;        // particle cell relative to the tile origin
+    int fo, jo;        // particle cell in the field region, window start in the current region
+    __device__ void at(const int*) { fo = (r1 + 1 + kAdjM2) * kAdjLF2 + r0 + 1 + kAdjM2; }
+    __device__ void window(const int*, const int delta[3])
+    {
+        jo = (r1 + 1 + kAdjM2 + (delta[1] < 0 ? -1 : 0)) * kAdjLJ2 + r0 + 1 + kAdjM2 + (delta[0] < 0 ? -1 : 0);
+    }
+    __device__ double F(int comp, int da, int db, int) const
+    {
+        return sf[comp * kAdjNF2 + fo + db * kAdjLF2 + da];
+    }
+    __device__ double L(int comp, int ix, int iy, int) const
+    {
+        return sj[comp * kAdjNJ2 + jo + iy * kAdjLJ2 + ix];
+    }
+    __device__ void add(int comp, int da, int db, int, double v) const
+    {
+        atomicAdd(&sacc[comp * kAdjNF2 + fo + db * kAdjLF2 + da], v);
+    }
+};
+
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_tile2(GridK g, AdjArgs a, const int64_t* __restrict__ tile_start,
+                                                        int split)
+{
+    constexpr int T = kAdjT2, M = kAdjM2, LF = kAdjLF2, LJ = kAdjLJ2, NF = kAdjNF2, NJ = kAdjNJ2;
+    __shared__ double sf[6 * NF];
+    __shared__ double sj[3 * NJ];
+    __shared__ double sacc[6 * NF];
+    __shared__ double sb[3];
+    const int unit = xcd_tile(blockIdx.x, g.ntiles * split);
+    const int tile = unit / split, part = unit - tile * split;
+    const int T0[2] = {(tile % g.nt[0]) * T, (tile / g.nt[0]) * T};
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1];
+    for (int e = threadIdx.x; e < 6 * NF; e += kAdjThreads) {
+        const int comp = e / NF, r = e - comp * NF;
+        const int gx = wrapi(T0[0] - 1 - M + r % LF, nx), gy = wrapi(T0[1] - 1 - M + r / LF, ny);
+        const int64_t cell = (int64_t)gy * nx + gx;
+        sf[e] = comp < 3 ? a.E[comp * N + cell] : a.Bn[(comp - 3) * N + cell];
+        sacc[e] = 0.0;
+    }
+    for (int e = threadIdx.x; e < 3 * NJ; e += kAdjThreads) {
+        const int comp = e / NJ, r = e - comp * NJ;
+        const int gx = wrapi(T0[0] - 2 - M + r % LJ, nx), gy = wrapi(T0[1] - 2 - M + r / LJ, ny);
+        sj[e] = a.lamJ[comp * N + (int64_t)gy * nx + gx];
+    }
+    if (threadIdx.x < 3) sb[threadIdx.x] = 0.0;
     __syncthreads();
-    if (threadIdx.x < 3) grid_add(&a.lam_bext[threadIdx.x], sb[threadIdx.x]);
+
+    double lbp[3] = {0.0, 0.0, 0.0};
+    const int64_t begin = tile_start[tile], end = tile_start[tile + 1];
+    for (int64_t p = begin + part * kAdjThreads + threadIdx.x; p < end; p += (int64_t)split * kAdjThreads) {
+        int i0[3];
+        double d0[3], w0[3], qp;
+        int64_t id;
+        load_particle<2>(a, p, i0, d0, w0, qp, id);
+        int rel[2];
+        bool inside = true;
+        for (int ax = 0; ax < 2; ++ax) {
+            int r = i0[ax] - T0[ax];
+            const int n = g.n[ax];
+            if (r > n / 2) r -= n;
+            if (r < -(n / 2)) r += n;
+            rel[ax] = r;
+            inside = inside && r >= -M && r <= T - 1 + M;
+        }
+        if (inside) {
+            LdsAcc2 acc;
+            acc.sf = sf;
+            acc.sj = sj;
+            acc.sacc = sacc;
+            acc.r0 = rel[0];
+            acc.r1 = rel[1];
+            adj_particle<2>(g, a, acc, i0, d0, w0, qp, id, lbp);
+        } else {
+            GlobalAcc<2> acc(g, a);
+            adj_particle<2>(g, a, acc, i0, d0, w0, qp, id, lbp);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 6 * NF; e += kAdjThreads) {
+        const double v = sacc[e];
+        if (v == 0.0) continue;
+        const int comp = e / NF, r = e - comp * NF;
+        const int gx = wrapi(T0[0] - 1 - M + r % LF, nx), gy = wrapi(T0[1] - 1 - M + r / LF, ny);
+        const int64_t cell = (int64_t)gy * nx + gx;
+        grid_add(comp < 3 ? &a.lamE[comp * N + cell] : &a.lamB[(comp - 3) * N + cell], v);
+    }
+    flush_bext(sb, lbp, a.lam_bext);
 }
 
 unsigned cells_blocks(int64_t n) { return (unsigned)((n + kCurlThreads - 1) / kCurlThreads); }
@@ -441,29 +741,162 @@ hipError_t launch_adjoint_seed(const Ctx& c, double* lam, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const Ctx& c, double* lam, double* const* lam_x, double* const* lam_w,
-                               double* lam_bext, hipStream_t s)
+namespace {
+
+// ---------------------------------------------------------------------------
+// The state a reverse step reads: E^n, B^{n-1/2} (6 planes) and per species
+// the particles in storage order with the tile table of their last sort
+// (tiles false: no valid table).  Either the context itself or a record.
+// ---------------------------------------------------------------------------
+struct PartView {
+    const double* pos[3];
+    const double* mom[3];
+    const double* weight;
+    const int64_t* id;
+    const int64_t* tile_start;
+    bool tiles;
+};
+
+struct StateView {
+    const double* fields;
+    PartView sp[kMaxSpecies];
+};
+
+StateView context_view(const Ctx& c)
 {
+    StateView v{};
+    v.fields = c.fields;
+    for (int i = 0; i < c.nsp; ++i) {
+        const Species& sp = c.sp[i];
+        for (int ax = 0; ax < 3; ++ax) {
+            v.sp[i].pos[ax] = (const double*)sp.cur.pos[ax];
+            v.sp[i].mom[ax] = (const double*)sp.cur.mom[ax];
+        }
+        v.sp[i].weight = (const double*)sp.cur.weight;
+        v.sp[i].id = sp.cur.id;
+        v.sp[i].tile_start = sp.tile_start;
+        v.sp[i].tiles = sp.sorted;
+    }
+    return v;
+}
+
+// Record layout (each array 256-byte aligned): E, B (6 N doubles); then per
+// mobile species with particles, in species order: x (dims rows of n),
+// w (3 rows), weight, id, tile table (ntiles + 1).  Carve with base ==
+// nullptr to size it.
+size_t carve_record(const Ctx& c, char* base, StateView* v)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* r = base ? base + off : nullptr;
+        off += align_up(bytes, kAlign);
+        return r;
+    };
+    const size_t N = (size_t)c.k.ncell;
+    char* f = take(6 * N * 8);
+    if (v) v->fields = (const double*)f;
+    for (int i = 0; i < c.nsp; ++i) {
+        const Species& sp = c.sp[i];
+        if (!sp.d.mobile || sp.n == 0) continue;
+        const size_t n = (size_t)sp.n;
+        PartView pv{};
+        for (int ax = 0; ax < c.k.dims; ++ax) pv.pos[ax] = (const double*)take(n * 8);
+        for (int k = 0; k < 3; ++k) pv.mom[k] = (const double*)take(n * 8);
+        pv.weight = (const double*)take(n * 8);
+        pv.id = (const int64_t*)take(n * 8);
+        pv.tile_start = (const int64_t*)take(((size_t)c.k.ntiles + 1) * 8);
+        pv.tiles = true;
+        if (v) v->sp[i] = pv;
+    }
+    return off;
+}
+
+// Copy of up to kMaxSeg arrays of 8-byte words in one launch (blockIdx.y =
+// array).  src == nullptr: write the tile table of an unsorted species, an
+// even split of its `fill` particles over count - 1 tiles (any particle may
+// be processed in any tile; the table only spreads the work).
+struct CopySeg {
+    const uint64_t* src;
+    uint64_t* dst;
+    int64_t count;
+    int64_t fill;
+};
+constexpr int kMaxSeg = 1 + kMaxSpecies * 8;
+struct CopySegs {
+    CopySeg s[kMaxSeg];
+};
+
+__global__ __launch_bounds__(256) void k_copy_segments(CopySegs segs)
+{
+    const CopySeg sg = segs.s[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    if (sg.src) {
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < sg.count; i += stride) sg.dst[i] = sg.src[i];
+    } else {
+        const int64_t tiles = sg.count - 1;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < sg.count; i += stride)
+            sg.dst[i] = (uint64_t)(i * sg.fill / tiles);
+    }
+}
+
+}  // namespace
+
+size_t adjoint_record_bytes(const Ctx& c) { return carve_record(c, nullptr, nullptr); }
+
+hipError_t launch_adjoint_record(const Ctx& c, void* record, hipStream_t s)
+{
+    StateView v{};
+    carve_record(c, (char*)record, &v);
+    CopySegs segs{};
+    int ns = 0;
+    int64_t longest = 0;
+    auto add = [&](const void* src, const void* dst, int64_t count, int64_t fill) {
+        segs.s[ns++] = CopySeg{(const uint64_t*)src, (uint64_t*)dst, count, fill};
+        longest = std::max(longest, count);
+    };
+    add(c.fields, v.fields, 6 * c.k.ncell, 0);
+    for (int i = 0; i < c.nsp; ++i) {
+        const Species& sp = c.sp[i];
+        if (!sp.d.mobile || sp.n == 0) continue;
+        const PartView& pv = v.sp[i];
+        for (int ax = 0; ax < c.k.dims; ++ax) add(sp.cur.pos[ax], pv.pos[ax], sp.n, 0);
+        for (int k = 0; k < 3; ++k) add(sp.cur.mom[k], pv.mom[k], sp.n, 0);
+        add(sp.cur.weight, pv.weight, sp.n, 0);
+        add(sp.cur.id, pv.id, sp.n, 0);
+        add(sp.sorted ? sp.tile_start : nullptr, pv.tile_start, (int64_t)c.k.ntiles + 1, sp.n);
+    }
+    const unsigned gx = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (longest + 255) / 256));
+    hipLaunchKernelGGL(k_copy_segments, dim3(gx, (unsigned)ns), dim3(256), 0, s, segs);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Ctx& c, const void* record, double* lam, double* const* lam_x,
+                               double* const* lam_w, double* lam_bext, hipStream_t s)
+{
+    StateView v{};
+    if (record) carve_record(c, (char*)record, &v);
+    else v = context_view(c);
     const int64_t N = c.k.ncell;
     const unsigned b = cells_blocks(N);
-    hipLaunchKernelGGL(k_adj_bn, dim3(b), dim3(kCurlThreads), 0, s, c.k, c.fields, c.bn);
+    hipLaunchKernelGGL(k_adj_bn, dim3(b), dim3(kCurlThreads), 0, s, c.k, v.fields, c.bn);
     hipLaunchKernelGGL(k_adj_pre, dim3(b), dim3(kCurlThreads), 0, s, c.k, lam, lam + 3 * N, c.adj);
     hipLaunchKernelGGL(k_adj_curl, dim3(b), dim3(kCurlThreads), 0, s, c.k, lam, lam + 3 * N);
     for (int i = 0; i < c.nsp; ++i) {
         const Species& sp = c.sp[i];
         if (!sp.d.mobile || sp.n == 0) continue;
+        const PartView& pv = v.sp[i];
         AdjArgs a{};
         for (int ax = 0; ax < 3; ++ax) {
-            a.pos[ax] = (const double*)sp.cur.pos[ax];
-            a.mom[ax] = (const double*)sp.cur.mom[ax];
+            a.pos[ax] = pv.pos[ax];
+            a.mom[ax] = pv.mom[ax];
         }
-        a.weight = (const double*)sp.cur.weight;
-        a.id = sp.cur.id;
+        a.weight = pv.weight;
+        a.id = pv.id;
         a.n = sp.n;
         a.count = sp.n;
         a.q = sp.d.q;
         a.qm = sp.d.q / sp.d.m;
-        a.E = c.fields;
+        a.E = v.fields;
         a.Bn = c.bn;
         a.lamJ = c.adj;
         a.lamE = lam;
@@ -472,10 +905,16 @@ hipError_t launch_adjoint_step(const Ctx& c, double* lam, double* const* lam_x, 
         a.lam_w = lam_w[i];
         a.lam_bext = lam_bext;
         const unsigned pb = (unsigned)((sp.n + kAdjThreads - 1) / kAdjThreads);
-        if (c.k.dims == 3)
+        if (c.k.dims == 3) {
             hipLaunchKernelGGL(k_adj_particles<3>, dim3(pb), dim3(kAdjThreads), 0, s, c.k, a);
-        else
+        } else if (pv.tiles) {
+            // enough workgroups to fill the chip: several per tile when tiles are few
+            const int split = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + c.k.ntiles - 1) / c.k.ntiles));
+            hipLaunchKernelGGL(k_adj_tile2, dim3((unsigned)(c.k.ntiles * split)), dim3(kAdjThreads), 0, s, c.k, a,
+                               pv.tile_start, split);
+        } else {
             hipLaunchKernelGGL(k_adj_particles<2>, dim3(pb), dim3(kAdjThreads), 0, s, c.k, a);
+        }
     }
     hipLaunchKernelGGL(k_adj_curl, dim3(b), dim3(kCurlThreads), 0, s, c.k, lam, lam + 3 * N);
     return hipGetLastError();

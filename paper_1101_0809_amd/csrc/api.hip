@@ -20,7 +20,6 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 namespace {
 
 thread_local std::string g_tls_err;
-constexpr size_t kAlign = 256;
 
 int fail(Ctx* c, int code, const std::string& msg)
 {
@@ -466,8 +465,8 @@ int pic_adjoint_seed_field_energy(pic_ctx* ctx, double* lam_fields, void* stream
     return PIC_OK;
 }
 
-int pic_adjoint_step(pic_ctx* ctx, double* lam_fields, double* const* lam_x, double* const* lam_w,
-                     double* lam_bext, void* stream)
+static int adjoint_step_common(pic_ctx* ctx, const void* record, size_t record_bytes, double* lam_fields,
+                               double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream)
 {
     if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
     Ctx& c = ctx->c;
@@ -477,9 +476,44 @@ int pic_adjoint_step(pic_ctx* ctx, double* lam_fields, double* const* lam_x, dou
     for (int i = 0; i < c.nsp; ++i)
         if (c.sp[i].d.mobile && c.sp[i].n > 0 && (!lam_x[i] || !lam_w[i]))
             return fail(&c, PIC_EINVAL, "null particle adjoint of a mobile species");
-    hipError_t e = launch_adjoint_step(c, lam_fields, lam_x, lam_w, lam_bext, (hipStream_t)stream);
+    if (record && record_bytes < adjoint_record_bytes(c))
+        return fail(&c, PIC_ESIZE, "record smaller than pic_adjoint_record_bytes");
+    hipError_t e = launch_adjoint_step(c, record, lam_fields, lam_x, lam_w, lam_bext, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(&c, e, "adjoint_step");
     return PIC_OK;
+}
+
+int pic_adjoint_step(pic_ctx* ctx, double* lam_fields, double* const* lam_x, double* const* lam_w,
+                     double* lam_bext, void* stream)
+{
+    return adjoint_step_common(ctx, nullptr, 0, lam_fields, lam_x, lam_w, lam_bext, stream);
+}
+
+int pic_adjoint_record_bytes(const pic_ctx* ctx, size_t* bytes)
+{
+    if (!ctx || !bytes) return fail(nullptr, PIC_EINVAL, "null argument");
+    *bytes = adjoint_record_bytes(ctx->c);
+    return PIC_OK;
+}
+
+int pic_adjoint_record(pic_ctx* ctx, void* record, size_t bytes, void* stream)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    if (!record) return fail(&c, PIC_EINVAL, "null record");
+    const int r = adjoint_ready(c);
+    if (r != PIC_OK) return r;
+    if (bytes < adjoint_record_bytes(c)) return fail(&c, PIC_ESIZE, "record smaller than pic_adjoint_record_bytes");
+    hipError_t e = launch_adjoint_record(c, record, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(&c, e, "adjoint_record");
+    return PIC_OK;
+}
+
+int pic_adjoint_step_record(pic_ctx* ctx, const void* record, size_t bytes, double* lam_fields,
+                            double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream)
+{
+    if (!record) return fail(ctx ? &ctx->c : nullptr, PIC_EINVAL, "null record");
+    return adjoint_step_common(ctx, record, bytes, lam_fields, lam_x, lam_w, lam_bext, stream);
 }
 
 int pic_diagnostics(pic_ctx* ctx, pic_diag* out, void* stream)

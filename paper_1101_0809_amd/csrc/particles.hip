@@ -45,16 +45,6 @@ __device__ __forceinline__ void global_add(double* p, double v)
     unsafeAtomicAdd(p, v);
 }
 
-// Workgroup -> tile map: consecutive workgroup ids are dealt round-robin to
-// the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
-// share field rows and J guard cells in that XCD's L2).
-__device__ __forceinline__ int xcd_tile(int bid, int ntiles)
-{
-    const int per = ntiles / kXcds, rem = ntiles % kXcds;
-    const int x = bid % kXcds, local = bid / kXcds;
-    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
-}
-
 // ---------------------------------------------------------------------------
 // The 2D3V particle-step kernel (tile kTile2^2, margin kMargin2); every
 // particle deposits its window at once.

@@ -13,6 +13,7 @@ namespace pic {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxSpecies = 4;
+constexpr size_t kAlign = 256;  // alignment of every carved buffer
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
 
 // Tile edge (cells) of the particle-step kernel, per dimensionality.
@@ -143,7 +144,11 @@ hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s);
 hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
 hipError_t launch_adjoint_seed(const Ctx& c, double* lam, hipStream_t s);
-hipError_t launch_adjoint_step(const Ctx& c, double* lam, double* const* lam_x, double* const* lam_w,
-                               double* lam_bext, hipStream_t s);
+// record == nullptr: the state before the step is the context's own; else a
+// record written by launch_adjoint_record.
+hipError_t launch_adjoint_step(const Ctx& c, const void* record, double* lam, double* const* lam_x,
+                               double* const* lam_w, double* lam_bext, hipStream_t s);
+size_t adjoint_record_bytes(const Ctx& c);
+hipError_t launch_adjoint_record(const Ctx& c, void* record, hipStream_t s);
 
 }  // namespace pic

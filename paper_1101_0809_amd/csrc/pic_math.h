@@ -354,6 +354,16 @@ __device__ __forceinline__ void deposit2(const R (&dm)[3][4], const R (&dp)[3][4
     }
 }
 
+// Workgroup -> tile map: consecutive workgroup ids are dealt round-robin to
+// the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
+// share field rows and J guard cells in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles)
+{
+    const int per = ntiles / kXcds, rem = ntiles % kXcds;
+    const int x = bid % kXcds, local = bid / kXcds;
+    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 // ---------------------------------------------------------------------------
 // Particle representations.
 // ---------------------------------------------------------------------------

@@ -266,12 +266,18 @@ class Sim:
         self._check(self.lib.pic_adjoint_seed_field_energy(
             self.ctx, ctypes.c_void_p(lam_fields.data_ptr()), _stream()))
 
-    def adjoint_step(self, lam_fields: torch.Tensor, lam_x: list, lam_w: list, lam_bext: torch.Tensor):
-        """One reverse step (include/pic.h): the context holds the state the
-        step was taken from; lam_* hold the adjoint of the state after it and
-        are replaced by the adjoint of the state before it.  lam_x[s] and
-        lam_w[s] are (3, count) FP64 device tensors in particle-id order (None
-        for immobile species); lam_bext (3,) accumulates dL/dB_ext."""
+    def adjoint_record_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        self._check(self.lib.pic_adjoint_record_bytes(self.ctx, ctypes.byref(n)))
+        return n.value
+
+    def adjoint_record(self, record: torch.Tensor):
+        """Copy the state the next step starts from into record (a uint8
+        device tensor of adjoint_record_bytes())."""
+        self._check(self.lib.pic_adjoint_record(self.ctx, ctypes.c_void_p(record.data_ptr()),
+                                                record.numel(), _stream()))
+
+    def _lam_ptrs(self, lam_x, lam_w):
         nsp = len(self.species)
         px = (ctypes.c_void_p * nsp)()
         pw = (ctypes.c_void_p * nsp)()
@@ -281,6 +287,25 @@ class Sim:
                 for t in (lam_x[i], lam_w[i]):
                     assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == 3 * n
                 px[i], pw[i] = lam_x[i].data_ptr(), lam_w[i].data_ptr()
+        return px, pw
+
+    def adjoint_step_record(self, record: torch.Tensor, lam_fields: torch.Tensor, lam_x: list,
+                            lam_w: list, lam_bext: torch.Tensor):
+        """adjoint_step with the state before the step taken from a record."""
+        px, pw = self._lam_ptrs(lam_x, lam_w)
+        assert lam_fields.numel() == 6 * self.ncell and lam_bext.numel() == 3
+        self._check(self.lib.pic_adjoint_step_record(
+            self.ctx, ctypes.c_void_p(record.data_ptr()), record.numel(),
+            ctypes.c_void_p(lam_fields.data_ptr()), px, pw, ctypes.c_void_p(lam_bext.data_ptr()),
+            _stream()))
+
+    def adjoint_step(self, lam_fields: torch.Tensor, lam_x: list, lam_w: list, lam_bext: torch.Tensor):
+        """One reverse step (include/pic.h): the context holds the state the
+        step was taken from; lam_* hold the adjoint of the state after it and
+        are replaced by the adjoint of the state before it.  lam_x[s] and
+        lam_w[s] are (3, count) FP64 device tensors in particle-id order (None
+        for immobile species); lam_bext (3,) accumulates dL/dB_ext."""
+        px, pw = self._lam_ptrs(lam_x, lam_w)
         assert lam_fields.numel() == 6 * self.ncell and lam_bext.numel() == 3
         self._check(self.lib.pic_adjoint_step(
             self.ctx, ctypes.c_void_p(lam_fields.data_ptr()), px, pw,

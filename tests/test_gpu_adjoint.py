@@ -119,15 +119,18 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("mode", ["checkpoints", "tape"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_adjoint_matches_reference_gradient(name):
+def test_adjoint_matches_reference_gradient(name, mode):
+    """Checkpoints: state copies every few steps, segments re-run in the
+    reverse pass; tape: a record of every step taken in the forward pass."""
     c = CASES[name]
     x, w, weight = picgen.beams(c["box"], c["n"], c["seed"], w_th=c["w_th"], drift=c["drift"],
                                 dims=c["dims"])
     g = ad.Grid(*c["box"], c["dt"])
     L_ref, gw_ref, gb_ref, gx_ref = ad.loss_and_grad(g, x, w, weight, -1.0, 1.0, c["bext"], c["steps"])
     L, gx, gw, gb = _gpu_grad(c["box"], c["dims"], c["dt"], x, w, weight, c["bext"], c["steps"],
-                              c["every"])
+                              c["every"] if mode == "checkpoints" else None)
     assert abs(L - L_ref) <= 1e-12 * L_ref
     _close(gw, gw_ref)
     _close(gx[: c["dims"]], gx_ref[: c["dims"]])
@@ -182,6 +185,48 @@ def test_autograd_function_and_central_difference_of_gpu_forward():
                             grid, c["steps"]))
     fd = (Lp - Lm) / (2 * h)
     assert abs(gb0[2] - fd) <= 1e-6 * abs(fd), (gb0[2], fd)
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_record_step_equals_context_step(dims):
+    """pic_adjoint_step_record on a record of the context's state gives what
+    pic_adjoint_step gives on the context itself, for a sorted state and for
+    the unsorted state right after loading."""
+    from paper_1101_0809_amd import Sim
+    box = (21, 18, 1) if dims == 2 else (10, 9, 11)
+    n = 1501 if dims == 2 else 1303
+    x, w, weight = picgen.beams(box, n, 110 + dims, w_th=0.3, drift=0.2, dims=dims)
+    shape = (box[2], box[1], box[0])
+    sim = Sim(nx=box[0], ny=box[1], nz=box[2], dt=0.45, dims=dims, bext=(0.01, 0.02, 0.03),
+              fields=_fields(shape, 120 + dims, 0.05), sort_every=4)
+    sim.add_species(-1.0, 1.0, capacity=n)
+    sim.load(0, x, w, weight)
+    dev = torch.device("cuda:0")
+    rng = np.random.Generator(np.random.PCG64(130 + dims))
+    lam0 = [torch.tensor(rng.normal(size=6 * sim.ncell), device=dev),
+            torch.tensor(rng.normal(size=(3, n)), device=dev),
+            torch.tensor(rng.normal(size=(3, n)), device=dev)]
+    for stepped in (0, 2):
+        sim.step(stepped)
+        outs = []
+        for use_record in (False, True):
+            lf, lx, lw = (t.clone() for t in lam0)
+            lb = torch.zeros(3, dtype=torch.float64, device=dev)
+            if use_record:
+                rec = torch.empty(sim.adjoint_record_bytes(), dtype=torch.uint8, device=dev)
+                sim.adjoint_record(rec)
+                sim.step(1)  # the context moves on; the record keeps the state
+                sim.adjoint_step_record(rec, lf, [lx], [lw], lb)
+            else:
+                sim.adjoint_step(lf, [lx], [lw], lb)
+            outs.append([t.cpu().numpy() for t in (lf, lx, lw, lb)])
+        for a, b in zip(*outs):
+            _close(a, b, 1e-13)
+    rec = torch.empty(sim.adjoint_record_bytes() - 256, dtype=torch.uint8, device=dev)
+    from paper_1101_0809_amd._lib import PicError
+    with pytest.raises(PicError):
+        sim.adjoint_record(rec)
+    sim.close()
 
 
 def test_adjoint_rejects_fp32_mode():
