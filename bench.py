@@ -141,7 +141,8 @@ def run_adjoint(wl, every: int):
     grad_ms = (time.perf_counter() - t0) * 1e3
 
     # one reverse step from a record of a sorted state (as every step after
-    # the first), repeated, and the record copy alone
+    # the first; particle adjoints in storage order, as in the sweep),
+    # repeated, and the record copy alone
     sim.restore(init)
     sim.step(1)
     rec = torch.empty(sim.adjoint_record_bytes(), dtype=torch.uint8, device=sim.device)
@@ -156,7 +157,7 @@ def run_adjoint(wl, every: int):
     a, b = ev(), ev()
     a.record(stream)
     for _ in range(reps):
-        sim.adjoint_step_record(rec, lam_f, lx, lw, lb)
+        sim.adjoint_step_record(rec, lam_f, lx, lw, lb, ordered=True)
     b.record(stream)
     torch.cuda.synchronize()
     adj_ms = a.elapsed_time(b) / reps

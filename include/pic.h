@@ -233,6 +233,27 @@ int pic_adjoint_record(pic_ctx* ctx, void* record, size_t bytes, void* stream);
 int pic_adjoint_step_record(pic_ctx* ctx, const void* record, size_t bytes, double* lam_fields,
                             double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream);
 
+/* Particle adjoints in storage order.  Reading them by id costs a scattered
+ * access per particle; a reverse sweep can keep them in the order of the
+ * particles in its records instead, which stays the same between sorts.
+ *
+ * pic_adjoint_step_record_ordered: pic_adjoint_step_record with lam_x[s],
+ * lam_w[s] ([3][n] FP64) indexed by the particle's position in the record.
+ * pic_adjoint_reorder: out[k] = in[position, in the order of record `from`,
+ * of the particle at position k in the order of record `to`], per species;
+ * a NULL record stands for id order.  A sweep calls it across every step that
+ * sorted (pic_sort, a first step after loading, or a periodic sort: the host
+ * state tells), and once at the end to return to id order.  Out of place
+ * (PIC_EINVAL if an output aliases an input); bytes is the size of the
+ * records (PIC_ESIZE if smaller than pic_adjoint_record_bytes, unused when
+ * both are NULL).  Uses the species' sort scratch in its particle buffer.
+ * Asynchronous. */
+int pic_adjoint_step_record_ordered(pic_ctx* ctx, const void* record, size_t bytes, double* lam_fields,
+                                    double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream);
+int pic_adjoint_reorder(pic_ctx* ctx, const void* from, const void* to, size_t bytes,
+                        const double* const* in_x, const double* const* in_w, double* const* out_x,
+                        double* const* out_w, void* stream);
+
 /* Number of particles currently held by a species (host-side count). */
 int64_t pic_particle_count(const pic_ctx* ctx, int species);
 

@@ -24,7 +24,8 @@ EXPORTS = (
     "pic_get_particles", "pic_sort", "pic_last_fallback_fraction", "pic_timing_start",
     "pic_timing_stop", "pic_get_host_state", "pic_set_host_state", "pic_destroy",
     "pic_adjoint_seed_field_energy", "pic_adjoint_step", "pic_adjoint_record_bytes",
-    "pic_adjoint_record", "pic_adjoint_step_record",
+    "pic_adjoint_record", "pic_adjoint_step_record", "pic_adjoint_step_record_ordered",
+    "pic_adjoint_reorder",
     "pic_last_error", "pic_version",
 )
 
@@ -116,6 +117,10 @@ def load(path: str = LIB_PATH):
         "pic_adjoint_record": (I, [P, P, ctypes.c_size_t, P]),
         "pic_adjoint_step_record": (I, [P, P, ctypes.c_size_t, P, ctypes.POINTER(P), ctypes.POINTER(P),
                                         P, P]),
+        "pic_adjoint_step_record_ordered": (I, [P, P, ctypes.c_size_t, P, ctypes.POINTER(P),
+                                                ctypes.POINTER(P), P, P]),
+        "pic_adjoint_reorder": (I, [P, P, P, ctypes.c_size_t, ctypes.POINTER(P), ctypes.POINTER(P),
+                                    ctypes.POINTER(P), ctypes.POINTER(P), P]),
         "pic_destroy": (None, [P]),
         "pic_last_error": (ctypes.c_char_p, [P]),
         "pic_version": (ctypes.c_char_p, []),

@@ -42,15 +42,24 @@ def _plan(sim: Sim, nsteps: int, every, budget_bytes) -> int:
     return 20
 
 
+def _step_recorded(sim: Sim, record: torch.Tensor) -> bool:
+    """Record the current state, take one step; return whether the step
+    changed the storage order of the particles (it sorted)."""
+    sim.adjoint_record(record)
+    before = sim.host_state()
+    unsorted = any(not before.sorted[i] for i, s in enumerate(sim.species) if s.mobile)
+    sim.step(1)
+    return unsorted or (sim.desc.sort_every > 0 and sim.host_state().since_sort == 0)
+
+
 def _forward(sim: Sim, nsteps: int, seg: int):
     """Step the context nsteps times from its current state.  Returns the
-    checkpoints [(length, state copy)] and, for a single segment, its tape."""
+    checkpoints [(length, state copy)] and, for a single segment, its tape
+    with the steps that sorted."""
     if seg >= nsteps:
         tape = _tape(sim, max(1, nsteps))
-        for i in range(nsteps):
-            sim.adjoint_record(tape[i])
-            sim.step(1)
-        return [], tape
+        sorted_at = [_step_recorded(sim, tape[i]) for i in range(nsteps)]
+        return [], (tape, sorted_at)
     ckpt = []
     done = 0
     while done < nsteps:
@@ -66,35 +75,63 @@ def _field_energy(sim: Sim) -> float:
     return d["field_e"] + d["field_b"]
 
 
+class _ParticleAdjoint:
+    """Particle adjoints of every species in one storage order, with a spare
+    pair for out-of-place reordering."""
+
+    def __init__(self, sim: Sim):
+        self.sim = sim
+        dev = sim.device
+        mk = lambda i, s: (torch.zeros((3, sim.count(i)), dtype=torch.float64, device=dev)
+                           if s.mobile else None)
+        self.x = [mk(i, s) for i, s in enumerate(sim.species)]
+        self.w = [mk(i, s) for i, s in enumerate(sim.species)]
+        self.x2 = [None if t is None else torch.empty_like(t) for t in self.x]
+        self.w2 = [None if t is None else torch.empty_like(t) for t in self.w]
+
+    def reorder(self, src, dst):
+        self.sim.adjoint_reorder(src, dst, self.x, self.w, self.x2, self.w2)
+        self.x, self.x2 = self.x2, self.x
+        self.w, self.w2 = self.w2, self.w
+
+
+def _sweep(sim: Sim, records, sorted_at, lam_fields, pa: _ParticleAdjoint, lam_b):
+    """Reverse steps over records[k-1] .. records[0]; the particle adjoints
+    enter in the order of records[k-1] and leave in that of records[0]."""
+    k = len(sorted_at)
+    for j in reversed(range(k)):
+        if j + 1 < k and sorted_at[j]:
+            pa.reorder(records[j + 1], records[j])
+        sim.adjoint_step_record(records[j], lam_fields, pa.x, pa.w, lam_b, ordered=True)
+
+
 def _reverse(sim: Sim, nsteps: int, ckpt: list, tape, lam_fields: torch.Tensor):
     """Walk back from the adjoint lam_fields of the final fields; return
     (lam_x, lam_w, lam_bext) of the state the forward pass started from
     (particle arrays per species, id order, None for immobile ones)."""
-    dev = sim.device
-    lam_x, lam_w = [], []
-    for i, s in enumerate(sim.species):
-        if s.mobile:
-            n = sim.count(i)
-            lam_x.append(torch.zeros((3, n), dtype=torch.float64, device=dev))
-            lam_w.append(torch.zeros((3, n), dtype=torch.float64, device=dev))
-        else:
-            lam_x.append(None)
-            lam_w.append(None)
-    lam_b = torch.zeros(3, dtype=torch.float64, device=dev)
+    pa = _ParticleAdjoint(sim)
+    lam_b = torch.zeros(3, dtype=torch.float64, device=sim.device)
     if tape is not None:
-        for i in reversed(range(nsteps)):
-            sim.adjoint_step_record(tape[i], lam_fields, lam_x, lam_w, lam_b)
-        return lam_x, lam_w, lam_b
+        records, sorted_at = tape
+        # the adjoints start at zero: any order is the order of the last record
+        _sweep(sim, records, sorted_at, lam_fields, pa, lam_b)
+        if nsteps:
+            pa.reorder(records[0], None)
+        return pa.x, pa.w, lam_b
     seg_tape = _tape(sim, max(k for k, _ in ckpt))
     for k, snap in reversed(ckpt):
         sim.restore(snap)
+        sorted_at = []
         for j in range(k):
-            sim.adjoint_record(seg_tape[j])
             if j + 1 < k:
-                sim.step(1)
-        for j in reversed(range(k)):
-            sim.adjoint_step_record(seg_tape[j], lam_fields, lam_x, lam_w, lam_b)
-    return lam_x, lam_w, lam_b
+                sorted_at.append(_step_recorded(sim, seg_tape[j]))
+            else:
+                sim.adjoint_record(seg_tape[j])
+                sorted_at.append(False)
+        pa.reorder(None, seg_tape[k - 1])
+        _sweep(sim, seg_tape, sorted_at, lam_fields, pa, lam_b)
+        pa.reorder(seg_tape[0], None)
+    return pa.x, pa.w, lam_b
 
 
 def field_energy_grad(sim: Sim, nsteps: int, every: int = None, budget_bytes: int = None):

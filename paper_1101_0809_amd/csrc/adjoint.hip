@@ -256,9 +256,10 @@ struct AdjArgs {
     const double* lamJ;  // 3 planes
     double* lamE;        // 3 planes, accumulated
     double* lamB;        // 3 planes, accumulated
-    double* lam_x;       // 3 x count, by particle id
-    double* lam_w;       // 3 x count, by particle id
+    double* lam_x;       // 3 x count, by particle id (by_id) or storage position
+    double* lam_w;       // 3 x count, likewise
     double* lam_bext;    // 3, accumulated
+    int by_id;
 };
 
 // Reverse of the momentum advance (Appendix, Eq. p2): recompute the forward
@@ -465,7 +466,7 @@ __device__ __forceinline__ void scatter_comp(Acc& acc, const Axis<double> (&w)[3
 // fields it gathered; add those into lambda_E, lambda_B (acc) and lbp.
 template <int D, class Acc>
 __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, Acc& acc, const int i0[3],
-                                             const double d0[3], const double w0[3], double qp, int64_t id,
+                                             const double d0[3], const double w0[3], double qp, int64_t li,
                                              double lbp[3])
 {
     const double c = g.c, c2 = c * c;
@@ -535,13 +536,13 @@ __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, A
     // x^{n+1} = x^n + V(w^{n+1/2}): d1 = d0 + disp - delta
     double ld1[3] = {0.0, 0.0, 0.0}, ld0[3] = {0.0, 0.0, 0.0};
     for (int ax = 0; ax < D; ++ax) {
-        ld1[ax] = a.lam_x[ax * a.count + id] + gd1[ax];
+        ld1[ax] = a.lam_x[ax * a.count + li] + gd1[ax];
         ld0[ax] = gd0[ax] + ld1[ax];
     }
     const double inv3 = inv * inv * inv;
     double lw1[3];
     for (int k = 0; k < 3; ++k) {
-        lw1[k] = a.lam_w[k * a.count + id];
+        lw1[k] = a.lam_w[k * a.count + li];
         if (D == 2) lw1[k] += ljz * jzc * ((k == 2 ? inv : 0.0) - w1[2] * w1[k] * inv3);
         for (int ax = 0; ax < D; ++ax)
             lw1[k] += ld1[ax] * g.cfl[ax] * ((ax == k ? inv : 0.0) - w1[ax] * w1[k] * inv3);
@@ -568,13 +569,13 @@ __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, A
     scatter_comp<D, 5>(acc, wv0, lB[2]);
     for (int k = 0; k < 3; ++k) lbp[k] += lB[k];
 
-    for (int ax = 0; ax < 3; ++ax) a.lam_x[ax * a.count + id] = ax < D ? ld0[ax] : 0.0;
-    for (int k = 0; k < 3; ++k) a.lam_w[k * a.count + id] = lw0[k];
+    for (int ax = 0; ax < 3; ++ax) a.lam_x[ax * a.count + li] = ax < D ? ld0[ax] : 0.0;
+    for (int k = 0; k < 3; ++k) a.lam_w[k * a.count + li] = lw0[k];
 }
 
 template <int D>
 __device__ __forceinline__ void load_particle(const AdjArgs& a, int64_t p, int i0[3], double d0[3],
-                                              double w0[3], double& qp, int64_t& id)
+                                              double w0[3], double& qp, int64_t& li)
 {
     for (int ax = 0; ax < 3; ++ax) {
         i0[ax] = 0;
@@ -586,7 +587,7 @@ __device__ __forceinline__ void load_particle(const AdjArgs& a, int64_t p, int i
         i0[ax] = (int)fl;
         d0[ax] = x - fl;
     }
-    id = a.id[p];
+    li = a.by_id ? a.id[p] : p;  // where the particle's adjoint is kept
     for (int k = 0; k < 3; ++k) w0[k] = a.mom[k][p];
     qp = a.q * a.weight[p];
 }
@@ -613,10 +614,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_particles(GridK g, AdjArgs 
     if (p < a.n) {
         int i0[3];
         double d0[3], w0[3], qp;
-        int64_t id;
-        load_particle<D>(a, p, i0, d0, w0, qp, id);
+        int64_t li;
+        load_particle<D>(a, p, i0, d0, w0, qp, li);
         GlobalAcc<D> acc(g, a);
-        adj_particle<D>(g, a, acc, i0, d0, w0, qp, id, lbp);
+        adj_particle<D>(g, a, acc, i0, d0, w0, qp, li, lbp);
     }
     flush_bext(sb, lbp, a.lam_bext);
 }
@@ -692,8 +693,8 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
     for (int64_t p = begin + part * kAdjThreads + threadIdx.x; p < end; p += (int64_t)split * kAdjThreads) {
         int i0[3];
         double d0[3], w0[3], qp;
-        int64_t id;
-        load_particle<2>(a, p, i0, d0, w0, qp, id);
+        int64_t li;
+        load_particle<2>(a, p, i0, d0, w0, qp, li);
         int rel[2];
         bool inside = true;
         for (int ax = 0; ax < 2; ++ax) {
@@ -711,10 +712,10 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
             acc.sacc = sacc;
             acc.r0 = rel[0];
             acc.r1 = rel[1];
-            adj_particle<2>(g, a, acc, i0, d0, w0, qp, id, lbp);
+            adj_particle<2>(g, a, acc, i0, d0, w0, qp, li, lbp);
         } else {
             GlobalAcc<2> acc(g, a);
-            adj_particle<2>(g, a, acc, i0, d0, w0, qp, id, lbp);
+            adj_particle<2>(g, a, acc, i0, d0, w0, qp, li, lbp);
         }
     }
     __syncthreads();
@@ -839,6 +840,29 @@ __global__ __launch_bounds__(256) void k_copy_segments(CopySegs segs)
     }
 }
 
+// Particle adjoints from one order to another: pos_from[id] = k for the
+// particle at position k of the source order (k_inverse), then
+// out[j] = in[pos_from[id_to[j]]] (k_permute).  A null id array is id order.
+__global__ __launch_bounds__(256) void k_inverse(const int64_t* __restrict__ id, int64_t n, uint32_t* __restrict__ pos)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) pos[id[k]] = (uint32_t)k;
+}
+
+__global__ __launch_bounds__(256) void k_permute(const int64_t* __restrict__ id_to, const uint32_t* __restrict__ pos_from,
+                                              int64_t n, const double* __restrict__ in_x, const double* __restrict__ in_w,
+                                              double* __restrict__ out_x, double* __restrict__ out_w)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int64_t pid = id_to ? id_to[j] : j;
+    const int64_t src = pos_from ? (int64_t)pos_from[pid] : pid;
+    for (int k = 0; k < 3; ++k) {
+        out_x[k * n + j] = in_x[k * n + src];
+        out_w[k * n + j] = in_w[k * n + src];
+    }
+}
+
 }  // namespace
 
 size_t adjoint_record_bytes(const Ctx& c) { return carve_record(c, nullptr, nullptr); }
@@ -870,7 +894,29 @@ hipError_t launch_adjoint_record(const Ctx& c, void* record, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const Ctx& c, const void* record, double* lam, double* const* lam_x,
+hipError_t launch_adjoint_reorder(Ctx& c, const void* from, const void* to, const double* const* in_x,
+                                  const double* const* in_w, double* const* out_x, double* const* out_w,
+                                  hipStream_t s)
+{
+    StateView vf{}, vt{};
+    if (from) carve_record(c, (char*)from, &vf);
+    if (to) carve_record(c, (char*)to, &vt);
+    for (int i = 0; i < c.nsp; ++i) {
+        Species& sp = c.sp[i];
+        if (!sp.d.mobile || sp.n == 0) continue;
+        const unsigned pb = (unsigned)((sp.n + 255) / 256);
+        uint32_t* pos = nullptr;
+        if (from) {
+            pos = sp.key;  // sort scratch, capacity >= n entries
+            hipLaunchKernelGGL(k_inverse, dim3(pb), dim3(256), 0, s, vf.sp[i].id, sp.n, pos);
+        }
+        hipLaunchKernelGGL(k_permute, dim3(pb), dim3(256), 0, s, to ? vt.sp[i].id : nullptr, pos, sp.n, in_x[i],
+                           in_w[i], out_x[i], out_w[i]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Ctx& c, const void* record, bool by_id, double* lam, double* const* lam_x,
                                double* const* lam_w, double* lam_bext, hipStream_t s)
 {
     StateView v{};
@@ -904,12 +950,13 @@ hipError_t launch_adjoint_step(const Ctx& c, const void* record, double* lam, do
         a.lam_x = lam_x[i];
         a.lam_w = lam_w[i];
         a.lam_bext = lam_bext;
+        a.by_id = by_id ? 1 : 0;
         const unsigned pb = (unsigned)((sp.n + kAdjThreads - 1) / kAdjThreads);
         if (c.k.dims == 3) {
             hipLaunchKernelGGL(k_adj_particles<3>, dim3(pb), dim3(kAdjThreads), 0, s, c.k, a);
         } else if (pv.tiles) {
             // enough workgroups to fill the chip: several per tile when tiles are few
-            const int split = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + c.k.ntiles - 1) / c.k.ntiles));
+            const int split = (int)std::min<int64_t>(8, std::max<int64_t>(1, (512 + c.k.ntiles - 1) / c.k.ntiles));
             hipLaunchKernelGGL(k_adj_tile2, dim3((unsigned)(c.k.ntiles * split)), dim3(kAdjThreads), 0, s, c.k, a,
                                pv.tile_start, split);
         } else {

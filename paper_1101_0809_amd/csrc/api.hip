@@ -465,8 +465,9 @@ int pic_adjoint_seed_field_energy(pic_ctx* ctx, double* lam_fields, void* stream
     return PIC_OK;
 }
 
-static int adjoint_step_common(pic_ctx* ctx, const void* record, size_t record_bytes, double* lam_fields,
-                               double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream)
+static int adjoint_step_common(pic_ctx* ctx, const void* record, size_t record_bytes, bool by_id,
+                               double* lam_fields, double* const* lam_x, double* const* lam_w, double* lam_bext,
+                               void* stream)
 {
     if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
     Ctx& c = ctx->c;
@@ -478,7 +479,7 @@ static int adjoint_step_common(pic_ctx* ctx, const void* record, size_t record_b
             return fail(&c, PIC_EINVAL, "null particle adjoint of a mobile species");
     if (record && record_bytes < adjoint_record_bytes(c))
         return fail(&c, PIC_ESIZE, "record smaller than pic_adjoint_record_bytes");
-    hipError_t e = launch_adjoint_step(c, record, lam_fields, lam_x, lam_w, lam_bext, (hipStream_t)stream);
+    hipError_t e = launch_adjoint_step(c, record, by_id, lam_fields, lam_x, lam_w, lam_bext, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(&c, e, "adjoint_step");
     return PIC_OK;
 }
@@ -486,7 +487,7 @@ static int adjoint_step_common(pic_ctx* ctx, const void* record, size_t record_b
 int pic_adjoint_step(pic_ctx* ctx, double* lam_fields, double* const* lam_x, double* const* lam_w,
                      double* lam_bext, void* stream)
 {
-    return adjoint_step_common(ctx, nullptr, 0, lam_fields, lam_x, lam_w, lam_bext, stream);
+    return adjoint_step_common(ctx, nullptr, 0, true, lam_fields, lam_x, lam_w, lam_bext, stream);
 }
 
 int pic_adjoint_record_bytes(const pic_ctx* ctx, size_t* bytes)
@@ -513,7 +514,38 @@ int pic_adjoint_step_record(pic_ctx* ctx, const void* record, size_t bytes, doub
                             double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream)
 {
     if (!record) return fail(ctx ? &ctx->c : nullptr, PIC_EINVAL, "null record");
-    return adjoint_step_common(ctx, record, bytes, lam_fields, lam_x, lam_w, lam_bext, stream);
+    return adjoint_step_common(ctx, record, bytes, true, lam_fields, lam_x, lam_w, lam_bext, stream);
+}
+
+int pic_adjoint_step_record_ordered(pic_ctx* ctx, const void* record, size_t bytes, double* lam_fields,
+                                    double* const* lam_x, double* const* lam_w, double* lam_bext, void* stream)
+{
+    if (!record) return fail(ctx ? &ctx->c : nullptr, PIC_EINVAL, "null record");
+    return adjoint_step_common(ctx, record, bytes, false, lam_fields, lam_x, lam_w, lam_bext, stream);
+}
+
+int pic_adjoint_reorder(pic_ctx* ctx, const void* from, const void* to, size_t bytes,
+                        const double* const* in_x, const double* const* in_w, double* const* out_x,
+                        double* const* out_w, void* stream)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    const int r = adjoint_ready(c);
+    if (r != PIC_OK) return r;
+    if (!in_x || !in_w || !out_x || !out_w) return fail(&c, PIC_EINVAL, "null particle adjoint array");
+    for (int i = 0; i < c.nsp; ++i) {
+        const Species& sp = c.sp[i];
+        if (!sp.d.mobile || sp.n == 0) continue;
+        if (!in_x[i] || !in_w[i] || !out_x[i] || !out_w[i])
+            return fail(&c, PIC_EINVAL, "null particle adjoint of a mobile species");
+        if (in_x[i] == out_x[i] || in_w[i] == out_w[i] || in_x[i] == out_w[i] || in_w[i] == out_x[i])
+            return fail(&c, PIC_EINVAL, "reorder is out of place: input and output must differ");
+    }
+    if ((from || to) && bytes < adjoint_record_bytes(c))
+        return fail(&c, PIC_ESIZE, "record smaller than pic_adjoint_record_bytes");
+    hipError_t e = launch_adjoint_reorder(c, from, to, in_x, in_w, out_x, out_w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(&c, e, "adjoint_reorder");
+    return PIC_OK;
 }
 
 int pic_diagnostics(pic_ctx* ctx, pic_diag* out, void* stream)

@@ -146,8 +146,15 @@ hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
 hipError_t launch_adjoint_seed(const Ctx& c, double* lam, hipStream_t s);
 // record == nullptr: the state before the step is the context's own; else a
 // record written by launch_adjoint_record.
-hipError_t launch_adjoint_step(const Ctx& c, const void* record, double* lam, double* const* lam_x,
+// by_id: particle adjoints indexed by id; else by storage position (of the
+// record, or of the context).
+hipError_t launch_adjoint_step(const Ctx& c, const void* record, bool by_id, double* lam, double* const* lam_x,
                                double* const* lam_w, double* lam_bext, hipStream_t s);
+// Particle adjoints from the storage order of record `from` to that of `to`
+// (null: id order); uses the species' sort-key scratch.
+hipError_t launch_adjoint_reorder(Ctx& c, const void* from, const void* to, const double* const* in_x,
+                                  const double* const* in_w, double* const* out_x, double* const* out_w,
+                                  hipStream_t s);
 size_t adjoint_record_bytes(const Ctx& c);
 hipError_t launch_adjoint_record(const Ctx& c, void* record, hipStream_t s);
 

@@ -289,12 +289,28 @@ class Sim:
                 px[i], pw[i] = lam_x[i].data_ptr(), lam_w[i].data_ptr()
         return px, pw
 
+    def host_state(self):
+        hs = L.HostState()
+        self._check(self.lib.pic_get_host_state(self.ctx, ctypes.byref(hs)))
+        return hs
+
+    def adjoint_reorder(self, src, dst, lam_x: list, lam_w: list, out_x: list, out_w: list):
+        """Particle adjoints from the storage order of record src to that of
+        record dst (None: id order), out of place."""
+        px, pw = self._lam_ptrs(lam_x, lam_w)
+        ox, ow = self._lam_ptrs(out_x, out_w)
+        nb = src.numel() if src is not None else (dst.numel() if dst is not None else 0)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+        self._check(self.lib.pic_adjoint_reorder(self.ctx, ptr(src), ptr(dst), nb, px, pw, ox, ow, _stream()))
+
     def adjoint_step_record(self, record: torch.Tensor, lam_fields: torch.Tensor, lam_x: list,
-                            lam_w: list, lam_bext: torch.Tensor):
-        """adjoint_step with the state before the step taken from a record."""
+                            lam_w: list, lam_bext: torch.Tensor, ordered: bool = False):
+        """adjoint_step with the state before the step taken from a record;
+        ordered: particle adjoints by position in the record instead of id."""
         px, pw = self._lam_ptrs(lam_x, lam_w)
         assert lam_fields.numel() == 6 * self.ncell and lam_bext.numel() == 3
-        self._check(self.lib.pic_adjoint_step_record(
+        fn = self.lib.pic_adjoint_step_record_ordered if ordered else self.lib.pic_adjoint_step_record
+        self._check(fn(
             self.ctx, ctypes.c_void_p(record.data_ptr()), record.numel(),
             ctypes.c_void_p(lam_fields.data_ptr()), px, pw, ctypes.c_void_p(lam_bext.data_ptr()),
             _stream()))

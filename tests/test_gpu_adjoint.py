@@ -229,6 +229,48 @@ def test_record_step_equals_context_step(dims):
     sim.close()
 
 
+def test_ordered_step_and_reorder():
+    """pic_adjoint_reorder from id order to a record's storage order is the
+    gather by the record's ids and back again the identity; the ordered
+    reverse step on reordered adjoints equals the id-order step."""
+    from paper_1101_0809_amd import Sim
+    box, n = (21, 18, 1), 1501
+    x, w, weight = picgen.beams(box, n, 140, w_th=0.3, drift=0.2, dims=2)
+    sim = Sim(nx=21, ny=18, nz=1, dt=0.5, dims=2, sort_every=3, fields=_fields((1, 18, 21), 141, 0.05))
+    sim.add_species(-1.0, 1.0, capacity=n)
+    sim.load(0, x, w, weight)
+    sim.step(2)
+    dev = torch.device("cuda:0")
+    rec = torch.empty(sim.adjoint_record_bytes(), dtype=torch.uint8, device=dev)
+    sim.adjoint_record(rec)
+    _, _, _, ids = sim.particles(0, raw=True)
+    rng = np.random.Generator(np.random.PCG64(142))
+    lx0 = torch.tensor(rng.normal(size=(3, n)), device=dev)
+    lw0 = torch.tensor(rng.normal(size=(3, n)), device=dev)
+    lf0 = torch.tensor(rng.normal(size=6 * sim.ncell), device=dev)
+    ox, ow = torch.empty_like(lx0), torch.empty_like(lw0)
+    sim.adjoint_reorder(None, rec, [lx0], [lw0], [ox], [ow])
+    assert np.array_equal(ox.cpu().numpy(), lx0.cpu().numpy()[:, ids])
+    assert np.array_equal(ow.cpu().numpy(), lw0.cpu().numpy()[:, ids])
+    bx, bw = torch.empty_like(lx0), torch.empty_like(lw0)
+    sim.adjoint_reorder(rec, None, [ox], [ow], [bx], [bw])
+    assert torch.equal(bx, lx0) and torch.equal(bw, lw0)
+    # id-order step vs ordered step on the reordered adjoints
+    lf_a, lx_a, lw_a = lf0.clone(), lx0.clone(), lw0.clone()
+    lb_a = torch.zeros(3, dtype=torch.float64, device=dev)
+    sim.adjoint_step_record(rec, lf_a, [lx_a], [lw_a], lb_a)
+    lf_b = lf0.clone()
+    lb_b = torch.zeros(3, dtype=torch.float64, device=dev)
+    sim.adjoint_step_record(rec, lf_b, [ox], [ow], lb_b, ordered=True)
+    sim.adjoint_reorder(rec, None, [ox], [ow], [bx], [bw])
+    for a, b in ((lf_a, lf_b), (lx_a, bx), (lw_a, bw), (lb_a, lb_b)):
+        _close(a.cpu().numpy(), b.cpu().numpy(), 1e-13)
+    from paper_1101_0809_amd._lib import PicError
+    with pytest.raises(PicError):
+        sim.adjoint_reorder(None, rec, [ox], [ow], [ox], [bw])  # in place
+    sim.close()
+
+
 def test_adjoint_rejects_fp32_mode():
     from paper_1101_0809_amd import Sim
     from paper_1101_0809_amd._lib import PicError
