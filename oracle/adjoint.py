@@ -3,8 +3,9 @@
 A second plain FP64 CPU implementation of the particle-in-cell step of
 Sokolov, arXiv:1101.0809 (the Appendix algorithm), written in PyTorch tensor
 operations so that ``torch.autograd`` differentiates it exactly: the gradient
-of the final field energy with respect to the initial momenta and to the
-external uniform magnetic field.  Only the tests use it; it shares no code
+of the final field energy with respect to the initial momenta, the initial
+positions and the external uniform magnetic field, and the vector-Jacobian
+product of one step.  Only the tests use it; it shares no code
 with the GPU path.  It follows the readings of the C oracle (``pic_oracle.c``)
 and the tests check its forward step against that oracle, and its gradient
 against central differences of that oracle.

@@ -56,6 +56,15 @@ def _forward(sim: Sim, nsteps: int, seg: int):
     """Step the context nsteps times from its current state.  Returns the
     checkpoints [(length, state copy)] and, for a single segment, its tape
     with the steps that sorted."""
+    # a species not yet sorted (just loaded) would be sorted by its first
+    # step anyway; sorting it now only reorders storage, and lets the reverse
+    # step of that first step use the tiled kernel
+    hs = sim.host_state()
+    if any(not hs.sorted[i] for i, s in enumerate(sim.species) if s.mobile):
+        sim.sort()
+        after = sim.host_state()
+        after.since_sort = hs.since_sort  # keep the periodic sorts where they were
+        sim.set_host_state(after)
     if seg >= nsteps:
         tape = _tape(sim, max(1, nsteps))
         sorted_at = [_step_recorded(sim, tape[i]) for i in range(nsteps)]

@@ -163,10 +163,14 @@ __device__ __forceinline__ void curl_d(const GridK& g, const double* B, const Ce
     out[2] = cx * (By[c.ip] - By[c.p]) - cy * (Bx[c.jp] - Bx[c.p]);
 }
 
-// B^n of the state (E^n, B^{n-1/2}) into bn, the state untouched.  Same
-// expression as the step's first half step.
-__global__ __launch_bounds__(kCurlThreads) void k_adj_bn(GridK g, const double* __restrict__ f,
-                                                         double* __restrict__ bn)
+// First kernel of a reverse step, per cell: B^n of the state (E^n,
+// B^{n-1/2}) into bn (same expression as the step's first half step; the
+// state is untouched); lambda_J = -4 pi dt lambda_E'; lambda_B <- lambda_B' +
+// C lambda_E' (the transpose of D is C: both are the curl, with backward and
+// forward differences).
+__global__ __launch_bounds__(kCurlThreads) void k_adj_pre(GridK g, const double* __restrict__ f,
+                                                          double* __restrict__ bn, const double* __restrict__ lamE,
+                                                          double* __restrict__ lamB, double* __restrict__ lamJ)
 {
     const int64_t p = (int64_t)blockIdx.x * kCurlThreads + threadIdx.x;
     if (p >= g.ncell) return;
@@ -177,18 +181,6 @@ __global__ __launch_bounds__(kCurlThreads) void k_adj_bn(GridK g, const double* 
     bn[p] = f[3 * N + p] - hy * (Ez[p] - Ez[c.jm]) + hz * (Ey[p] - Ey[c.km]);
     bn[N + p] = f[4 * N + p] - hz * (Ex[p] - Ex[c.km]) + hx * (Ez[p] - Ez[c.im]);
     bn[2 * N + p] = f[5 * N + p] - hx * (Ey[p] - Ey[c.im]) + hy * (Ex[p] - Ex[c.jm]);
-}
-
-// lambda_J = -4 pi dt lambda_E';  lambda_B <- lambda_B' + C lambda_E' (the
-// transpose of D is C: both are the curl, with backward and forward differences).
-__global__ __launch_bounds__(kCurlThreads) void k_adj_pre(GridK g, const double* __restrict__ lamE,
-                                                          double* __restrict__ lamB,
-                                                          double* __restrict__ lamJ)
-{
-    const int64_t p = (int64_t)blockIdx.x * kCurlThreads + threadIdx.x;
-    if (p >= g.ncell) return;
-    const int64_t N = g.ncell;
-    const CellNb c = neighbours(p, g);
     double ce[3];
     curl_c(g, lamE, c, ce);
     for (int k = 0; k < 3; ++k) {
@@ -629,7 +621,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_particles(GridK g, AdjArgs 
 // added to the grid once at the end; a particle more than M cells outside its
 // tile (it moved since the sort) uses the global-memory accessor instead.
 constexpr int kAdjT2 = kTile2;
-constexpr int kAdjM2 = 2;
+constexpr int kAdjM2 = 3;
 constexpr int kAdjLF2 = kAdjT2 + 2 + 2 * kAdjM2;
 constexpr int kAdjLJ2 = kAdjT2 + 4 + 2 * kAdjM2;
 constexpr int kAdjNF2 = kAdjLF2 * kAdjLF2;
@@ -924,8 +916,7 @@ hipError_t launch_adjoint_step(const Ctx& c, const void* record, bool by_id, dou
     else v = context_view(c);
     const int64_t N = c.k.ncell;
     const unsigned b = cells_blocks(N);
-    hipLaunchKernelGGL(k_adj_bn, dim3(b), dim3(kCurlThreads), 0, s, c.k, v.fields, c.bn);
-    hipLaunchKernelGGL(k_adj_pre, dim3(b), dim3(kCurlThreads), 0, s, c.k, lam, lam + 3 * N, c.adj);
+    hipLaunchKernelGGL(k_adj_pre, dim3(b), dim3(kCurlThreads), 0, s, c.k, v.fields, c.bn, lam, lam + 3 * N, c.adj);
     hipLaunchKernelGGL(k_adj_curl, dim3(b), dim3(kCurlThreads), 0, s, c.k, lam, lam + 3 * N);
     for (int i = 0; i < c.nsp; ++i) {
         const Species& sp = c.sp[i];

@@ -381,9 +381,12 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
     hipError_t e = ensure_sorted(c, s);
     if (e == hipSuccess) e = ensure_r0(c, s);
     if (e != hipSuccess) return hip_fail(&c, e, "step setup");
-    // fallback statistics of this call (pic_last_fallback_fraction)
-    e = zero_counters(c.counters + 1, 2, s);
-    if (e != hipSuccess) return hip_fail(&c, e, "step");
+    // fallback statistics of this call (pic_last_fallback_fraction), zeroed
+    // by the first field kernel of the call
+    if (nsteps == 0) {
+        e = zero_counters(c.counters + 1, 2, s);
+        if (e != hipSuccess) return hip_fail(&c, e, "step");
+    }
     for (int it = 0; it < nsteps; ++it) {
         const bool timed = ctx->timing_used < ctx->timing_cap;
         hipEvent_t* ev = timed ? &ctx->ev[5 * (size_t)ctx->timing_used] : nullptr;
@@ -393,7 +396,7 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
         // both B half steps use E^n: one kernel writes B^n (for the particles)
         // to the workspace and B^{n+1/2} in place
         mark(0);
-        if (e == hipSuccess) e = launch_field_half_b_pair(c, s);
+        if (e == hipSuccess) e = launch_field_half_b_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 2 : 0);
         mark(1);
         for (int i = 0; i < c.nsp && e == hipSuccess; ++i)
             if (c.sp[i].d.mobile) e = launch_particle_step(c, c.sp[i], s);

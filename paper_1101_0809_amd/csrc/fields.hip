@@ -9,6 +9,8 @@
 // are re-reads of rows that the same or a neighbouring workgroup just fetched
 // and are served from L2.  Both kernels are HBM-bound (9 or 12 FP64 values
 // moved per cell).
+#include <algorithm>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -63,9 +65,11 @@ __global__ __launch_bounds__(kFieldThreads) void k_half_b(GridK g, double* __res
 // B^{n-1/2} - (1/2) curl_h E^n to bn, then B^{n+1/2} = B^n - (1/2) curl_h E^n
 // in place, each half step with the same expression and rounding as k_half_b.
 __global__ __launch_bounds__(kFieldThreads) void k_half_b_pair(GridK g, double* __restrict__ f,
-                                                               double* __restrict__ bn)
+                                                               double* __restrict__ bn,
+                                                               unsigned long long* __restrict__ zero, int nzero)
 {
     const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
+    if (p < nzero) zero[p] = 0;  // counters of the particle kernels that follow
     if (p >= g.ncell) return;
     const CellIdx c = cell_of(p, g);
     const int64_t N = g.ncell;
@@ -182,10 +186,10 @@ hipError_t launch_field_half_b(const Ctx& c, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s)
+hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s, unsigned long long* zero, int nzero)
 {
-    const unsigned blocks = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
-    hipLaunchKernelGGL(k_half_b_pair, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields, c.bn);
+    const unsigned blocks = (unsigned)((std::max<int64_t>(c.k.ncell, nzero) + kFieldThreads - 1) / kFieldThreads);
+    hipLaunchKernelGGL(k_half_b_pair, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields, c.bn, zero, nzero);
     if (c.k.src_kind == 1)  // the line's two half steps, after the grid kernel read its E^y
         hipLaunchKernelGGL(k_aux_half_b_pair, dim3(1), dim3(kFieldThreads), 0, s, c.k);
     return hipGetLastError();

@@ -128,7 +128,9 @@ size_t align_up(size_t v, size_t a);
 
 // ---- launchers (stream = hipStream_t) ----
 hipError_t launch_field_half_b(const Ctx& c, hipStream_t s);
-hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s);
+// Both B half steps of a step; also zeroes zero[0 .. nzero) first (counters).
+hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s, unsigned long long* zero = nullptr,
+                                    int nzero = 0);
 hipError_t launch_field_update_e(const Ctx& c, hipStream_t s, int64_t step);
 hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_load(Ctx& c, Species& sp, int64_t n, const double* x, const double* w,

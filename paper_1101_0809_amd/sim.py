@@ -294,6 +294,9 @@ class Sim:
         self._check(self.lib.pic_get_host_state(self.ctx, ctypes.byref(hs)))
         return hs
 
+    def set_host_state(self, hs):
+        self._check(self.lib.pic_set_host_state(self.ctx, ctypes.byref(hs)))
+
     def adjoint_reorder(self, src, dst, lam_x: list, lam_w: list, out_x: list, out_w: list):
         """Particle adjoints from the storage order of record src to that of
         record dst (None: id order), out of place."""

@@ -279,3 +279,66 @@ def test_adjoint_rejects_fp32_mode():
     with pytest.raises(PicError):
         sim.adjoint_seed_field_energy(lam)
     sim.close()
+
+
+def test_full_size_2d_beams_gradient_matches_central_differences():
+    """The differentiable workload at its full size (2D3V 256 x 256, 1,048,576
+    electrons in two beams drifting at +-0.2 c, B_z = 0.02, 200 steps): the
+    tape gradient against central differences (h = 1e-6) of the GPU forward
+    pass on B_z, on 6 random momentum components and along 2 random
+    directions of all momenta, and against the checkpointed gradient (every
+    20 steps).  Reruns of the forward pass agree to the last bit or two (the
+    order of LDS atomics may change), far below what h = 1e-6 resolves, so
+    the differences carry truncation error: measured about 1e-5 relative on
+    B_z and the directions and 2e-7 of the largest component on single
+    components."""
+    from paper_1101_0809_amd import Sim
+    from paper_1101_0809_amd.adjoint import field_energy_grad
+    wl = picgen.WORKLOADS["2d3v_256sq_beams"]
+    e = picgen.electrons(wl)
+
+    def make(w=None, bext=None):
+        sim = Sim(nx=wl.nx, ny=wl.ny, nz=1, dt=wl.dt, dims=2, sort_every=wl.sort_every,
+                  bext=wl.bext if bext is None else tuple(bext))
+        sim.add_species(-1.0, 1.0, e.n)
+        sim.load(0, e.x, e.w if w is None else w, e.weight)
+        return sim
+
+    def loss(w=None, bext=None):
+        sim = make(w, bext)
+        sim.step(wl.steps)
+        d = sim.diagnostics()
+        sim.close()
+        return d["field_e"] + d["field_b"]
+
+    sim = make()
+    L, gx, gw, gb = field_energy_grad(sim, wl.steps)
+    sim.close()
+    gw = gw[0].cpu().numpy()
+    gb = gb.cpu().numpy()
+    sim = make()
+    L2, _, gw2, gb2 = field_energy_grad(sim, wl.steps, every=20)
+    sim.close()
+    assert abs(L2 - L) <= 1e-12 * L
+    _close(gw2[0].cpu().numpy(), gw, 1e-10)
+    _close(gb2.cpu().numpy(), gb, 1e-10)
+    assert abs(loss() - L) <= 1e-12 * L
+    h = 1e-6
+    b = np.array(wl.bext)
+    fd = (loss(bext=b + [0, 0, h]) - loss(bext=b - [0, 0, h])) / (2 * h)
+    assert abs(gb[2] - fd) <= 1e-4 * abs(fd), (gb[2], fd)
+    scale = np.max(np.abs(gw))
+    rng = np.random.Generator(np.random.PCG64(7))
+    for _ in range(6):
+        c, p = int(rng.integers(0, 3)), int(rng.integers(0, e.n))
+        wp, wm = e.w.copy(), e.w.copy()
+        wp[c, p] += h
+        wm[c, p] -= h
+        fd = (loss(wp) - loss(wm)) / (2 * h)
+        assert abs(gw[c, p] - fd) <= 1e-5 * scale, (c, p, gw[c, p], fd)
+    for _ in range(2):
+        d = rng.normal(size=e.w.shape)
+        d /= np.linalg.norm(d)
+        fd = (loss(e.w + h * d) - loss(e.w - h * d)) / (2 * h)
+        an = float(np.sum(gw * d))
+        assert abs(an - fd) <= 1e-4 * abs(an), (an, fd)
