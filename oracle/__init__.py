@@ -46,7 +46,7 @@ class _Grid(ctypes.Structure):
                 ("bext", ctypes.c_double * 3),
                 ("src_kind", ctypes.c_int64), ("src_plane", ctypes.c_int64),
                 ("src_amp", ctypes.c_double), ("src_omega", ctypes.c_double),
-                ("src_ramp", ctypes.c_double)]
+                ("src_ramp", ctypes.c_double), ("order", ctypes.c_int64)]
 
 
 class _Species(ctypes.Structure):
@@ -66,6 +66,7 @@ def lib():
         sig = {
             "orc_shape": (d, [ctypes.c_int, d]),
             "orc_cumulative1": (d, [d]),
+            "orc_cumulative2": (d, [d]),
             "orc_gather": (None, [g, p, p, p, p]),
             "orc_push": (None, [d, d, d, p, p, p]),
             "orc_displacement": (None, [g, p, p]),
@@ -110,6 +111,7 @@ class Grid:
     c: float = 1.0
     bext: tuple = (0.0, 0.0, 0.0)
     source: tuple = None   # (plane, amplitude, omega, ramp time): +x plane wave, E^y
+    order: int = 1         # alternating order l_a = order + 1/2 (Section 4.5): 1 or 2
 
     @property
     def shape(self):
@@ -123,6 +125,7 @@ class Grid:
         g = _Grid()
         g.nx, g.ny, g.nz = self.nx, self.ny, self.nz
         g.dx, g.dy, g.dz, g.dt, g.c = self.dx, self.dy, self.dz, self.dt, self.c
+        g.order = int(self.order)
         for a in range(3):
             g.bext[a] = float(self.bext[a])
         if self.source is not None:
@@ -234,6 +237,10 @@ def shape(l: int, r: float) -> float:
 
 def cumulative1(s: float) -> float:
     return lib().orc_cumulative1(s)
+
+
+def cumulative2(s: float) -> float:
+    return lib().orc_cumulative2(s)
 
 
 def gather(grid: Grid, fields: np.ndarray, xp):

@@ -73,12 +73,31 @@ double orc_cumulative1(double s)
     return 1.0;
 }
 
-/* Order-1 1/2 alternating form factor (Section 4.5): at an integer point
- * (node) n it is f^(1)(n - x_p); at a half-integer point (cell centre c+1/2)
- * it is Delta F_{c+1/2}(x_p) = f^(2)(c + 1/2 - x_p). */
-static double node_w(long n, double xp) { return orc_shape(1, (double)n - xp); }
-static double cell_w(long c, double xp) { return orc_shape(2, (double)c + 0.5 - xp); }
-static double cumul(long n, double xp) { return orc_cumulative1((double)n - xp); }
+/* Integral of f^(2) from -infinity to s (the cumulative form factor of order
+ * 2, for the order-2 1/2 current). */
+double orc_cumulative2(double s)
+{
+    if (s <= -1.5) return 0.0;
+    if (s <= -0.5) return (1.5 + s) * (1.5 + s) * (1.5 + s) / 6.0;
+    if (s <= 0.5) return 1.0 / 6.0 + 0.75 * (s + 0.5) - (s * s * s + 0.125) / 3.0;
+    if (s < 1.5) return 1.0 - (1.5 - s) * (1.5 - s) * (1.5 - s) / 6.0;
+    return 1.0;
+}
+
+/* Alternating form factor of order l + 1/2 (Section 4.5), l = g->order: at
+ * an integer point (node) n it is f^(l)(n - x_p); at a half-integer point
+ * (cell centre c+1/2) it is Delta F_{c+1/2}(x_p) = f^(l+1)(c + 1/2 - x_p);
+ * the current uses the cumulative F_n of f^(l) (Section 3.1). */
+static int order_of(const orc_grid* g) { return g->order == 2 ? 2 : 1; }
+static double node_w(const orc_grid* g, long n, double xp) { return orc_shape(order_of(g), (double)n - xp); }
+static double cell_w(const orc_grid* g, long c, double xp)
+{
+    return orc_shape(order_of(g) + 1, (double)c + 0.5 - xp);
+}
+static double cumul(const orc_grid* g, long n, double xp)
+{
+    return order_of(g) == 2 ? orc_cumulative2((double)n - xp) : orc_cumulative1((double)n - xp);
+}
 
 static long wrap(long i, long n)
 {
@@ -102,9 +121,12 @@ static size_t ncell(const orc_grid* g) { return (size_t)g->nx * g->ny * g->nz; }
  * every weight; weights outside the support are exactly zero.
  * ------------------------------------------------------------------------- */
 /* Summation boxes: offsets -BOX_LO .. +BOX_HI from floor(x_p) contain every
- * node with a non-zero f_i (offsets 0, 1) and every cell with a non-zero
- * Delta F (offsets -1, 0, 1) of the order-1 1/2 form factor; the extra
- * entries get exactly zero weight. */
+ * node with a non-zero f_i (order 1 1/2: offsets 0, 1; order 2 1/2: -1..2)
+ * and every cell with a non-zero Delta F (-1..1; -2..2); the extra entries
+ * get exactly zero weight.  For the current the box runs from floor of the
+ * lower end point to floor of the upper one, widened the same way, which
+ * holds every node whose cumulative F changes (F_n(x) is constant outside
+ * |n - x| < 1 resp. 3/2). */
 #define BOX_LO 2
 #define BOX_HI 2
 
@@ -122,8 +144,8 @@ void orc_gather(const orc_grid* g, const double* fields, const double xp[3], dou
     for (int a = 0; a < 3; ++a)
         for (int o = 0; o <= BOX_LO + BOX_HI; ++o) {
             long n = base[a] + o - BOX_LO;
-            nw[a][o] = node_w(n, xp[a]);
-            cw[a][o] = cell_w(n, xp[a]);
+            nw[a][o] = node_w(g, n, xp[a]);
+            cw[a][o] = cell_w(g, n, xp[a]);
         }
 
     for (int c = 0; c < 3; ++c) Ep[c] = Bp[c] = 0.0;
@@ -209,13 +231,13 @@ void orc_deposit(const orc_grid* g, const double x0[3], const double x1[3], doub
         int t1 = (comp + 1) % 3, t2 = (comp + 2) % 3; /* transverse axes */
         double pref = -(1.0 / 6.0) * (h[comp] / g->dt) * charge / V;
         for (long a = lo[comp]; a <= hi[comp]; ++a) {
-            double dF = cumul(a, x1[comp]) - cumul(a, x0[comp]);
+            double dF = cumul(g, a, x1[comp]) - cumul(g, a, x0[comp]);
             if (dF == 0.0) continue;
             for (long b = lo[t1]; b <= hi[t1]; ++b) {
-                double s0b = cell_w(b, x0[t1]), s1b = cell_w(b, x1[t1]);
+                double s0b = cell_w(g, b, x0[t1]), s1b = cell_w(g, b, x1[t1]);
                 if (s0b == 0.0 && s1b == 0.0) continue;
                 for (long cc = lo[t2]; cc <= hi[t2]; ++cc) {
-                    double s0c = cell_w(cc, x0[t2]), s1c = cell_w(cc, x1[t2]);
+                    double s0c = cell_w(g, cc, x0[t2]), s1c = cell_w(g, cc, x1[t2]);
                     double brace = 2.0 * (s1b * s1c + s0b * s0c) + s1b * s0c + s0b * s1c;
                     if (brace == 0.0) continue;
                     long ijk[3];
@@ -253,14 +275,14 @@ void orc_deposit_quarter(const orc_grid* g, const double x0[3], const double x1[
         double partial = 0.0; /* sum over cells c < a of dF^-_{c+1/2} */
         for (long a = lo[comp]; a <= hi[comp]; ++a) {
             if (a > lo[comp])
-                partial += cell_w(a - 1, x1[comp]) - cell_w(a - 1, x0[comp]);
+                partial += cell_w(g, a - 1, x1[comp]) - cell_w(g, a - 1, x0[comp]);
             if (partial == 0.0) continue;
             for (long b = lo[t1]; b <= hi[t1]; ++b) {
-                double pb = cell_w(b, x1[t1]) + cell_w(b, x0[t1]);
-                double mb = cell_w(b, x1[t1]) - cell_w(b, x0[t1]);
+                double pb = cell_w(g, b, x1[t1]) + cell_w(g, b, x0[t1]);
+                double mb = cell_w(g, b, x1[t1]) - cell_w(g, b, x0[t1]);
                 for (long cc = lo[t2]; cc <= hi[t2]; ++cc) {
-                    double pc = cell_w(cc, x1[t2]) + cell_w(cc, x0[t2]);
-                    double mc = cell_w(cc, x1[t2]) - cell_w(cc, x0[t2]);
+                    double pc = cell_w(g, cc, x1[t2]) + cell_w(g, cc, x0[t2]);
+                    double mc = cell_w(g, cc, x1[t2]) - cell_w(g, cc, x0[t2]);
                     double tr = pb * pc + mb * mc / 3.0;
                     if (tr == 0.0) continue;
                     long ijk[3];
@@ -281,13 +303,13 @@ void orc_rho_add(const orc_grid* g, const double xp[3], double charge, double* r
     long base[3];
     for (int a = 0; a < 3; ++a) base[a] = (long)floor(xp[a]);
     for (long k = base[2] - BOX_LO; k <= base[2] + BOX_HI; ++k) {
-        double wk = cell_w(k, xp[2]);
+        double wk = cell_w(g, k, xp[2]);
         if (wk == 0.0) continue;
         for (long j = base[1] - BOX_LO; j <= base[1] + BOX_HI; ++j) {
-            double wj = cell_w(j, xp[1]);
+            double wj = cell_w(g, j, xp[1]);
             if (wj == 0.0) continue;
             for (long i = base[0] - BOX_LO; i <= base[0] + BOX_HI; ++i) {
-                double wi = cell_w(i, xp[0]);
+                double wi = cell_w(g, i, xp[0]);
                 if (wi == 0.0) continue;
                 rho[idx(g, i, j, k)] += charge / V * wi * wj * wk;
             }

@@ -22,6 +22,8 @@ typedef struct orc_grid {
      * E0 ramp(t) sin(omega t), ramp = sin^2(pi t / (2 src_ramp)) until src_ramp */
     int64_t src_kind, src_plane;
     double src_amp, src_omega, src_ramp;
+    /* alternating order l_a = order + 1/2 (Section 4.5): 1 (also when 0) or 2 */
+    int64_t order;
 } orc_grid;
 
 #define ORC_AUX 8192  /* auxiliary line length: E^y[ORC_AUX] then B^z[ORC_AUX] */
@@ -39,6 +41,7 @@ typedef struct orc_species {
 
 double orc_shape(int l, double r);
 double orc_cumulative1(double s);
+double orc_cumulative2(double s);
 void orc_gather(const orc_grid* g, const double* fields, const double xp[3], double Ep[3],
                 double Bp[3]);
 void orc_push(double q_over_m, double dt, double c, const double Ep[3], const double Bp[3],

@@ -74,6 +74,15 @@ def test_cumulative_is_integral_of_hat():
         assert oracle.cumulative1(s) == pytest.approx(ref, abs=1e-13)
 
 
+def test_cumulative2_is_integral_of_quadratic():
+    """The order-2 cumulative form factor is the integral of f^(2) (Section
+    3.1 one order up), for the current of the order-2 1/2 scheme."""
+    for s in np.concatenate([RNG.uniform(-2.0, 2.0, 40), [-1.5, -0.5, 0.0, 0.5, 1.5]]):
+        ref, _ = integrate.quad(lambda t: oracle.shape(2, t), -2.0, s, points=[-1.5, -0.5, 0.5, 1.5],
+                                epsabs=1e-14)
+        assert oracle.cumulative2(s) == pytest.approx(ref, abs=1e-13)
+
+
 def test_alternating_order_table_1p5():
     """Oracle point and cell weights equal the printed order-1 1/2 table (Section 4.5)."""
     for xp in RNG.uniform(0, 10, 40):
@@ -105,12 +114,15 @@ def test_alternating_order_table_2p5():
 # Q2-Q4  current and charge (Section 3.2)
 # --------------------------------------------------------------------------
 
-def test_cumulative_sum_identity():
-    """sum_i [F_i(x) - F_i(x')] = x' - x (Eq. sumcurrent)."""
+@pytest.mark.parametrize("order", [1, 2])
+def test_cumulative_sum_identity(order):
+    """sum_i [F_i(x) - F_i(x')] = x' - x (Eq. sumcurrent), for the cumulative
+    of f^(1) and of f^(2)."""
+    F = oracle.cumulative1 if order == 1 else oracle.cumulative2
     for _ in range(30):
         x = RNG.uniform(3, 7)
         xq = x + RNG.uniform(-1.5, 1.5)
-        s = sum(oracle.cumulative1(i - x) - oracle.cumulative1(i - xq) for i in range(-2, 14))
+        s = sum(F(i - x) - F(i - xq) for i in range(-2, 14))
         assert s == pytest.approx(xq - x, abs=1e-14)
 
 
@@ -118,9 +130,10 @@ def _grid(n=8, dt=0.4, **kw):
     return oracle.Grid(n, n, n, dt, **kw)
 
 
-def test_face_sum_equals_velocity():
+@pytest.mark.parametrize("order", [1, 2])
+def test_face_sum_equals_velocity(order):
     """sum over faces of xi^x equals u^x (Section 3.2, exact relationship)."""
-    g = _grid(10, dt=0.37, dx=1.3, dy=0.8, dz=1.1)
+    g = _grid(10, dt=0.37, dx=1.3, dy=0.8, dz=1.1, order=order)
     V = g.dx * g.dy * g.dz
     for _ in range(20):
         x0 = RNG.uniform(2, 8, 3)
@@ -132,19 +145,26 @@ def test_face_sum_equals_velocity():
             assert J[a].sum() * V == pytest.approx(u[a], abs=1e-14)
 
 
-def _box_path_current(x0, x1, n, dt, h):
+def _box_path_current(x0, x1, n, dt, h, order=1):
     """Mean over the six axis orderings of the box-path integrals of Eq. Jx
     (Section 3.2).  F_i and Delta F are obtained by numerical integration of the
-    hat function (their definitions, Eq. intff), not from closed forms."""
+    node form factor f^(order) (their definitions, Eq. intff), not from closed
+    forms: the hat for order 1, the quadratic spline (the hat integrated over
+    a unit cell, done numerically here too) for order 2."""
     hat = lambda t: max(0.0, 1.0 - abs(t))
+    if order == 1:
+        f, knots = hat, (-1.0, 0.0, 1.0)
+    else:
+        f = lambda t: integrate.quad(hat, t - 0.5, t + 0.5, points=[-1.0, 0.0, 1.0], epsabs=1e-15)[0]
+        knots = (-1.5, -0.5, 0.5, 1.5)
 
     def F(i, xp):  # cumulative form factor at node i
-        lo = min(i, xp - 1.0)
-        return integrate.quad(lambda t: hat(t - xp), lo - 1.0, i,
-                              points=[xp - 1, xp, xp + 1], epsabs=1e-15, limit=200)[0]
+        lo = min(i, xp - 2.0)
+        return integrate.quad(lambda t: f(t - xp), lo - 1.0, i,
+                              points=[xp + k for k in knots], epsabs=1e-15, limit=200)[0]
 
     def dF(c, xp):  # integral over the cell [c, c+1]
-        return integrate.quad(lambda t: hat(t - xp), c, c + 1, points=[xp - 1, xp, xp + 1],
+        return integrate.quad(lambda t: f(t - xp), c, c + 1, points=[xp + k for k in knots],
                               epsabs=1e-15, limit=200)[0]
 
     import itertools
@@ -171,16 +191,20 @@ def _box_path_current(x0, x1, n, dt, h):
     return J
 
 
-def test_current_equals_six_box_path_average():
+@pytest.mark.parametrize("order", [1, 2])
+def test_current_equals_six_box_path_average(order):
     """The one-sixth and one-quarter forms of Eq. current both equal the mean of
     the six box-path integrals, computed here from the definitions."""
-    n, dt = 6, 0.45
+    n, dt = 8, 0.45
     h = np.array([1.0, 1.0, 1.0])
-    g = oracle.Grid(n, n, n, dt)
-    for x0, x1 in [(np.array([2.3, 2.7, 3.1]), np.array([2.9, 3.2, 2.6])),
-                   (np.array([3.05, 2.5, 2.95]), np.array([2.4, 2.5, 3.4])),
-                   (np.array([2.5, 2.5, 2.5]), np.array([2.5, 2.5, 2.5]) + 0.2)]:
-        ref = _box_path_current(x0, x1, n, dt, h)
+    g = oracle.Grid(n, n, n, dt, order=order)
+    cases = [(np.array([3.3, 3.7, 4.1]), np.array([3.9, 4.2, 3.6])),
+             (np.array([4.05, 3.5, 3.95]), np.array([3.4, 3.5, 4.4])),
+             (np.array([3.5, 3.5, 3.5]), np.array([3.5, 3.5, 3.5]) + 0.2)]
+    if order == 2:
+        cases = cases[:2]  # nested quadrature: keep the run short
+    for x0, x1 in cases:
+        ref = _box_path_current(x0, x1, n, dt, h, order)
         six = oracle.deposit(g, x0, x1, charge=1.0, form="sixth")
         quarter = oracle.deposit(g, x0, x1, charge=1.0, form="quarter")
         assert np.max(np.abs(six - ref)) < 1e-12
@@ -192,11 +216,12 @@ def _div_face(g, J):
             + (np.roll(J[2], -1, axis=0) - J[2]) / g.dz)
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("form", ["sixth", "quarter"])
-def test_single_particle_continuity(form):
+def test_single_particle_continuity(form, order):
     """(rho^{n+1} - rho^n)/dt + div J = 0 for one particle, any move of less
     than a cell, including moves across the periodic boundary (Eq. chargelaw)."""
-    g = oracle.Grid(7, 6, 5, 0.41, dx=1.2, dy=0.9, dz=1.05)
+    g = oracle.Grid(7, 6, 5, 0.41, dx=1.2, dy=0.9, dz=1.05, order=order)
     x0s, x1s = picgen.random_moves(60, seed=7, box=(7, 6, 5), max_step=0.95)
     for p in range(x0s.shape[1]):
         x0, x1 = x0s[:, p], x1s[:, p]
@@ -212,13 +237,14 @@ def test_single_particle_continuity(form):
 # Q5  whole-run Gauss law and div B invariants (Section 2)
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("shape", [(6, 5, 4), (8, 8, 1)])
-def test_gauss_and_divb_invariant(shape):
+def test_gauss_and_divb_invariant(shape, order):
     nx, ny, nz = shape
     wl = picgen.Workload("pin", nx, ny, nz, 3 if nz > 1 else 2, 0.45, 4, (0.2,) * 3, 0.3, 20)
     e = picgen.electrons(wl)
     ions = picgen.ions_like(wl, e)
-    st = oracle.State(oracle.Grid(nx, ny, nz, wl.dt),
+    st = oracle.State(oracle.Grid(nx, ny, nz, wl.dt, order=order),
                       [oracle.Species(e.x, e.w, e.weight, q=-1.0, m=1.0),
                        oracle.Species(ions.x, ions.w, ions.weight, q=1.0, m=100.0, mobile=False)])
     # start from a non-trivial field with zero divergence of B
@@ -260,9 +286,10 @@ def test_push_pure_electric_kick():
         assert np.allclose(w1, w - 0.25 * E, rtol=0, atol=1e-15)
 
 
-def test_gather_partition_of_unity():
+@pytest.mark.parametrize("order", [1, 2])
+def test_gather_partition_of_unity(order):
     """Uniform grid fields are reproduced exactly at any position (Eq. one)."""
-    g = oracle.Grid(5, 4, 6, 0.3)
+    g = oracle.Grid(5, 4, 6, 0.3, order=order)
     vals = RNG.normal(0, 1, 6)
     fields = np.zeros((9,) + g.shape)
     for c in range(6):
@@ -271,6 +298,40 @@ def test_gather_partition_of_unity():
         xp = RNG.uniform(0, 1, 3) * np.array([5, 4, 6])
         E, B = oracle.gather(g, fields, xp)
         assert np.allclose(np.concatenate([E, B]), vals, atol=1e-14, rtol=0)
+
+
+def test_gather_stencil_order2_matches_table():
+    """Order 2 1/2: a unit value at one grid point of each component comes
+    back at the particle as the product of the printed Section 4.5 table
+    entries: node factors f_{i-1:i+1} along the component's own axis for E
+    (along the other two for B), cell factors Delta F_{i-3/2:i+3/2} on the
+    rest, with i = int(x_p + 1/2) per axis."""
+    n = 9
+    g = oracle.Grid(n, n, n, 0.3, order=2)
+
+    def table(x):
+        i = math.floor(x + 0.5)
+        d = x + 0.5 - i
+        node = {i - 1: (1 - d) ** 2 / 2, i: 0.75 - (0.5 - d) ** 2, i + 1: d ** 2 / 2}
+        cell = {i - 2: (1 - d) ** 3 / 6, i - 1: (2 - d) ** 3 / 6 - 2 * (1 - d) ** 3 / 3,
+                i: (1 + d) ** 3 / 6 - 2 * d ** 3 / 3, i + 1: d ** 3 / 6}
+        return node, cell
+    node_axes = {0: (0,), 1: (1,), 2: (2,), 3: (1, 2), 4: (0, 2), 5: (0, 1)}
+    for _ in range(6):
+        xp = RNG.uniform(3, 6, 3)
+        tabs = [table(xp[a]) for a in range(3)]
+        for comp in range(6):
+            for _ in range(4):
+                pt = [int(RNG.integers(math.floor(xp[a]) - 2, math.floor(xp[a]) + 3)) for a in range(3)]
+                fields = np.zeros((9, n, n, n))
+                fields[comp][pt[2] % n, pt[1] % n, pt[0] % n] = 1.0
+                E, B = oracle.gather(g, fields, xp)
+                got = np.concatenate([E, B])[comp]
+                ref = 1.0
+                for a in range(3):
+                    node, cell = tabs[a]
+                    ref *= (node if a in node_axes[comp] else cell).get(pt[a], 0.0)
+                assert got == pytest.approx(ref, abs=1e-15)
 
 
 # --------------------------------------------------------------------------
