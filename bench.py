@@ -46,7 +46,7 @@ def grid_bytes_particle_kernel() -> int:
     return 9 * 8
 
 
-def run_gpu(wl, precision: str, steps: int, warmup: int):
+def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1):
     import numpy as np
     import torch
 
@@ -56,7 +56,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int):
     e = picgen.electrons(wl)
     ion = picgen.ions_like(wl, e)
     sim = Sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=wl.dims, precision=precision,
-              sort_every=wl.sort_every, bext=wl.bext)
+              sort_every=wl.sort_every, bext=wl.bext, order=order)
     s = sim.add_species(e.q, e.m, e.n)
     sim.load(s, e.x, e.w, e.weight)
     si = sim.add_species(ion.q, ion.m, 0, mobile=False)
@@ -219,21 +219,24 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
     return 2 * nbytes / sec / 1e9
 
 
-def roofline(res, precision, wl, copy_gbs=None):
+def roofline(res, precision, wl, copy_gbs=None, order=1):
     per_launch_ms = res["phases"]["particles"] / max(1, res["phases"]["steps"])
     bytes_launch = (res["n"] * particle_bytes(precision, wl.dims)
                     + wl.ncell * grid_bytes_particle_kernel())
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     kernel = "k_particle_step3" if wl.dims == 3 else "k_particle_step"
+    traffic = measured_traffic(precision, wl.name)
+    if order == 2:
+        kernel, traffic = "k_step_o2", None
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(precision, wl.name), "bytes_per_launch": bytes_launch,
+            "traffic": traffic, "bytes_per_launch": bytes_launch,
             "avg_launch_ms": round(per_launch_ms, 5),
             "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
             "frac_of_copy": None if copy_gbs is None else round(achieved / copy_gbs, 4)}
 
 
-def cpu_baseline(wl, sample_steps: int = 1):
+def cpu_baseline(wl, sample_steps: int = 1, order: int = 1):
     """The FP64 oracle as it stands, serial, on the host: one step of the full
     workload (all particles, full grid)."""
     import oracle
@@ -241,7 +244,7 @@ def cpu_baseline(wl, sample_steps: int = 1):
 
     e = picgen.electrons(wl)
     ion = picgen.ions_like(wl, e)
-    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext),
+    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext, order=order),
                       [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m),
                        oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=False)])
     t0 = time.perf_counter()
@@ -249,7 +252,7 @@ def cpu_baseline(wl, sample_steps: int = 1):
     dt = time.perf_counter() - t0
     return {"value": round(e.n * sample_steps / dt, 1), "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{sample_steps} full step(s) of the same workload ({e.n} particles, "
+            "sample": f"{sample_steps} full step(s) of the same workload ({e.n} particles, order {order} 1/2, "
                       f"{wl.nx}x{wl.ny}x{wl.nz} grid), serial C oracle, {dt:.1f} s, "
                       f"host {platform.processor() or platform.machine()} "
                       f"({os.cpu_count()} logical CPUs, 1 used)"}
@@ -270,6 +273,8 @@ def main(argv=None):
                     help="instead of the throughput line, time the checkpointed field-energy "
                          "gradient of the 2D3V 256x256 beams workload (FP64) against its forward "
                          "pass and print that as the one JSON line")
+    ap.add_argument("--order", type=int, choices=[1, 2], default=1,
+                    help="alternating form-factor order l_a = order + 1/2 (2: FP64 only)")
     ap.add_argument("--every", type=int, default=None,
                     help="checkpoint spacing of --adjoint (default: record every step when the "
                          "tape fits in half the free device memory)")
@@ -325,9 +330,11 @@ def main(argv=None):
     import picgen
     wl = picgen.WORKLOADS[args.workload]
     precs = ["fp64", "fp32c"] if args.precision == "both" else [args.precision]
+    if args.order == 2:
+        precs = ["fp64"]
     results = {}
     for p in precs:
-        results[p] = run_gpu(wl, p, args.steps, args.warmup)
+        results[p] = run_gpu(wl, p, args.steps, args.warmup, args.order)
         r = results[p]
         print(f"# {p}: {r['ms_per_step']:.4f} ms/step, particle kernel "
               f"{r['phases']['particles'] / max(1, r['phases']['steps']):.4f} ms, "
@@ -352,8 +359,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "particles": r["n"],
                    "ppc": wl.ppc, "dt": wl.dt, "sort_every": wl.sort_every,
-                   "precision": main_p, "parallelism": "none (1 GPU)"},
-        "roofline": roofline(r, main_p, wl, copy_gbs),
+                   "precision": main_p, "order": f"{args.order} 1/2", "parallelism": "none (1 GPU)"},
+        "roofline": roofline(r, main_p, wl, copy_gbs, args.order),
         "phases_ms_per_step": {k: round(v / max(1, r["phases"]["steps"]), 5)
                                for k, v in r["phases"].items() if k != "steps"},
         "checks": {"gauss_rel": r["diag"]["gauss_rel"], "nonfinite": r["diag"]["nonfinite"],
@@ -367,7 +374,7 @@ def main(argv=None):
                          "roofline": roofline(r32, "fp32c", wl, copy_gbs),
                          "gauss_rel": r32["diag"]["gauss_rel"]}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl)
+        line["cpu_baseline"] = cpu_baseline(wl, order=args.order)
     print(json.dumps(line), flush=True)
     return 0
 

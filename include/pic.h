@@ -4,7 +4,7 @@
  * (Sokolov, arXiv:1101.0809).
  *
  * One time step (paper Appendix) is: half step of B (Eq. updateB); for every
- * particle, the order-1 1/2 alternating form factor at x^n (Section 4.5),
+ * particle, the alternating form factor (order 1 1/2, or 2 1/2) at x^n (Section 4.5),
  * gather of E with the alpha weights (Eq. alphax) and of B with the beta
  * weights (Eq. betax), relativistic momentum advance of the equation of
  * motion Eq. (1) as split in the Appendix (Eq. p2), position advance
@@ -74,7 +74,9 @@ typedef struct pic_grid_desc {
     int32_t dims;        /* 3, or 2 for 2D3V (requires nz == 1: nothing depends on z) */
     int32_t nx, ny, nz;  /* cells per axis, >= 1 */
     int32_t precision;   /* enum pic_precision */
-    int32_t order;       /* form-factor order: 1 selects l_a = 1 1/2 (the only value) */
+    int32_t order;       /* alternating form-factor order l_a = order + 1/2 (Section 4.5):
+                            1 (l_a = 1 1/2) or 2 (l_a = 2 1/2: quadratic node and cubic
+                            cell factors, 5-cell current window; FP64 only, no adjoint) */
     int32_t sort_every;  /* re-sort particles by cell every this many steps (0: only
                             when loaded) */
     int32_t reserved;    /* must be 0 */

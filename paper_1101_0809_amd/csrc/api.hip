@@ -58,8 +58,12 @@ int make_grid(const pic_grid_desc* g, GridK* k, std::string* msg)
         *msg = "precision must be PIC_FP64 or PIC_FP32C";
         return PIC_EINVAL;
     }
-    if (g->order != 1) {
-        *msg = "order must be 1 (alternating order 1 1/2)";
+    if (g->order != 1 && g->order != 2) {
+        *msg = "order must be 1 or 2 (alternating order 1 1/2 or 2 1/2)";
+        return PIC_EINVAL;
+    }
+    if (g->order == 2 && g->precision != PIC_FP64) {
+        *msg = "alternating order 2 1/2 is FP64 only";
         return PIC_EINVAL;
     }
     if (g->sort_every < 0 || g->reserved != 0) {
@@ -453,6 +457,7 @@ static int adjoint_ready(Ctx& c)
 {
     if (c.g.precision != PIC_FP64) return fail(&c, PIC_EINVAL, "the adjoint is FP64 only");
     if (c.k.src_kind != 0) return fail(&c, PIC_EINVAL, "the adjoint does not cover the plane-wave source");
+    if (c.g.order != 1) return fail(&c, PIC_EINVAL, "the adjoint covers alternating order 1 1/2 only");
     return PIC_OK;
 }
 

@@ -943,6 +943,7 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
 {
     if (sp.n == 0) return hipSuccess;
+    if (c.g.order == 2) return launch_particle_step_o2(c, sp, s);
     double* J = c.fields + 6 * c.k.ncell;
     const dim3 grid(c.k.ntiles);
     if (c.g.precision == PIC_FP64) {
@@ -969,6 +970,7 @@ hipError_t launch_deposit_only(const Ctx& c, const double* x0, const double* x1,
                                const double* charge, int64_t n, double* J, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    if (c.g.order == 2) return launch_deposit_only_o2(c, x0, x1, charge, n, J, s);
     const dim3 grid(blocks_for(n));
     if (c.g.precision == PIC_FP64) {
         if (c.k.dims == 3)
@@ -1025,6 +1027,11 @@ hipError_t launch_get(const Ctx& c, const Species& sp, double* x, double* w, dou
 hipError_t launch_rho(const Ctx& c, const Species& sp, double* rho, hipStream_t s)
 {
     if (sp.n == 0) return hipSuccess;
+    if (c.g.order == 2) {
+        const double* x[3] = {(const double*)sp.cur.pos[0], (const double*)sp.cur.pos[1],
+                              (const double*)sp.cur.pos[2]};
+        return launch_rho_o2(c, x, (const double*)sp.cur.weight, sp.n, sp.d.q, rho, s);
+    }
     if (sp.sorted) {  // tiles are valid: LDS accumulation per tile
         const dim3 tg(c.k.ntiles);
         const bool f64 = c.g.precision == PIC_FP64;
@@ -1060,6 +1067,10 @@ hipError_t launch_rho_raw(const Ctx& c, const double* x, const double* weight, d
                           int64_t n, double* rho, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    if (c.g.order == 2) {
+        const double* xr[3] = {x, x + n, x + 2 * n};
+        return launch_rho_o2(c, xr, weight, n, charge, rho, s);
+    }
     const dim3 grid(blocks_for(n));
     const bool w32 = c.g.precision == PIC_FP32C;
     if (c.k.dims == 3)

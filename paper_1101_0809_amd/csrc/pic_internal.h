@@ -143,6 +143,13 @@ hipError_t launch_rho(const Ctx& c, const Species& sp, double* rho, hipStream_t 
 hipError_t launch_rho_raw(const Ctx& c, const double* x, const double* weight, double charge,
                           int64_t n, double* rho, hipStream_t s);
 hipError_t launch_sort(Ctx& c, Species& sp, hipStream_t s);
+// Alternating order 2 1/2 (grid order 2, FP64): the particle step, the
+// current of given moves and the charge density of positions x[ax][p].
+hipError_t launch_particle_step_o2(Ctx& c, Species& sp, hipStream_t s);
+hipError_t launch_deposit_only_o2(const Ctx& c, const double* x0, const double* x1, const double* charge,
+                                  int64_t n, double* J, hipStream_t s);
+hipError_t launch_rho_o2(const Ctx& c, const double* const x[3], const double* weight, int64_t n, double q,
+                         double* rho, hipStream_t s);
 hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s);
 hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
 hipError_t launch_adjoint_seed(const Ctx& c, double* lam, hipStream_t s);

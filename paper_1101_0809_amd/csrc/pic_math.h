@@ -354,6 +354,234 @@ __device__ __forceinline__ void deposit2(const R (&dm)[3][4], const R (&dp)[3][4
     }
 }
 
+// ---------------------------------------------------------------------------
+// Alternating order 2 1/2 (Section 4.5): with i = int(x + 1/2) and
+// d = x + 1/2 - i, the node factors f_{i-1:i+1} are the quadratic spline
+// ((1-d)^2/2; 3/4-(1/2-d)^2; d^2/2) and the cell factors
+// Delta F_{i-3/2:i+3/2} the cubic one ((1-d)^3/6; (2-d)^3/6-2(1-d)^3/3;
+// (1+d)^3/6-2d^3/3; d^3/6).  Positions are stored as cell c = floor(x) and
+// offset d0 = x - c; then i = c + h with h = (d0 >= 1/2), so node k of the
+// table sits at offset h - 1 + k from c and cell k at offset h - 2 + k.
+// ---------------------------------------------------------------------------
+template <class R>
+struct Axis2 {
+    R f[3];  // nodes c+h-1 .. c+h+1
+    R s[4];  // cells c+h-2 .. c+h+1
+    int h;
+};
+
+template <class R>
+__device__ __forceinline__ void cell_weights2(R d, R s[4])
+{
+    const R e = R(1) - d;
+    const R e3 = e * e * e, d3 = d * d * d;
+    const R t = R(2) - d, u = R(1) + d;
+    s[0] = e3 * R(1.0 / 6.0);
+    s[1] = t * t * t * R(1.0 / 6.0) - R(2.0 / 3.0) * e3;
+    s[2] = u * u * u * R(1.0 / 6.0) - R(2.0 / 3.0) * d3;
+    s[3] = d3 * R(1.0 / 6.0);
+}
+
+// d0 in [0, 1): the offset from the cell.
+template <class R>
+__device__ __forceinline__ Axis2<R> form_factor2(R d0)
+{
+    Axis2<R> a;
+    a.h = d0 >= R(0.5) ? 1 : 0;
+    const R d = d0 + R(0.5) - R(a.h);
+    const R e = R(1) - d;
+    const R m = R(0.5) - d;
+    a.f[0] = R(0.5) * e * e;
+    a.f[1] = R(0.75) - m * m;
+    a.f[2] = R(0.5) * d * d;
+    cell_weights2<R>(d, a.s);
+    return a;
+}
+
+// Gather (Eqs. alphax, betax) at order 2 1/2: F(comp, oa, ob, oc) returns the
+// grid value at offsets (oa, ob, oc) in [-2, 2] from the particle cell.  3D:
+// 48 points for each E component and 36 for each B component.
+template <class R, class Acc>
+__device__ __forceinline__ void gather3_o2(const Axis2<R> (&w)[3], Acc F, R E[3], R B[3])
+{
+    const Axis2<R>& X = w[0];
+    const Axis2<R>& Y = w[1];
+    const Axis2<R>& Z = w[2];
+    const int nx = X.h - 1, ny = Y.h - 1, nz = Z.h - 1;  // first node offset
+    const int cx = X.h - 2, cy = Y.h - 2, cz = Z.h - 2;  // first cell offset
+    R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
+    for (int c = 0; c < 4; ++c) {
+        R sx = 0, sy = 0;
+        for (int b = 0; b < 4; ++b) {
+            R t = 0;
+            for (int a = 0; a < 3; ++a) t += X.f[a] * F(0, nx + a, cy + b, cz + c);
+            sx += Y.s[b] * t;
+        }
+        ex += Z.s[c] * sx;
+        for (int b = 0; b < 3; ++b) {
+            R t = 0;
+            for (int a = 0; a < 4; ++a) t += X.s[a] * F(1, cx + a, ny + b, cz + c);
+            sy += Y.f[b] * t;
+        }
+        ey += Z.s[c] * sy;
+    }
+    for (int c = 0; c < 3; ++c) {
+        R sz = 0, sbx = 0, sby = 0;
+        for (int b = 0; b < 4; ++b) {
+            R t = 0;
+            for (int a = 0; a < 4; ++a) t += X.s[a] * F(2, cx + a, cy + b, nz + c);
+            sz += Y.s[b] * t;
+        }
+        ez += Z.f[c] * sz;
+        for (int b = 0; b < 3; ++b) {
+            R t = 0;
+            for (int a = 0; a < 4; ++a) t += X.s[a] * F(3, cx + a, ny + b, nz + c);
+            sbx += Y.f[b] * t;
+        }
+        bx += Z.f[c] * sbx;
+        for (int b = 0; b < 4; ++b) {
+            R t = 0;
+            for (int a = 0; a < 3; ++a) t += X.f[a] * F(4, nx + a, cy + b, nz + c);
+            sby += Y.s[b] * t;
+        }
+        by += Z.f[c] * sby;
+    }
+    for (int c = 0; c < 4; ++c) {
+        R s = 0;
+        for (int b = 0; b < 3; ++b) {
+            R t = 0;
+            for (int a = 0; a < 3; ++a) t += X.f[a] * F(5, nx + a, ny + b, cz + c);
+            s += Y.f[b] * t;
+        }
+        bz += Z.s[c] * s;
+    }
+    E[0] = ex;
+    E[1] = ey;
+    E[2] = ez;
+    B[0] = bx;
+    B[1] = by;
+    B[2] = bz;
+}
+
+// 2D3V: the z factors sum to one on the single plane.
+template <class R, class Acc>
+__device__ __forceinline__ void gather2_o2(const Axis2<R> (&w)[3], Acc F, R E[3], R B[3])
+{
+    const Axis2<R>& X = w[0];
+    const Axis2<R>& Y = w[1];
+    const int nx = X.h - 1, ny = Y.h - 1, cx = X.h - 2, cy = Y.h - 2;
+    R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
+    for (int b = 0; b < 4; ++b) {
+        R t0 = 0, t2 = 0, t4 = 0;
+        for (int a = 0; a < 3; ++a) {
+            t0 += X.f[a] * F(0, nx + a, cy + b, 0);
+            t4 += X.f[a] * F(4, nx + a, cy + b, 0);
+        }
+        for (int a = 0; a < 4; ++a) t2 += X.s[a] * F(2, cx + a, cy + b, 0);
+        ex += Y.s[b] * t0;
+        ez += Y.s[b] * t2;
+        by += Y.s[b] * t4;
+    }
+    for (int b = 0; b < 3; ++b) {
+        R t1 = 0, t3 = 0, t5 = 0;
+        for (int a = 0; a < 4; ++a) {
+            t1 += X.s[a] * F(1, cx + a, ny + b, 0);
+            t3 += X.s[a] * F(3, cx + a, ny + b, 0);
+        }
+        for (int a = 0; a < 3; ++a) t5 += X.f[a] * F(5, nx + a, ny + b, 0);
+        ey += Y.f[b] * t1;
+        bx += Y.f[b] * t3;
+        bz += Y.f[b] * t5;
+    }
+    E[0] = ex;
+    E[1] = ey;
+    E[2] = ez;
+    B[0] = bx;
+    B[1] = by;
+    B[2] = bz;
+}
+
+// Current window at order 2 1/2: start and end cell factors (4 cells each,
+// from i0 - 2 and i1 - 2 with i = int(x + 1/2)) on a common window of 5 cells
+// starting at s = min(i0, i1) - 2; shift = i1 - i0 in {-1, 0, 1}.
+template <class R>
+__device__ __forceinline__ void window5(const R s0[4], const R s1[4], int shift, R dm[5], R dp[5])
+{
+    const bool o0 = shift < 0, o1 = shift > 0;
+    R a[5], b[5];
+    for (int t = 0; t < 5; ++t) {
+        a[t] = R(0);
+        b[t] = R(0);
+    }
+    for (int k = 0; k < 4; ++k) {
+        a[k + (o0 ? 1 : 0)] = s0[k];
+        b[k + (o1 ? 1 : 0)] = s1[k];
+    }
+    for (int t = 0; t < 5; ++t) {
+        dm[t] = b[t] - a[t];
+        dp[t] = b[t] + a[t];
+    }
+}
+
+// Current of one particle at order 2 1/2 (Eq. current, one-quarter form):
+// the same formula as deposit3 on 5-cell windows, faces s+1 .. s+4 (the face
+// s+5 gets the sum of all dm = 0); 4 x 5 x 5 = 100 contributions per
+// component.  Sink(comp, ix, iy, iz, v) as for deposit3.
+template <class R, class Sink>
+__device__ __forceinline__ void deposit3_o2(const R (&dm)[3][5], const R (&dp)[3][5], const R jfac[3], Sink S)
+{
+    const R third = R(1) / R(3);
+    for (int comp = 0; comp < 3; ++comp) {
+        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
+        R P[4];
+        P[0] = dm[comp][0];
+        P[1] = P[0] + dm[comp][1];
+        P[2] = P[1] + dm[comp][2];
+        P[3] = -dm[comp][4];
+        for (int t = 0; t < 4; ++t) P[t] *= jfac[comp];
+        for (int b = 0; b < 5; ++b)
+            for (int c = 0; c < 5; ++c) {
+                const R tr = dp[u][b] * dp[v][c] + (dm[u][b] * third) * dm[v][c];
+                for (int t = 0; t < 4; ++t) {
+                    int ijk[3];
+                    ijk[comp] = t + 1;
+                    ijk[u] = b;
+                    ijk[v] = c;
+                    S(comp, ijk[0], ijk[1], ijk[2], P[t] * tr);
+                }
+            }
+    }
+}
+
+// 2D3V at order 2 1/2: 20 + 20 + 25 contributions (z collapsed as in
+// deposit2).
+template <class R, class Sink>
+__device__ __forceinline__ void deposit2_o2(const R (&dm)[3][5], const R (&dp)[3][5], const R jfac[3], R jz,
+                                            Sink S)
+{
+    const R third = R(1) / R(3);
+    for (int comp = 0; comp < 2; ++comp) {
+        const int u = 1 - comp;
+        R P[4];
+        P[0] = dm[comp][0];
+        P[1] = P[0] + dm[comp][1];
+        P[2] = P[1] + dm[comp][2];
+        P[3] = -dm[comp][4];
+        for (int t = 0; t < 4; ++t) P[t] *= R(2) * jfac[comp];
+        for (int b = 0; b < 5; ++b)
+            for (int t = 0; t < 4; ++t) {
+                int ij[2];
+                ij[comp] = t + 1;
+                ij[u] = b;
+                S(comp, ij[0], ij[1], 0, P[t] * dp[u][b]);
+            }
+    }
+    for (int a = 0; a < 5; ++a) {
+        const R mx = dm[0][a] * third;
+        for (int b = 0; b < 5; ++b) S(2, a, b, 0, jz * (dp[0][a] * dp[1][b] + mx * dm[1][b]));
+    }
+}
+
 // Workgroup -> tile map: consecutive workgroup ids are dealt round-robin to
 // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
 // share field rows and J guard cells in that XCD's L2).

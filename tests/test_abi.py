@@ -68,7 +68,8 @@ def test_query_sizes():
     (dict(dims=2), -1),                      # 2D needs nz == 1
     (dict(dims=4), -1),
     (dict(nx=0), -1),
-    (dict(order=2), -1),
+    (dict(order=3), -1),
+    (dict(order=2, precision=1), -1),        # order 2 1/2 is FP64 only
     (dict(precision=7), -1),
     (dict(reserved=1), -1),
     (dict(precision=1, nx=4096), -1),        # FP32 cell packing limit
