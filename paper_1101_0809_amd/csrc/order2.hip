@@ -251,61 +251,97 @@ __global__ __launch_bounds__(kO2NT3) void k_push_o2_3d(GridK g, StepArgs a, Part
     }
 }
 
+// One particle's windows for the current pass: start position from the spare
+// copy, end position and cell shifts from pass 1.  Returns whether the
+// particle is within the current region's margin of the tile.
+struct O2Move {
+    int i0[3], rel[3], s[3];
+    bool still;
+};
+
+__device__ __forceinline__ bool o2_windows(const GridK& g, const StepArgs& a, const PartArrays& spare, int64_t p,
+                                           const int T0[3], int M, double (&dm)[3][5], double (&dp)[3][5],
+                                           O2Move& mv)
+{
+    const int64_t code = spare.id[p];
+    bool inside = true;
+    mv.still = true;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double x0 = ((const double*)spare.pos[ax])[p];
+        const double x1 = ((const double*)a.pos[ax])[p];
+        const double f0 = floor(x0), f1 = floor(x1);
+        mv.i0[ax] = (int)f0;
+        const int delta = (int)((code >> (2 * ax)) & 3) - 1;
+        const Axis2<double> e0 = form_factor2<double>(x0 - f0);
+        const Axis2<double> e1 = form_factor2<double>(x1 - f1);
+        const int shift = delta + e1.h - e0.h;
+        mv.still = mv.still && shift == 0;
+        window5<double>(e0.s, e1.s, shift, dm[ax], dp[ax]);
+        mv.s[ax] = e0.h + (shift < 0 ? shift : 0) - 2;
+        int r = mv.i0[ax] - T0[ax];
+        const int n = g.n[ax];
+        if (r > n / 2) r -= n;
+        if (r < -(n / 2)) r += n;
+        mv.rel[ax] = r;
+        inside = inside && r >= -M && r <= kTile3 - 1 + M;
+    }
+    return inside;
+}
+
+// Pass 2.  Particles whose int(x + 1/2) stays put on every axis (most of
+// them at thermal speeds) deposit their 144 contributions at once; the
+// others are queued (their indices in the spare copy's weight array, at the
+// tile's own index range) and deposit their 300 afterwards, so that a wave
+// does not run both forms for a few lanes.
 __global__ __launch_bounds__(kO2NT3) void k_deposit_o2_3d(GridK g, StepArgs a, PartArrays spare,
                                                           double* __restrict__ Jg)
 {
     constexpr int T = kTile3, M = kO2M3b, NT = kO2NT3;
     constexpr int LJ = T + 6 + 2 * M, NJ = LJ * LJ * LJ;
     __shared__ double sj[3 * NJ];
+    __shared__ unsigned int qn;
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     const int T0[3] = {(tile % g.nt[0]) * T, ((tile / g.nt[0]) % g.nt[1]) * T, (tile / (g.nt[0] * g.nt[1])) * T};
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj[e] = 0.0;
+    if (threadIdx.x == 0) qn = 0;
     __syncthreads();
     const int64_t begin = a.tile_start[tile], end = a.tile_start[tile + 1];
-    for (int64_t p = begin + threadIdx.x; p < end; p += NT) {
-        const int64_t code = spare.id[p];
-        int i0[3], rel[3];
-        bool inside = true;
+    int64_t* queue = (int64_t*)spare.weight + begin;  // end - begin entries
+    auto deposit = [&](int64_t p, bool allow_still) {
         double dm[3][5], dp[3][5];
-        int s[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            const double x0 = ((const double*)spare.pos[ax])[p];
-            const double x1 = ((const double*)a.pos[ax])[p];
-            const double f0 = floor(x0), f1 = floor(x1);
-            i0[ax] = (int)f0;
-            const int delta = (int)((code >> (2 * ax)) & 3) - 1;
-            const Axis2<double> e0 = form_factor2<double>(x0 - f0);
-            const Axis2<double> e1 = form_factor2<double>(x1 - f1);
-            const int shift = delta + e1.h - e0.h;
-            window5<double>(e0.s, e1.s, shift, dm[ax], dp[ax]);
-            s[ax] = e0.h + (shift < 0 ? shift : 0) - 2;
-            int r = i0[ax] - T0[ax];
-            const int n = g.n[ax];
-            if (r > n / 2) r -= n;
-            if (r < -(n / 2)) r += n;
-            rel[ax] = r;
-            inside = inside && r >= -M && r <= T - 1 + M;
+        O2Move mv;
+        const bool inside = o2_windows(g, a, spare, p, T0, M, dm, dp, mv);
+        if (allow_still && !(mv.still && inside)) {
+            queue[atomicAdd(&qn, 1u)] = p;
+            return;
         }
         const double qp = a.q * ((const double*)a.weight)[p];
         double jfac[3];
         for (int ax = 0; ax < 3; ++ax) jfac[ax] = g.jscale[ax] * qp;
         if (inside) {
-            const int jb = (rel[0] + s[0] + 3 + M) + (rel[1] + s[1] + 3 + M) * LJ + (rel[2] + s[2] + 3 + M) * LJ * LJ;
+            const int jb = (mv.rel[0] + mv.s[0] + 3 + M) + (mv.rel[1] + mv.s[1] + 3 + M) * LJ +
+                           (mv.rel[2] + mv.s[2] + 3 + M) * LJ * LJ;
             auto S = [&](int comp, int ix, int iy, int iz, double v) {
                 atomicAdd(&sj[comp * NJ + jb + ix + iy * LJ + iz * LJ * LJ], v);
             };
-            deposit3_o2<double>(dm, dp, jfac, S);
+            if (allow_still) deposit3_o2_still<double>(dm, dp, jfac, S);
+            else deposit3_o2<double>(dm, dp, jfac, S);
         } else {
             auto S = [&](int comp, int ix, int iy, int iz, double v) {
-                const int64_t cell = ((int64_t)wrapi(i0[2] + s[2] + iz, nz) * ny + wrapi(i0[1] + s[1] + iy, ny)) * nx +
-                                     wrapi(i0[0] + s[0] + ix, nx);
+                const int64_t cell =
+                    ((int64_t)wrapi(mv.i0[2] + mv.s[2] + iz, nz) * ny + wrapi(mv.i0[1] + mv.s[1] + iy, ny)) * nx +
+                    wrapi(mv.i0[0] + mv.s[0] + ix, nx);
                 add_global(&Jg[comp * N + cell], v);
             };
             deposit3_o2<double>(dm, dp, jfac, S);
         }
-    }
+    };
+    for (int64_t p = begin + threadIdx.x; p < end; p += NT) deposit(p, true);
+    __syncthreads();
+    const int64_t nq = qn;
+    for (int64_t k = threadIdx.x; k < nq; k += NT) deposit(queue[k], false);
     __syncthreads();
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
         const double v = sj[e];

@@ -553,6 +553,36 @@ __device__ __forceinline__ void deposit3_o2(const R (&dm)[3][5], const R (&dp)[3
     }
 }
 
+// A particle whose int(x + 1/2) stays the same on every axis has start and
+// end factors on the same 4 cells per axis: the window's fifth cell and the
+// face s+4 carry exactly zero, leaving 3 x 4 x 4 contributions per component
+// (144 in all).  The values are those of deposit3_o2 on the same window.
+template <class R, class Sink>
+__device__ __forceinline__ void deposit3_o2_still(const R (&dm)[3][5], const R (&dp)[3][5], const R jfac[3],
+                                                  Sink S)
+{
+    const R third = R(1) / R(3);
+    for (int comp = 0; comp < 3; ++comp) {
+        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
+        R P[3];
+        P[0] = dm[comp][0];
+        P[1] = P[0] + dm[comp][1];
+        P[2] = P[1] + dm[comp][2];
+        for (int t = 0; t < 3; ++t) P[t] *= jfac[comp];
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c) {
+                const R tr = dp[u][b] * dp[v][c] + (dm[u][b] * third) * dm[v][c];
+                for (int t = 0; t < 3; ++t) {
+                    int ijk[3];
+                    ijk[comp] = t + 1;
+                    ijk[u] = b;
+                    ijk[v] = c;
+                    S(comp, ijk[0], ijk[1], ijk[2], P[t] * tr);
+                }
+            }
+    }
+}
+
 // 2D3V at order 2 1/2: 20 + 20 + 25 contributions (z collapsed as in
 // deposit2).
 template <class R, class Sink>
