@@ -46,7 +46,8 @@ class _Grid(ctypes.Structure):
                 ("bext", ctypes.c_double * 3),
                 ("src_kind", ctypes.c_int64), ("src_plane", ctypes.c_int64),
                 ("src_amp", ctypes.c_double), ("src_omega", ctypes.c_double),
-                ("src_ramp", ctypes.c_double), ("order", ctypes.c_int64)]
+                ("src_ramp", ctypes.c_double), ("order", ctypes.c_int64),
+                ("interp", ctypes.c_int64)]
 
 
 class _Species(ctypes.Structure):
@@ -112,6 +113,7 @@ class Grid:
     bext: tuple = (0.0, 0.0, 0.0)
     source: tuple = None   # (plane, amplitude, omega, ramp time): +x plane wave, E^y
     order: int = 1         # alternating order l_a = order + 1/2 (Section 4.5): 1 or 2
+    interp: int = 0        # 0 alternating order; 1 the conventional uniform order (Eq. wrong1)
 
     @property
     def shape(self):
@@ -126,6 +128,7 @@ class Grid:
         g.nx, g.ny, g.nz = self.nx, self.ny, self.nz
         g.dx, g.dy, g.dz, g.dt, g.c = self.dx, self.dy, self.dz, self.dt, self.c
         g.order = int(self.order)
+        g.interp = int(self.interp)
         for a in range(3):
             g.bext[a] = float(self.bext[a])
         if self.source is not None:

@@ -130,6 +130,16 @@ static size_t ncell(const orc_grid* g) { return (size_t)g->nx * g->ny * g->nz; }
 #define BOX_LO 2
 #define BOX_HI 2
 
+/* Weight of a component at node n along one of its node axes: f_n(x_p) for
+ * the alternating form factor; for the conventional interpolation of Eq.
+ * wrong1 the mean of the cell factors of the two cells that share the node,
+ * (Delta F_{n-1/2} + Delta F_{n+1/2}) / 2. */
+static double node_gather_w(const orc_grid* g, long n, double xp)
+{
+    if (g->interp == 1) return 0.5 * (cell_w(g, n - 1, xp) + cell_w(g, n, xp));
+    return node_w(g, n, xp);
+}
+
 void orc_gather(const orc_grid* g, const double* fields, const double xp[3], double Ep[3],
                 double Bp[3])
 {
@@ -144,7 +154,7 @@ void orc_gather(const orc_grid* g, const double* fields, const double xp[3], dou
     for (int a = 0; a < 3; ++a)
         for (int o = 0; o <= BOX_LO + BOX_HI; ++o) {
             long n = base[a] + o - BOX_LO;
-            nw[a][o] = node_w(g, n, xp[a]);
+            nw[a][o] = node_gather_w(g, n, xp[a]);
             cw[a][o] = cell_w(g, n, xp[a]);
         }
 

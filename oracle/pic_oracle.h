@@ -24,6 +24,11 @@ typedef struct orc_grid {
     double src_amp, src_omega, src_ramp;
     /* alternating order l_a = order + 1/2 (Section 4.5): 1 (also when 0) or 2 */
     int64_t order;
+    /* field interpolation: 0 alternating-order (Eqs. alphax, betax); 1 the
+     * "conventional" uniform order of Eq. wrong1 (with order 1 only): along a
+     * component's node axes the weight is the mean of the two adjacent cell
+     * factors, Delta F elsewhere */
+    int64_t interp;
 } orc_grid;
 
 #define ORC_AUX 8192  /* auxiliary line length: E^y[ORC_AUX] then B^z[ORC_AUX] */
