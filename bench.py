@@ -46,7 +46,7 @@ def grid_bytes_particle_kernel() -> int:
     return 9 * 8
 
 
-def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1):
+def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1, interp: str = "alternating"):
     import numpy as np
     import torch
 
@@ -56,7 +56,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1):
     e = picgen.electrons(wl)
     ion = picgen.ions_like(wl, e)
     sim = Sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=wl.dims, precision=precision,
-              sort_every=wl.sort_every, bext=wl.bext, order=order)
+              sort_every=wl.sort_every, bext=wl.bext, order=order, interp=interp)
     s = sim.add_species(e.q, e.m, e.n)
     sim.load(s, e.x, e.w, e.weight)
     si = sim.add_species(ion.q, ion.m, 0, mobile=False)
@@ -219,7 +219,7 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
     return 2 * nbytes / sec / 1e9
 
 
-def roofline(res, precision, wl, copy_gbs=None, order=1):
+def roofline(res, precision, wl, copy_gbs=None, order=1, interp="alternating"):
     per_launch_ms = res["phases"]["particles"] / max(1, res["phases"]["steps"])
     bytes_launch = (res["n"] * particle_bytes(precision, wl.dims)
                     + wl.ncell * grid_bytes_particle_kernel())
@@ -227,7 +227,11 @@ def roofline(res, precision, wl, copy_gbs=None, order=1):
     kernel = "k_particle_step3" if wl.dims == 3 else "k_particle_step"
     traffic = measured_traffic(precision, wl.name)
     if order == 2:
-        kernel, traffic = "k_step_o2", None
+        kernel = "k_push_o2_3d + k_deposit_o2_3d" if wl.dims == 3 else "k_step_o2<2>"
+        traffic = None
+    elif interp == "conventional":
+        kernel = "k_push_conv3 + k_deposit_conv3" if wl.dims == 3 else "k_step_conv2"
+        traffic = None
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": bytes_launch,
@@ -236,7 +240,7 @@ def roofline(res, precision, wl, copy_gbs=None, order=1):
             "frac_of_copy": None if copy_gbs is None else round(achieved / copy_gbs, 4)}
 
 
-def cpu_baseline(wl, sample_steps: int = 1, order: int = 1):
+def cpu_baseline(wl, sample_steps: int = 1, order: int = 1, interp: str = "alternating"):
     """The FP64 oracle as it stands, serial, on the host: one step of the full
     workload (all particles, full grid)."""
     import oracle
@@ -244,7 +248,8 @@ def cpu_baseline(wl, sample_steps: int = 1, order: int = 1):
 
     e = picgen.electrons(wl)
     ion = picgen.ions_like(wl, e)
-    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext, order=order),
+    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext, order=order,
+                                  interp=1 if interp == "conventional" else 0),
                       [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m),
                        oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=False)])
     t0 = time.perf_counter()
@@ -253,6 +258,7 @@ def cpu_baseline(wl, sample_steps: int = 1, order: int = 1):
     return {"value": round(e.n * sample_steps / dt, 1), "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{sample_steps} full step(s) of the same workload ({e.n} particles, order {order} 1/2, "
+                      f"{interp} interpolation, "
                       f"{wl.nx}x{wl.ny}x{wl.nz} grid), serial C oracle, {dt:.1f} s, "
                       f"host {platform.processor() or platform.machine()} "
                       f"({os.cpu_count()} logical CPUs, 1 used)"}
@@ -275,6 +281,9 @@ def main(argv=None):
                          "pass and print that as the one JSON line")
     ap.add_argument("--order", type=int, choices=[1, 2], default=1,
                     help="alternating form-factor order l_a = order + 1/2 (2: FP64 only)")
+    ap.add_argument("--interp", choices=["alternating", "conventional"], default="alternating",
+                    help="field interpolation: the alternating-order form factor, or the conventional "
+                         "uniform order of Eq. wrong1 (the comparison of Section 5; FP64, order 1)")
     ap.add_argument("--every", type=int, default=None,
                     help="checkpoint spacing of --adjoint (default: record every step when the "
                          "tape fits in half the free device memory)")
@@ -330,11 +339,11 @@ def main(argv=None):
     import picgen
     wl = picgen.WORKLOADS[args.workload]
     precs = ["fp64", "fp32c"] if args.precision == "both" else [args.precision]
-    if args.order == 2:
+    if args.order == 2 or args.interp == "conventional":
         precs = ["fp64"]
     results = {}
     for p in precs:
-        results[p] = run_gpu(wl, p, args.steps, args.warmup, args.order)
+        results[p] = run_gpu(wl, p, args.steps, args.warmup, args.order, args.interp)
         r = results[p]
         print(f"# {p}: {r['ms_per_step']:.4f} ms/step, particle kernel "
               f"{r['phases']['particles'] / max(1, r['phases']['steps']):.4f} ms, "
@@ -359,8 +368,9 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "particles": r["n"],
                    "ppc": wl.ppc, "dt": wl.dt, "sort_every": wl.sort_every,
-                   "precision": main_p, "order": f"{args.order} 1/2", "parallelism": "none (1 GPU)"},
-        "roofline": roofline(r, main_p, wl, copy_gbs, args.order),
+                   "precision": main_p, "order": f"{args.order} 1/2", "interp": args.interp,
+                   "parallelism": "none (1 GPU)"},
+        "roofline": roofline(r, main_p, wl, copy_gbs, args.order, args.interp),
         "phases_ms_per_step": {k: round(v / max(1, r["phases"]["steps"]), 5)
                                for k, v in r["phases"].items() if k != "steps"},
         "checks": {"gauss_rel": r["diag"]["gauss_rel"], "nonfinite": r["diag"]["nonfinite"],
@@ -374,7 +384,7 @@ def main(argv=None):
                          "roofline": roofline(r32, "fp32c", wl, copy_gbs),
                          "gauss_rel": r32["diag"]["gauss_rel"]}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, order=args.order)
+        line["cpu_baseline"] = cpu_baseline(wl, order=args.order, interp=args.interp)
     print(json.dumps(line), flush=True)
     return 0
 

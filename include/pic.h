@@ -79,7 +79,11 @@ typedef struct pic_grid_desc {
                             cell factors, 5-cell current window; FP64 only, no adjoint) */
     int32_t sort_every;  /* re-sort particles by cell every this many steps (0: only
                             when loaded) */
-    int32_t reserved;    /* must be 0 */
+    int32_t interp;      /* field interpolation: 0 the alternating-order form factor
+                            (Eqs. alphax, betax); 1 the "conventional" uniform order of
+                            Eq. wrong1, the comparison of Section 5 (mean of the two
+                            adjacent order-1 1/2 cell factors on a component's node axes;
+                            order 1 and FP64 only, no adjoint) */
     double dx, dy, dz;   /* cell sizes */
     double dt;           /* time step */
     double c;            /* speed of light */
@@ -135,6 +139,9 @@ typedef struct pic_diag {
     double rho_mobile_max;   /* max_cells |4 pi rho_mobile^n| */
     double divb_max;         /* max over nodes of |div_h B^{n-1/2}| */
     int64_t nonfinite;       /* count of non-finite field values and particle momenta */
+    double kinetic_half_step; /* sum (q_p dt / 2) u^{n-1/2} . E^n(x^n), E gathered with the
+                                 run's interpolation: with kinetic, the particle energy at
+                                 t^n of Section 4.1 */
 } pic_diag;
 
 /* Buffer sizes for a grid and a particle capacity.  Any pointer in g may be

@@ -33,7 +33,7 @@ EXPORTS = (
 class GridDesc(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("sort_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sort_every", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("dt", ctypes.c_double), ("c", ctypes.c_double), ("bext", ctypes.c_double * 3),
                 ("src_kind", ctypes.c_int32), ("src_plane", ctypes.c_int32),
@@ -57,7 +57,7 @@ class Diag(ctypes.Structure):
                 ("field_b", ctypes.c_double), ("charge", ctypes.c_double),
                 ("gauss_abs", ctypes.c_double), ("gauss_rel", ctypes.c_double),
                 ("rho_mobile_max", ctypes.c_double), ("divb_max", ctypes.c_double),
-                ("nonfinite", ctypes.c_int64)]
+                ("nonfinite", ctypes.c_int64), ("kinetic_half_step", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

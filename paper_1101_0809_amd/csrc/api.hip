@@ -66,8 +66,16 @@ int make_grid(const pic_grid_desc* g, GridK* k, std::string* msg)
         *msg = "alternating order 2 1/2 is FP64 only";
         return PIC_EINVAL;
     }
-    if (g->sort_every < 0 || g->reserved != 0) {
-        *msg = "sort_every must be >= 0 and reserved 0";
+    if (g->sort_every < 0) {
+        *msg = "sort_every must be >= 0";
+        return PIC_EINVAL;
+    }
+    if (g->interp != 0 && g->interp != 1) {
+        *msg = "interp must be 0 (alternating order) or 1 (conventional, Eq. wrong1)";
+        return PIC_EINVAL;
+    }
+    if (g->interp == 1 && (g->order != 1 || g->precision != PIC_FP64)) {
+        *msg = "the conventional interpolation runs at order 1 in FP64 only";
         return PIC_EINVAL;
     }
     if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) || !(g->dt > 0) || !(g->c > 0)) {
@@ -457,7 +465,8 @@ static int adjoint_ready(Ctx& c)
 {
     if (c.g.precision != PIC_FP64) return fail(&c, PIC_EINVAL, "the adjoint is FP64 only");
     if (c.k.src_kind != 0) return fail(&c, PIC_EINVAL, "the adjoint does not cover the plane-wave source");
-    if (c.g.order != 1) return fail(&c, PIC_EINVAL, "the adjoint covers alternating order 1 1/2 only");
+    if (c.g.order != 1 || c.g.interp != 0)
+        return fail(&c, PIC_EINVAL, "the adjoint covers the alternating order 1 1/2 only");
     return PIC_OK;
 }
 

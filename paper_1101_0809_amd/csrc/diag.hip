@@ -2,19 +2,21 @@
 // particles (Eq. rho), discrete Gauss residual R = div_h E - 4 pi rho at cell
 // centres and its drift from the reference R^0 (the charge-conservation
 // invariant of Section 2), div_h B at nodes, field and kinetic energies
-// (Section 4.1).  Reductions run over a fixed grid of workgroups followed by
-// one reducing workgroup, so the result does not depend on scheduling.
-#include "pic_internal.h"
+// (Section 4.1), including the half-step term sum (q dt / 2) u^{n-1/2} .
+// E(x^n) with E gathered by the run's own interpolation.  Reductions run over
+// a fixed grid of workgroups followed by one reducing workgroup, so the
+// result does not depend on scheduling.
+#include "pic_math.h"
 
 namespace pic {
 namespace {
 
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 1024;
-constexpr int kSlots = 8;
+constexpr int kSlots = 9;
 // slots: 0 max|R-R0|  1 max|4 pi rho_m|  2 sum E^2  3 sum (B^n)^2  4 max|divB|
-//        5 sum rho    6 nonfinite      7 kinetic
-constexpr bool kIsMax[kSlots] = {true, true, false, false, true, false, false, false};
+//        5 sum rho    6 nonfinite      7 kinetic   8 half-step term
+constexpr bool kIsMax[kSlots] = {true, true, false, false, true, false, false, false, false};
 
 __device__ __forceinline__ double combine(int slot, double a, double b)
 {
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(kRedThreads) void k_diag_cells(GridK g, const doubl
                                                             const double* __restrict__ r0,
                                                             double* __restrict__ part)
 {
-    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t N = g.ncell;
     const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
     for (int64_t p = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; p < N;
@@ -112,12 +114,50 @@ __global__ __launch_bounds__(kRedThreads) void k_diag_cells(GridK g, const doubl
     block_reduce_store(v, part + (int64_t)blockIdx.x * kSlots);
 }
 
-template <class R>
-__global__ __launch_bounds__(kRedThreads) void k_diag_particles(PartArrays a, int64_t n, double m,
-                                                                double inv_c2,
+// E^n at a particle with the run's interpolation (0: alternating order 1 1/2,
+// 1: alternating order 2 1/2, 2: the conventional uniform order of Eq.
+// wrong1), read from the grid.
+template <int D>
+__device__ __forceinline__ void gather_e(const GridK& g, int scheme, const double* f, const int i0[3],
+                                        const double d0[3], double E[3])
+{
+    const int64_t N = g.ncell;
+    auto F = [&](int comp, int oa, int ob, int oc) -> double {
+        const int64_t cell = ((int64_t)(D == 3 ? wrapi(i0[2] + oc, g.n[2]) : 0) * g.n[1] + wrapi(i0[1] + ob, g.n[1])) *
+                                 g.n[0] +
+                             wrapi(i0[0] + oa, g.n[0]);
+        return f[comp * N + cell];
+    };
+    double B[3];
+    if (scheme == 1) {
+        Axis2<double> w[3];
+        for (int a = 0; a < 3; ++a) w[a] = form_factor2<double>(a < D ? d0[a] : 0.0);
+        if (D == 3) gather3_o2<double>(w, F, E, B);
+        else gather2_o2<double>(w, F, E, B);
+    } else if (scheme == 2) {
+        AxisC<double> w[3];
+        for (int a = 0; a < 3; ++a) w[a] = form_factor_conv<double>(a < D ? d0[a] : 0.0);
+        if (D == 3) gather3_conv<double>(w, F, E, B);
+        else gather2_conv<double>(w, F, E, B);
+    } else {
+        Axis<double> w[3];
+        for (int a = 0; a < 3; ++a) w[a] = form_factor<double>(a < D ? d0[a] : 0.0);
+        if (D == 3) gather3<double>(w, F, E, B);
+        else gather2<double>(w, F, E, B);
+    }
+}
+
+template <class R, int D>
+__global__ __launch_bounds__(kRedThreads) void k_diag_particles(GridK g, int scheme, PartArrays a, int64_t n,
+                                                                double q, double m, double dt,
+                                                                const double* __restrict__ fields,
                                                                 double* __restrict__ part)
 {
-    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double inv_c2 = 1.0 / (g.c * g.c);
+    StepArgs sa{};
+    for (int ax = 0; ax < 3; ++ax) sa.pos[ax] = a.pos[ax];
+    sa.cell = a.cell;
+    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t p = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * kRedThreads) {
         const double w0 = (double)((const R*)a.mom[0])[p];
@@ -129,7 +169,16 @@ __global__ __launch_bounds__(kRedThreads) void k_diag_particles(PartArrays a, in
             continue;
         }
         const double gam = sqrt(1.0 + w2s * inv_c2);
-        v[7] += m * (double)((const R*)a.weight)[p] * w2s / (gam + 1.0);
+        const double wt = (double)((const R*)a.weight)[p];
+        v[7] += m * wt * w2s / (gam + 1.0);
+        int i0[3];
+        R dr[3];
+        PosIO<R, D>::load(sa, p, i0, dr);
+        double d0[3] = {0.0, 0.0, 0.0};
+        for (int ax = 0; ax < D; ++ax) d0[ax] = (double)dr[ax];
+        double E[3];
+        gather_e<D>(g, scheme, fields, i0, d0, E);
+        v[8] += 0.5 * q * wt * dt * (E[0] * w0 + E[1] * w1 + E[2] * w2) / gam;
     }
     block_reduce_store(v, part + (int64_t)blockIdx.x * kSlots);
 }
@@ -137,7 +186,7 @@ __global__ __launch_bounds__(kRedThreads) void k_diag_particles(PartArrays a, in
 __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ part, int nb,
                                                               double* __restrict__ out)
 {
-    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nb; b += kRedThreads)
         for (int s = 0; s < kSlots; ++s) v[s] = combine(s, v[s], part[(int64_t)b * kSlots + s]);
     block_reduce_store(v, out);
@@ -187,12 +236,23 @@ hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s)
         if (!sp.d.mobile) continue;
         nmob += sp.n;
         double* pp = part + (int64_t)nb * kSlots;
-        if (c.g.precision == PIC_FP64)
-            hipLaunchKernelGGL((k_diag_particles<double>), dim3(kRedBlocks), dim3(kRedThreads), 0, s,
-                               sp.cur, sp.n, sp.d.m, 1.0 / (c.g.c * c.g.c), pp);
-        else
-            hipLaunchKernelGGL((k_diag_particles<float>), dim3(kRedBlocks), dim3(kRedThreads), 0, s,
-                               sp.cur, sp.n, sp.d.m, 1.0 / (c.g.c * c.g.c), pp);
+        const int scheme = c.g.order == 2 ? 1 : (c.g.interp == 1 ? 2 : 0);
+        const bool f64 = c.g.precision == PIC_FP64;
+        if (c.k.dims == 3) {
+            if (f64)
+                hipLaunchKernelGGL((k_diag_particles<double, 3>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k,
+                                   scheme, sp.cur, sp.n, sp.d.q, sp.d.m, c.g.dt, c.fields, pp);
+            else
+                hipLaunchKernelGGL((k_diag_particles<float, 3>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k,
+                                   scheme, sp.cur, sp.n, sp.d.q, sp.d.m, c.g.dt, c.fields, pp);
+        } else {
+            if (f64)
+                hipLaunchKernelGGL((k_diag_particles<double, 2>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k,
+                                   scheme, sp.cur, sp.n, sp.d.q, sp.d.m, c.g.dt, c.fields, pp);
+            else
+                hipLaunchKernelGGL((k_diag_particles<float, 2>), dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k,
+                                   scheme, sp.cur, sp.n, sp.d.q, sp.d.m, c.g.dt, c.fields, pp);
+        }
         nb += kRedBlocks;
     }
     double* fin = part + (int64_t)nb * kSlots;
@@ -208,6 +268,7 @@ hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s)
     out->step = c.step;
     out->n_particles = nmob;
     out->kinetic = h[7];
+    out->kinetic_half_step = h[8];
     out->field_e = V / (8.0 * kPi) * h[2];
     out->field_b = V / (8.0 * kPi) * h[3];
     out->charge = V * h[5];

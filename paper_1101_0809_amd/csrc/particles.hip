@@ -944,6 +944,7 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
 {
     if (sp.n == 0) return hipSuccess;
     if (c.g.order == 2) return launch_particle_step_o2(c, sp, s);
+    if (c.g.interp == 1) return launch_particle_step_conv(c, sp, s);
     double* J = c.fields + 6 * c.k.ncell;
     const dim3 grid(c.k.ntiles);
     if (c.g.precision == PIC_FP64) {

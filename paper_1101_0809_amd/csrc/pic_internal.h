@@ -150,6 +150,8 @@ hipError_t launch_deposit_only_o2(const Ctx& c, const double* x0, const double* 
                                   int64_t n, double* J, hipStream_t s);
 hipError_t launch_rho_o2(const Ctx& c, const double* const x[3], const double* weight, int64_t n, double q,
                          double* rho, hipStream_t s);
+// The conventional interpolation of Eq. wrong1 (grid interp 1, order 1, FP64).
+hipError_t launch_particle_step_conv(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s);
 hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
 hipError_t launch_adjoint_seed(const Ctx& c, double* lam, hipStream_t s);

@@ -612,6 +612,131 @@ __device__ __forceinline__ void deposit2_o2(const R (&dm)[3][5], const R (&dp)[3
     }
 }
 
+// ---------------------------------------------------------------------------
+// The "conventional" uniform-order interpolation of Eq. wrong1 (the comparison
+// of Section 5): along a component's node axes the weight of node n is the
+// mean of the order-1 1/2 cell factors of the two cells that share it,
+// (Delta F_{n-1/2} + Delta F_{n+1/2}) / 2, on nodes c-1 .. c+2; along its
+// cell axes it is Delta F on cells c-1 .. c+1.  3D: 36 points per E
+// component, 48 per B component.  The charge and current are those of the
+// order-1 1/2 scheme.
+// ---------------------------------------------------------------------------
+template <class R>
+struct AxisC {
+    R g[4];  // nodes c-1 .. c+2
+    R s[3];  // cells c-1 .. c+1
+};
+
+template <class R>
+__device__ __forceinline__ AxisC<R> form_factor_conv(R d)
+{
+    AxisC<R> a;
+    cell_weights<R>(d, a.s);
+    a.g[0] = R(0.5) * a.s[0];
+    a.g[1] = R(0.5) * (a.s[0] + a.s[1]);
+    a.g[2] = R(0.5) * (a.s[1] + a.s[2]);
+    a.g[3] = R(0.5) * a.s[2];
+    return a;
+}
+
+// F(comp, oa, ob, oc): grid value at offsets in [-1, 2] from the particle cell.
+template <class R, class Acc>
+__device__ __forceinline__ void gather3_conv(const AxisC<R> (&w)[3], Acc F, R E[3], R B[3])
+{
+    const AxisC<R>& X = w[0];
+    const AxisC<R>& Y = w[1];
+    const AxisC<R>& Z = w[2];
+    R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
+    for (int c = 0; c < 3; ++c) {
+        R sx = 0, sy = 0;
+        for (int b = 0; b < 3; ++b) {
+            R t = 0;
+            for (int a = 0; a < 4; ++a) t += X.g[a] * F(0, a - 1, b - 1, c - 1);
+            sx += Y.s[b] * t;
+        }
+        ex += Z.s[c] * sx;
+        for (int b = 0; b < 4; ++b) {
+            R t = 0;
+            for (int a = 0; a < 3; ++a) t += X.s[a] * F(1, a - 1, b - 1, c - 1);
+            sy += Y.g[b] * t;
+        }
+        ey += Z.s[c] * sy;
+    }
+    for (int c = 0; c < 4; ++c) {
+        R sz = 0, sbx = 0, sby = 0;
+        for (int b = 0; b < 3; ++b) {
+            R t = 0;
+            for (int a = 0; a < 3; ++a) t += X.s[a] * F(2, a - 1, b - 1, c - 1);
+            sz += Y.s[b] * t;
+        }
+        ez += Z.g[c] * sz;
+        for (int b = 0; b < 4; ++b) {
+            R t = 0;
+            for (int a = 0; a < 3; ++a) t += X.s[a] * F(3, a - 1, b - 1, c - 1);
+            sbx += Y.g[b] * t;
+        }
+        bx += Z.g[c] * sbx;
+        for (int b = 0; b < 3; ++b) {
+            R t = 0;
+            for (int a = 0; a < 4; ++a) t += X.g[a] * F(4, a - 1, b - 1, c - 1);
+            sby += Y.s[b] * t;
+        }
+        by += Z.g[c] * sby;
+    }
+    for (int c = 0; c < 3; ++c) {
+        R s = 0;
+        for (int b = 0; b < 4; ++b) {
+            R t = 0;
+            for (int a = 0; a < 4; ++a) t += X.g[a] * F(5, a - 1, b - 1, c - 1);
+            s += Y.g[b] * t;
+        }
+        bz += Z.s[c] * s;
+    }
+    E[0] = ex;
+    E[1] = ey;
+    E[2] = ez;
+    B[0] = bx;
+    B[1] = by;
+    B[2] = bz;
+}
+
+// 2D3V: the z weights sum to one on the single plane.
+template <class R, class Acc>
+__device__ __forceinline__ void gather2_conv(const AxisC<R> (&w)[3], Acc F, R E[3], R B[3])
+{
+    const AxisC<R>& X = w[0];
+    const AxisC<R>& Y = w[1];
+    R ex = 0, ey = 0, ez = 0, bx = 0, by = 0, bz = 0;
+    for (int b = 0; b < 3; ++b) {
+        R t0 = 0, t2 = 0, t4 = 0;
+        for (int a = 0; a < 4; ++a) {
+            t0 += X.g[a] * F(0, a - 1, b - 1, 0);
+            t4 += X.g[a] * F(4, a - 1, b - 1, 0);
+        }
+        for (int a = 0; a < 3; ++a) t2 += X.s[a] * F(2, a - 1, b - 1, 0);
+        ex += Y.s[b] * t0;
+        ez += Y.s[b] * t2;
+        by += Y.s[b] * t4;
+    }
+    for (int b = 0; b < 4; ++b) {
+        R t1 = 0, t3 = 0, t5 = 0;
+        for (int a = 0; a < 3; ++a) {
+            t1 += X.s[a] * F(1, a - 1, b - 1, 0);
+            t3 += X.s[a] * F(3, a - 1, b - 1, 0);
+        }
+        for (int a = 0; a < 4; ++a) t5 += X.g[a] * F(5, a - 1, b - 1, 0);
+        ey += Y.g[b] * t1;
+        bx += Y.g[b] * t3;
+        bz += Y.g[b] * t5;
+    }
+    E[0] = ex;
+    E[1] = ey;
+    E[2] = ez;
+    B[0] = bx;
+    B[1] = by;
+    B[2] = bz;
+}
+
 // Workgroup -> tile map: consecutive workgroup ids are dealt round-robin to
 // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
 // share field rows and J guard cells in that XCD's L2).

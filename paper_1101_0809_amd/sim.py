@@ -49,10 +49,13 @@ class Sim:
     def __init__(self, nx: int, ny: int, nz: int, dt: float, dims: int = 3,
                  precision: str = "fp64", dx: float = 1.0, dy: float = 1.0, dz: float = 1.0,
                  c: float = 1.0, sort_every: int = 0, bext=(0.0, 0.0, 0.0),
-                 device: str = "cuda:0", fields: np.ndarray = None, source=None, order: int = 1):
+                 device: str = "cuda:0", fields: np.ndarray = None, source=None, order: int = 1,
+                 interp: str = "alternating"):
         """source: None or (plane, amplitude, omega, ramp time) for the +x
         E^y plane-wave source of include/pic.h.  order: alternating form
-        factor order l_a = order + 1/2 (1, or 2 in FP64)."""
+        factor order l_a = order + 1/2 (1, or 2 in FP64).  interp:
+        "alternating" or "conventional" (the uniform-order comparison of
+        Eq. wrong1; order 1, FP64)."""
         if not torch.cuda.is_available():
             raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
         self.lib = L.load()
@@ -61,7 +64,8 @@ class Sim:
         d = L.GridDesc()
         d.dims, d.nx, d.ny, d.nz = dims, nx, ny, nz
         d.precision = {"fp64": L.PIC_FP64, "fp32c": L.PIC_FP32C}[precision]
-        d.order, d.sort_every, d.reserved = int(order), sort_every, 0
+        d.order, d.sort_every = int(order), sort_every
+        d.interp = {"alternating": 0, "conventional": 1}[interp]
         d.dx, d.dy, d.dz, d.dt, d.c = dx, dy, dz, dt, c
         for a in range(3):
             d.bext[a] = float(bext[a])
@@ -224,7 +228,8 @@ class Sim:
                if d["src_kind"] == 1 else None)
         sim = cls(d["nx"], d["ny"], d["nz"], d["dt"], dims=d["dims"], precision=prec,
                   dx=d["dx"], dy=d["dy"], dz=d["dz"], c=d["c"], sort_every=d["sort_every"],
-                  bext=tuple(d["bext"]), device=device, source=src, order=d["order"])
+                  bext=tuple(d["bext"]), device=device, source=src, order=d["order"],
+                  interp=("alternating", "conventional")[d["interp"]])
         for sp in st["species"]:
             sim.add_species(sp["q"], sp["m"], sp["capacity"], mobile=sp["mobile"])
         sim.fields_t.copy_(st["fields"])

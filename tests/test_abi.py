@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def _desc(L, **kw):
     d = L.GridDesc()
     d.dims, d.nx, d.ny, d.nz = 3, 16, 16, 16
-    d.precision, d.order, d.sort_every, d.reserved = L.PIC_FP64, 1, 10, 0
+    d.precision, d.order, d.sort_every, d.interp = L.PIC_FP64, 1, 10, 0
     d.dx = d.dy = d.dz = 1.0
     d.dt, d.c = 0.45, 1.0
     for k, v in kw.items():
@@ -71,7 +71,9 @@ def test_query_sizes():
     (dict(order=3), -1),
     (dict(order=2, precision=1), -1),        # order 2 1/2 is FP64 only
     (dict(precision=7), -1),
-    (dict(reserved=1), -1),
+    (dict(interp=2), -1),
+    (dict(interp=1, order=2), -1),          # conventional: order 1 only
+    (dict(interp=1, precision=1), -1),      # conventional: FP64 only
     (dict(precision=1, nx=4096), -1),        # FP32 cell packing limit
     (dict(dx=-1.0), -1),
 ])

@@ -581,3 +581,36 @@ def test_128cube_slab_laser_fullsize_sampled(precision):
     assert d["gauss_rel"] <= (1e-12 if precision == "fp64" else 1e-6), d
     assert d["nonfinite"] == 0
     assert d["field_e"] > 0.0
+
+
+@pytest.mark.parametrize("dims", [3, 2])
+@pytest.mark.parametrize("scheme", ["alternating-1", "alternating-2", "conventional"])
+def test_energy_diagnostics_match_oracle(scheme, dims):
+    """pic_diagnostics' energies (kinetic at t^{n-1/2}, the half-step term
+    (q dt / 2) u . E(x^n) with the run's own gather, E and B^n field energies,
+    Section 4.1) against the oracle's, after a run with fields grown from a
+    drifting plasma."""
+    order = 2 if scheme == "alternating-2" else 1
+    interp = "conventional" if scheme == "conventional" else "alternating"
+    if dims == 3:
+        wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=12, ny=10, nz=9, ppc=3, steps=15, sort_every=5,
+                                                      drift=0.1)
+    else:
+        wl = picgen.WORKLOADS["2d3v_32x32_fp64"].scaled(nx=24, ny=20, steps=30, sort_every=5, drift=0.1)
+    e = picgen.electrons(wl)
+    from paper_1101_0809_amd import Sim
+    sim = Sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=dims, sort_every=wl.sort_every, order=order,
+              interp=interp)
+    sim.add_species(e.q, e.m, e.n)
+    sim.load(0, e.x, e.w, e.weight)
+    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, order=order, interp=1 if interp == "conventional" else 0),
+                      [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m)])
+    sim.step(wl.steps)
+    st.step(wl.steps)
+    d = sim.diagnostics()
+    ref = st.energies()
+    assert abs(d["kinetic"] - ref[0]) <= 1e-12 * ref[0]
+    assert abs(d["kinetic_half_step"] - ref[1]) <= 1e-10 * abs(ref[1]) + 1e-14 * ref[0], (d["kinetic_half_step"], ref[1])
+    assert abs(d["field_e"] - ref[2]) <= 1e-11 * ref[2]
+    assert abs(d["field_b"] - ref[3]) <= 1e-11 * ref[3] + 1e-14 * ref[2]
+    sim.close()
