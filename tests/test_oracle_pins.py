@@ -636,3 +636,38 @@ def test_plane_wave_source_keeps_gauss_and_divb():
     assert np.max(np.abs(st.gauss_residual() - R0)) / rho_e < 1e-12
     assert np.max(np.abs(st.div_b())) < 1e-14
     assert np.max(np.abs(st.fields[1])) > 0.1 * omega
+
+
+# --------------------------------------------------------------------------
+# Electrostatic initial field (Section 4.3, Eqs. poiphi and egradphidis)
+# --------------------------------------------------------------------------
+
+def test_poisson_solution_satisfies_gauss_law_and_energy_identity():
+    """E = -grad_h Phi of the reference Poisson solve satisfies the discrete
+    Gauss law div_h E = 4 pi (rho - <rho>) cell by cell, and the field energy
+    equals the potential form printed in Section 4.3:
+    V/(8 pi) sum E^2 = (V/2) sum rho Phi."""
+    from oracle import poisson
+    g = oracle.Grid(10, 7, 6, 0.3, dx=1.1, dy=0.8, dz=1.3)
+    rho = RNG.normal(0, 1, g.shape)
+    phi = poisson.solve(g, rho)
+    E = poisson.e_of_phi(g, phi)
+    resid = poisson.div_e(g, E) - 4 * np.pi * (rho - rho.mean())
+    assert np.max(np.abs(resid)) < 1e-12 * np.max(np.abs(4 * np.pi * rho))
+    V = g.dx * g.dy * g.dz
+    lhs = V / (8 * np.pi) * np.sum(E * E)
+    rhs = V / 2 * np.sum((rho - rho.mean()) * phi)
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_poisson_single_mode_closed_form():
+    """rho = cos(2 pi m x / L) along x: Phi = 4 pi rho / lambda_m with the
+    discrete eigenvalue lambda_m = (2 - 2 cos(2 pi m / N)) / dx^2."""
+    from oracle import poisson
+    n, m, dx = 16, 3, 0.7
+    g = oracle.Grid(n, 4, 3, 0.3, dx=dx)
+    x = np.arange(n)
+    rho = np.broadcast_to(np.cos(2 * np.pi * m * x / n), g.shape).copy()
+    phi = poisson.solve(g, rho)
+    lam = (2 - 2 * np.cos(2 * np.pi * m / n)) / dx ** 2
+    assert np.max(np.abs(phi - 4 * np.pi * rho / lam)) < 1e-12
