@@ -263,6 +263,22 @@ int pic_adjoint_reorder(pic_ctx* ctx, const void* from, const void* to, size_t b
                         const double* const* in_x, const double* const* in_w, double* const* out_x,
                         double* const* out_w, void* stream);
 
+/* Electrostatic field of the current charge (Section 4.3): solve the
+ * discrete Poisson equation of Eq. poiphi on the periodic grid for the
+ * cell-centred potential of the total charge density (mobile species plus the
+ * immobile background) and set E = -grad_h Phi (Eq. egradphidis), so that
+ * div_h E = 4 pi rho cell by cell; B is left as it is.  The periodic problem
+ * needs a neutral total: the mean charge density is removed from the right
+ * side, and with neutralize = 1 it is also added, with the opposite sign, to
+ * the background as a uniform charge (the uniform neutralizing background of
+ * a start without co-located ions).  Conjugate gradients on the GPU to a
+ * relative residual tol (<= 0: 1e-13); *iterations and *residual (either may
+ * be NULL) report the count and the reached relative residual.  The Gauss
+ * reference R^0 is recaptured before the next step.  Synchronizes the
+ * stream.  PIC_ESTATE if the tolerance was not reached. */
+int pic_solve_poisson(pic_ctx* ctx, int neutralize, double tol, int64_t* iterations, double* residual,
+                      void* stream);
+
 /* Number of particles currently held by a species (host-side count). */
 int64_t pic_particle_count(const pic_ctx* ctx, int species);
 

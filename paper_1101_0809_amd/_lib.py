@@ -25,7 +25,7 @@ EXPORTS = (
     "pic_timing_stop", "pic_get_host_state", "pic_set_host_state", "pic_destroy",
     "pic_adjoint_seed_field_energy", "pic_adjoint_step", "pic_adjoint_record_bytes",
     "pic_adjoint_record", "pic_adjoint_step_record", "pic_adjoint_step_record_ordered",
-    "pic_adjoint_reorder",
+    "pic_adjoint_reorder", "pic_solve_poisson",
     "pic_last_error", "pic_version",
 )
 
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH):
                                                 ctypes.POINTER(P), P, P]),
         "pic_adjoint_reorder": (I, [P, P, P, ctypes.c_size_t, ctypes.POINTER(P), ctypes.POINTER(P),
                                     ctypes.POINTER(P), ctypes.POINTER(P), P]),
+        "pic_solve_poisson": (I, [P, I, D, ctypes.POINTER(I64), ctypes.POINTER(D), P]),
         "pic_destroy": (None, [P]),
         "pic_last_error": (ctypes.c_char_p, [P]),
         "pic_version": (ctypes.c_char_p, []),

@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -562,6 +564,29 @@ int pic_adjoint_reorder(pic_ctx* ctx, const void* from, const void* to, size_t b
         return fail(&c, PIC_ESIZE, "record smaller than pic_adjoint_record_bytes");
     hipError_t e = launch_adjoint_reorder(c, from, to, in_x, in_w, out_x, out_w, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(&c, e, "adjoint_reorder");
+    return PIC_OK;
+}
+
+int pic_solve_poisson(pic_ctx* ctx, int neutralize, double tol, int64_t* iterations, double* residual,
+                      void* stream)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    if (neutralize != 0 && neutralize != 1) return fail(&c, PIC_EINVAL, "neutralize must be 0 or 1");
+    if (!(tol > 0.0)) tol = 1e-13;
+    hipStream_t s = (hipStream_t)stream;
+    // the total charge density goes to the Gauss reference's buffer, which is
+    // recaptured before the next step
+    hipError_t e = launch_total_rho(c, c.r0, s);
+    int64_t it = 0;
+    double res = 0.0;
+    const int64_t nmax = std::max(c.k.n[0], std::max(c.k.n[1], c.k.n[2]));
+    if (e == hipSuccess) e = solve_poisson(c, c.r0, neutralize != 0, tol, 50 * nmax + 200, &it, &res, s);
+    c.r0_valid = false;
+    if (e != hipSuccess) return hip_fail(&c, e, "solve_poisson");
+    if (iterations) *iterations = it;
+    if (residual) *residual = res;
+    if (res > tol) return fail(&c, PIC_ESTATE, "Poisson solve did not reach the tolerance");
     return PIC_OK;
 }
 

@@ -210,7 +210,22 @@ hipError_t mobile_rho(Ctx& c, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kRedThreads) void k_sum2(const double* __restrict__ a, const double* __restrict__ b,
+                                                      double* __restrict__ out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+        out[i] = a[i] + b[i];
+}
+
 }  // namespace
+
+hipError_t launch_total_rho(Ctx& c, double* out, hipStream_t s)
+{
+    hipError_t e = mobile_rho(c, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum2, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.rho_m, c.rho_bg, out, c.k.ncell);
+    return hipGetLastError();
+}
 
 hipError_t launch_capture_r0(Ctx& c, hipStream_t s)
 {

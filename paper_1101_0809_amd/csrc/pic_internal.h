@@ -154,6 +154,13 @@ hipError_t launch_rho_o2(const Ctx& c, const double* const x[3], const double* w
 hipError_t launch_particle_step_conv(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s);
 hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
+// rho of the mobile species (into the workspace's rho_m) plus the background, into out.
+hipError_t launch_total_rho(Ctx& c, double* out, hipStream_t s);
+// Electrostatic field of the charge density rho (Eqs. poiphi, egradphidis)
+// into E; with neutralize, minus the mean of rho is first added to the
+// background.  Conjugate gradients to a relative residual tol; synchronizes.
+hipError_t solve_poisson(Ctx& c, double* rho, bool neutralize, double tol, int64_t max_iter, int64_t* iters,
+                         double* rel_residual, hipStream_t s);
 hipError_t launch_adjoint_seed(const Ctx& c, double* lam, hipStream_t s);
 // record == nullptr: the state before the step is the context's own; else a
 // record written by launch_adjoint_record.

@@ -180,6 +180,16 @@ class Sim:
             ctypes.c_void_p(q.data_ptr()), q.numel(), ctypes.c_void_p(J.data_ptr()), _stream()))
         return J
 
+    def solve_poisson(self, neutralize: bool = True, tol: float = 1e-13):
+        """E from the discrete Poisson equation of the current charge
+        (include/pic.h, pic_solve_poisson); returns (iterations, relative
+        residual)."""
+        it = ctypes.c_int64()
+        res = ctypes.c_double()
+        self._check(self.lib.pic_solve_poisson(self.ctx, int(neutralize), tol, ctypes.byref(it),
+                                               ctypes.byref(res), _stream()))
+        return it.value, res.value
+
     def diagnostics(self) -> dict:
         d = L.Diag()
         self._check(self.lib.pic_diagnostics(self.ctx, ctypes.byref(d), _stream()))
