@@ -102,6 +102,16 @@ typedef struct pic_grid_desc {
     int32_t src_kind;
     int32_t src_plane;
     double src_amp, src_omega, src_ramp;
+    /* Field form.  0: the grid carries B (Eq. updateB).  1: it carries the
+     * vector potential A at the E points (Section 4.2, Eq. dadt): each step
+     * updates A^{n+1/2} = A^{n-1/2} - c dt E^n and takes B = curl_h A (B^n of
+     * A^n for the particles, B^{n+1/2} into the field buffer's B planes, which
+     * become outputs: div_h B = 0 holds identically).  A lives in the grid
+     * workspace, starts at zero (pic_init_grid sets the B planes to
+     * curl_h 0 = 0) and is set and read with pic_set_vector_potential /
+     * pic_get_vector_potential.  Not with the plane-wave source or the adjoint. */
+    int32_t field_form;
+    int32_t reserved2;   /* must be 0 */
 } pic_grid_desc;
 
 #define PIC_AUX 8192
@@ -278,6 +288,14 @@ int pic_adjoint_reorder(pic_ctx* ctx, const void* from, const void* to, size_t b
  * stream.  PIC_ESTATE if the tolerance was not reached. */
 int pic_solve_poisson(pic_ctx* ctx, int neutralize, double tol, int64_t* iterations, double* residual,
                       void* stream);
+
+/* Vector-potential form (field_form 1): pic_set_vector_potential copies A
+ * (3 N FP64 device array, the layout of E: A^x at (i, j+1/2, k+1/2), ...)
+ * as A^{n-1/2} of the current state and sets the B planes to curl_h A;
+ * pic_get_vector_potential copies A^{n-1/2} out.  PIC_ESTATE in field form 0.
+ * Asynchronous. */
+int pic_set_vector_potential(pic_ctx* ctx, const double* A, void* stream);
+int pic_get_vector_potential(pic_ctx* ctx, double* A, void* stream);
 
 /* Number of particles currently held by a species (host-side count). */
 int64_t pic_particle_count(const pic_ctx* ctx, int species);

@@ -290,3 +290,30 @@ def half_b(grid: Grid, fields: np.ndarray):
 
 def update_e(grid: Grid, fields: np.ndarray):
     lib().orc_update_e(ctypes.byref(grid._c()), _ptr(fields))
+
+
+# --- vector-potential form (Section 4.2, Eq. dadt) ---------------------------
+
+def curl_a(grid: Grid, A: np.ndarray) -> np.ndarray:
+    """B (3, nz, ny, nx) = curl_h A on the staggered grid: B^x at (i+1/2, j, k)
+    from A^z at j -+ 1/2 and A^y at k -+ 1/2, and cyclic (A stored like E)."""
+    Ax, Ay, Az = A
+    r = lambda a, ax: np.roll(a, 1, axis=ax)  # value at index - 1 along ax
+    return np.stack([(Az - r(Az, 1)) / grid.dy - (Ay - r(Ay, 0)) / grid.dz,
+                     (Ax - r(Ax, 0)) / grid.dz - (Az - r(Az, 2)) / grid.dx,
+                     (Ay - r(Ay, 2)) / grid.dx - (Ax - r(Ax, 1)) / grid.dy])
+
+
+def step_vector_potential(st: "State", A: np.ndarray, nsteps: int) -> np.ndarray:
+    """Advance a state in the vector-potential form: before each step B^{n-1/2}
+    is curl_h A^{n-1/2}; after it A^{n+1/2} = A^{n-1/2} - c dt E^n with the
+    E^n the step started from.  Returns A after the steps; the state's B is
+    curl_h of it."""
+    A = np.array(A, dtype=np.float64)
+    for _ in range(nsteps):
+        st.fields[3:6] = curl_a(st.grid, A)
+        E = st.fields[0:3].copy()
+        st.step(1)
+        A = A - st.grid.c * st.grid.dt * E
+    st.fields[3:6] = curl_a(st.grid, A)
+    return A

@@ -25,7 +25,8 @@ EXPORTS = (
     "pic_timing_stop", "pic_get_host_state", "pic_set_host_state", "pic_destroy",
     "pic_adjoint_seed_field_energy", "pic_adjoint_step", "pic_adjoint_record_bytes",
     "pic_adjoint_record", "pic_adjoint_step_record", "pic_adjoint_step_record_ordered",
-    "pic_adjoint_reorder", "pic_solve_poisson",
+    "pic_adjoint_reorder", "pic_solve_poisson", "pic_set_vector_potential",
+    "pic_get_vector_potential",
     "pic_last_error", "pic_version",
 )
 
@@ -38,7 +39,8 @@ class GridDesc(ctypes.Structure):
                 ("dt", ctypes.c_double), ("c", ctypes.c_double), ("bext", ctypes.c_double * 3),
                 ("src_kind", ctypes.c_int32), ("src_plane", ctypes.c_int32),
                 ("src_amp", ctypes.c_double), ("src_omega", ctypes.c_double),
-                ("src_ramp", ctypes.c_double)]
+                ("src_ramp", ctypes.c_double), ("field_form", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class SpeciesDesc(ctypes.Structure):
@@ -122,6 +124,8 @@ def load(path: str = LIB_PATH):
         "pic_adjoint_reorder": (I, [P, P, P, ctypes.c_size_t, ctypes.POINTER(P), ctypes.POINTER(P),
                                     ctypes.POINTER(P), ctypes.POINTER(P), P]),
         "pic_solve_poisson": (I, [P, I, D, ctypes.POINTER(I64), ctypes.POINTER(D), P]),
+        "pic_set_vector_potential": (I, [P, P, P]),
+        "pic_get_vector_potential": (I, [P, P, P]),
         "pic_destroy": (None, [P]),
         "pic_last_error": (ctypes.c_char_p, [P]),
         "pic_version": (ctypes.c_char_p, []),

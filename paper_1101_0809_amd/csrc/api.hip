@@ -145,6 +145,15 @@ int make_grid(const pic_grid_desc* g, GridK* k, std::string* msg)
     k->src_omega = g->src_omega;
     k->src_ramp = g->src_ramp;
     k->aux = nullptr;
+    if ((g->field_form != 0 && g->field_form != 1) || g->reserved2 != 0) {
+        *msg = "field_form must be 0 (B) or 1 (vector potential) and reserved2 0";
+        return PIC_EINVAL;
+    }
+    if (g->field_form == 1 && g->src_kind != 0) {
+        *msg = "the vector-potential form does not carry the plane-wave source";
+        return PIC_EINVAL;
+    }
+    k->field_form = g->field_form;
     return PIC_OK;
 }
 
@@ -158,6 +167,7 @@ size_t workspace_bytes(const GridK& k, uint32_t nkeys)
     b += align_up(8 * sizeof(unsigned long long), kAlign);               // counters
     b += align_up(3 * (size_t)k.ncell * 8, kAlign);                      // B^n for the particles
     b += align_up(3 * (size_t)k.ncell * 8, kAlign);                      // adjoint scratch
+    if (k.field_form == 1) b += align_up(3 * (size_t)k.ncell * 8, kAlign);  // vector potential
     b += align_up(2 * (size_t)PIC_AUX * 8, kAlign);                      // source line (last)
     return b;
 }
@@ -305,8 +315,13 @@ int pic_init_grid(const pic_grid_desc* g, void* fields, size_t field_bytes, void
     c.counters = (unsigned long long*)take(8 * sizeof(unsigned long long));
     c.bn = (double*)take(3 * (size_t)k.ncell * 8);
     c.adj = (double*)take(3 * (size_t)k.ncell * 8);
+    if (k.field_form == 1) c.avec = (double*)take(3 * (size_t)k.ncell * 8);
     c.k.aux = (double*)take(2 * (size_t)PIC_AUX * 8);  // last: its place is documented
     hipError_t e = hipMemset(c.rho_bg, 0, (size_t)k.ncell * 8);
+    if (e == hipSuccess && c.avec) {  // A = 0 and B = curl_h A = 0
+        e = hipMemset(c.avec, 0, 3 * (size_t)k.ncell * 8);
+        if (e == hipSuccess) e = hipMemset(c.fields + 3 * k.ncell, 0, 3 * (size_t)k.ncell * 8);
+    }
     if (e == hipSuccess) e = hipMemset(c.k.aux, 0, 2 * (size_t)PIC_AUX * 8);
     if (e == hipSuccess) e = hipMemset(c.counters, 0, 8 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -410,7 +425,10 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
         // both B half steps use E^n: one kernel writes B^n (for the particles)
         // to the workspace and B^{n+1/2} in place
         mark(0);
-        if (e == hipSuccess) e = launch_field_half_b_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 2 : 0);
+        if (e == hipSuccess)
+            e = c.k.field_form == 1
+                    ? launch_field_half_a_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 2 : 0)
+                    : launch_field_half_b_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 2 : 0);
         mark(1);
         for (int i = 0; i < c.nsp && e == hipSuccess; ++i)
             if (c.sp[i].d.mobile) e = launch_particle_step(c, c.sp[i], s);
@@ -451,6 +469,7 @@ int pic_field_solve(pic_ctx* ctx, int what, void* stream)
     Ctx& c = ctx->c;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
+    if (c.k.field_form != 0) return fail(&c, PIC_ESTATE, "field_solve advances B; this context carries A");
     if (what == PIC_B_HALF) {
         e = launch_field_half_b(c, s);
     } else if (what == PIC_E_FULL) {
@@ -467,6 +486,7 @@ static int adjoint_ready(Ctx& c)
 {
     if (c.g.precision != PIC_FP64) return fail(&c, PIC_EINVAL, "the adjoint is FP64 only");
     if (c.k.src_kind != 0) return fail(&c, PIC_EINVAL, "the adjoint does not cover the plane-wave source");
+    if (c.k.field_form != 0) return fail(&c, PIC_EINVAL, "the adjoint covers the B form only");
     if (c.g.order != 1 || c.g.interp != 0)
         return fail(&c, PIC_EINVAL, "the adjoint covers the alternating order 1 1/2 only");
     return PIC_OK;
@@ -587,6 +607,30 @@ int pic_solve_poisson(pic_ctx* ctx, int neutralize, double tol, int64_t* iterati
     if (iterations) *iterations = it;
     if (residual) *residual = res;
     if (res > tol) return fail(&c, PIC_ESTATE, "Poisson solve did not reach the tolerance");
+    return PIC_OK;
+}
+
+int pic_set_vector_potential(pic_ctx* ctx, const double* A, void* stream)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    if (!A) return fail(&c, PIC_EINVAL, "null vector potential");
+    if (c.k.field_form != 1) return fail(&c, PIC_ESTATE, "the context carries B (field_form 0)");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c.avec, A, 3 * (size_t)c.k.ncell * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_b_of_a(c, s);
+    if (e != hipSuccess) return hip_fail(&c, e, "set_vector_potential");
+    return PIC_OK;
+}
+
+int pic_get_vector_potential(pic_ctx* ctx, double* A, void* stream)
+{
+    if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
+    Ctx& c = ctx->c;
+    if (!A) return fail(&c, PIC_EINVAL, "null output");
+    if (c.k.field_form != 1) return fail(&c, PIC_ESTATE, "the context carries B (field_form 0)");
+    hipError_t e = hipMemcpyAsync(A, c.avec, 3 * (size_t)c.k.ncell * 8, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(&c, e, "get_vector_potential");
     return PIC_OK;
 }
 

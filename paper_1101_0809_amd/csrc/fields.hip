@@ -175,6 +175,58 @@ __global__ __launch_bounds__(kFieldThreads) void k_update_e(GridK g, double* __r
     Jz[p] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Vector-potential form (Section 4.2, Eq. dadt): A at the E points,
+// A^{n+1/2} = A^{n-1/2} - c dt E^n, and B = curl_h A with the same backward
+// differences as the B update: B^x = (A^z - A^z_{j-1})/dy - (A^y - A^y_{k-1})/dz,
+// B^y = (A^x - A^x_{k-1})/dz - (A^z - A^z_{i-1})/dx,
+// B^z = (A^y - A^y_{i-1})/dx - (A^x - A^x_{j-1})/dy.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFieldThreads) void k_advance_a(GridK g, const double* __restrict__ f,
+                                                             double* __restrict__ A,
+                                                             unsigned long long* __restrict__ zero, int nzero)
+{
+    const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
+    if (p < nzero) zero[p] = 0;  // counters of the particle kernels that follow
+    if (p >= g.ncell) return;
+    const int64_t N = g.ncell;
+    const double cdt = g.c * g.dt;
+    for (int a = 0; a < 3; ++a) A[a * N + p] -= cdt * f[a * N + p];
+}
+
+// curl_h of (A + s E) at cell p (s = c dt / 2 gives A^n from A^{n+1/2}).
+__device__ __forceinline__ void curl_a(const GridK& g, const double* __restrict__ A, const double* __restrict__ E,
+                                       double s, const CellIdx& c, double out[3])
+{
+    const int64_t N = g.ncell, p = c.p;
+    const int64_t sy = g.n[0], sz = (int64_t)g.n[0] * g.n[1];
+    const int64_t im = c.i == 0 ? p + (g.n[0] - 1) : p - 1;
+    const int64_t jm = c.j == 0 ? p + (int64_t)(g.n[1] - 1) * sy : p - sy;
+    const int64_t km = c.k == 0 ? p + (int64_t)(g.n[2] - 1) * sz : p - sz;
+    auto v = [&](int comp, int64_t q) { return A[comp * N + q] + s * E[comp * N + q]; };
+    out[0] = (v(2, p) - v(2, jm)) * g.inv_h[1] - (v(1, p) - v(1, km)) * g.inv_h[2];
+    out[1] = (v(0, p) - v(0, km)) * g.inv_h[2] - (v(2, p) - v(2, im)) * g.inv_h[0];
+    out[2] = (v(1, p) - v(1, im)) * g.inv_h[0] - (v(0, p) - v(0, jm)) * g.inv_h[1];
+}
+
+// B^n = curl_h A^n into bn (A^n = A^{n+1/2} + (c dt / 2) E^n) and B^{n+1/2} =
+// curl_h A^{n+1/2} into the field buffer (bn may be null: B planes only).
+__global__ __launch_bounds__(kFieldThreads) void k_b_of_a(GridK g, double* __restrict__ f, const double* __restrict__ A,
+                                                          double* __restrict__ bn)
+{
+    const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
+    if (p >= g.ncell) return;
+    const int64_t N = g.ncell;
+    const CellIdx c = cell_of(p, g);
+    double b[3];
+    if (bn) {
+        curl_a(g, A, f, 0.5 * g.c * g.dt, c, b);
+        for (int a = 0; a < 3; ++a) bn[a * N + p] = b[a];
+    }
+    curl_a(g, A, f, 0.0, c, b);
+    for (int a = 0; a < 3; ++a) f[(3 + a) * N + p] = b[a];
+}
+
 }  // namespace
 
 hipError_t launch_field_half_b(const Ctx& c, hipStream_t s)
@@ -202,6 +254,27 @@ hipError_t launch_field_update_e(const Ctx& c, hipStream_t s, int64_t step)
     if (c.k.src_kind == 1)  // the line's E^y at t = (step + 1) dt
         hipLaunchKernelGGL(k_aux_update_e, dim3(1), dim3(kFieldThreads), 0, s, c.k,
                            (double)(step + 1) * c.k.dt);
+    return hipGetLastError();
+}
+
+}  // namespace pic
+
+namespace pic {
+
+hipError_t launch_field_half_a_pair(const Ctx& c, hipStream_t s, unsigned long long* zero, int nzero)
+{
+    const unsigned blocks = (unsigned)((std::max<int64_t>(c.k.ncell, nzero) + kFieldThreads - 1) / kFieldThreads);
+    hipLaunchKernelGGL(k_advance_a, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields, c.avec, zero, nzero);
+    const unsigned cb = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
+    hipLaunchKernelGGL(k_b_of_a, dim3(cb), dim3(kFieldThreads), 0, s, c.k, c.fields, c.avec, c.bn);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_of_a(const Ctx& c, hipStream_t s)
+{
+    const unsigned cb = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
+    hipLaunchKernelGGL(k_b_of_a, dim3(cb), dim3(kFieldThreads), 0, s, c.k, c.fields, (const double*)c.avec,
+                       (double*)nullptr);
     return hipGetLastError();
 }
 

@@ -96,6 +96,7 @@ struct GridK {
     int src_plane;
     double src_amp, src_omega, src_ramp;
     double* aux;       // auxiliary line: E^y[PIC_AUX] then B^z[PIC_AUX] (workspace)
+    int field_form;    // 0: B carried; 1: vector potential carried (B = curl A)
 };
 
 struct Ctx {
@@ -113,6 +114,7 @@ struct Ctx {
     double* red = nullptr;      // reduction partials
     double* bn = nullptr;       // B^n of the current step (3 planes), read by the particles
     double* adj = nullptr;      // adjoint scratch (3 planes): lambda_J of a reverse step
+    double* avec = nullptr;     // vector potential A^{n-1/2} (3 planes, field form 1 only)
     unsigned long long* counters = nullptr;  // [0] range errors, [1] fallback particles,
                                              // [2] particles processed
     uint32_t nkeys = 0;
@@ -132,6 +134,11 @@ hipError_t launch_field_half_b(const Ctx& c, hipStream_t s);
 hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s, unsigned long long* zero = nullptr,
                                     int nzero = 0);
 hipError_t launch_field_update_e(const Ctx& c, hipStream_t s, int64_t step);
+// Field form 1: A^{n+1/2} = A^{n-1/2} - c dt E^n, B^n = curl_h A^n into bn,
+// B^{n+1/2} = curl_h A^{n+1/2} into the B planes (zeroing counters as above).
+hipError_t launch_field_half_a_pair(const Ctx& c, hipStream_t s, unsigned long long* zero = nullptr, int nzero = 0);
+// B planes = curl_h A (field form 1).
+hipError_t launch_b_of_a(const Ctx& c, hipStream_t s);
 hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s);
 hipError_t launch_load(Ctx& c, Species& sp, int64_t n, const double* x, const double* w,
                        const double* weight, hipStream_t s);

@@ -50,12 +50,13 @@ class Sim:
                  precision: str = "fp64", dx: float = 1.0, dy: float = 1.0, dz: float = 1.0,
                  c: float = 1.0, sort_every: int = 0, bext=(0.0, 0.0, 0.0),
                  device: str = "cuda:0", fields: np.ndarray = None, source=None, order: int = 1,
-                 interp: str = "alternating"):
+                 interp: str = "alternating", field_form: str = "B"):
         """source: None or (plane, amplitude, omega, ramp time) for the +x
         E^y plane-wave source of include/pic.h.  order: alternating form
         factor order l_a = order + 1/2 (1, or 2 in FP64).  interp:
         "alternating" or "conventional" (the uniform-order comparison of
-        Eq. wrong1; order 1, FP64)."""
+        Eq. wrong1; order 1, FP64).  field_form: "B", or "A" to carry the
+        vector potential (Section 4.2, Eq. dadt) with B = curl_h A."""
         if not torch.cuda.is_available():
             raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
         self.lib = L.load()
@@ -66,6 +67,7 @@ class Sim:
         d.precision = {"fp64": L.PIC_FP64, "fp32c": L.PIC_FP32C}[precision]
         d.order, d.sort_every = int(order), sort_every
         d.interp = {"alternating": 0, "conventional": 1}[interp]
+        d.field_form = {"B": 0, "A": 1}[field_form]
         d.dx, d.dy, d.dz, d.dt, d.c = dx, dy, dz, dt, c
         for a in range(3):
             d.bext[a] = float(bext[a])
@@ -190,6 +192,20 @@ class Sim:
                                                ctypes.byref(res), _stream()))
         return it.value, res.value
 
+    def set_vector_potential(self, A):
+        """A^{n-1/2} (3, nz, ny, nx) of a field_form "A" context; B becomes curl_h A."""
+        A = A if isinstance(A, torch.Tensor) else _dev_f64(A, self.device)
+        A = A.to(self.device, torch.float64).contiguous()
+        assert A.numel() == 3 * self.ncell
+        self._check(self.lib.pic_set_vector_potential(self.ctx, ctypes.c_void_p(A.data_ptr()), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def vector_potential(self) -> np.ndarray:
+        A = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.pic_get_vector_potential(self.ctx, ctypes.c_void_p(A.data_ptr()), _stream()))
+        torch.cuda.synchronize()
+        return A.cpu().numpy()
+
     def diagnostics(self) -> dict:
         d = L.Diag()
         self._check(self.lib.pic_diagnostics(self.ctx, ctypes.byref(d), _stream()))
@@ -239,7 +255,8 @@ class Sim:
         sim = cls(d["nx"], d["ny"], d["nz"], d["dt"], dims=d["dims"], precision=prec,
                   dx=d["dx"], dy=d["dy"], dz=d["dz"], c=d["c"], sort_every=d["sort_every"],
                   bext=tuple(d["bext"]), device=device, source=src, order=d["order"],
-                  interp=("alternating", "conventional")[d["interp"]])
+                  interp=("alternating", "conventional")[d["interp"]],
+                  field_form=("B", "A")[d["field_form"]])
         for sp in st["species"]:
             sim.add_species(sp["q"], sp["m"], sp["capacity"], mobile=sp["mobile"])
         sim.fields_t.copy_(st["fields"])

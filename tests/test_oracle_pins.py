@@ -671,3 +671,22 @@ def test_poisson_single_mode_closed_form():
     phi = poisson.solve(g, rho)
     lam = (2 - 2 * np.cos(2 * np.pi * m / n)) / dx ** 2
     assert np.max(np.abs(phi - 4 * np.pi * rho / lam)) < 1e-12
+
+
+def test_vector_potential_form_equals_b_form():
+    """Advancing A by Eq. dadt and taking B = curl_h A gives the same run as
+    advancing B by Eq. updateB (curl_h of the A update is the B update), and
+    div_h B stays zero."""
+    wl = picgen.Workload("aform", 8, 7, 6, 3, 0.45, 3, (0.2,) * 3, 0.3, 12, seed=9, drift=0.1)
+    e = picgen.electrons(wl)
+    g = oracle.Grid(8, 7, 6, wl.dt)
+    A0 = RNG.normal(0, 1e-3, (3,) + g.shape)
+    ref = oracle.State(g, [oracle.Species(e.x, e.w, e.weight, q=-1.0, m=1.0)])
+    ref.fields[3:6] = oracle.curl_a(g, A0)
+    st = oracle.State(g, [oracle.Species(e.x, e.w, e.weight, q=-1.0, m=1.0)])
+    ref.step(wl.steps)
+    A = oracle.step_vector_potential(st, A0, wl.steps)
+    scale = np.max(np.abs(ref.fields[0:6]))
+    assert np.max(np.abs(st.fields[0:6] - ref.fields[0:6])) <= 1e-13 * scale
+    assert np.max(np.abs(st.species[0].w - ref.species[0].w)) <= 1e-13
+    assert np.max(np.abs(st.div_b())) <= 1e-14 * np.max(np.abs(A)) / 0.5
