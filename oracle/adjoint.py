@@ -256,3 +256,22 @@ def step_vjp(g: Grid, E, B, x, w, weight, q, m, bext, lamE, lamB, lamx, lamw):
          + (sp[0].w * c(lamw)).sum())
     L.backward()
     return E.grad.numpy(), B.grad.numpy(), x0.grad.numpy(), w0.grad.numpy(), b0.grad.numpy()
+
+
+def loss_and_grad_species(g: Grid, species, bext, nsteps):
+    """loss_and_grad for several mobile species: species is a list of
+    (x, w, weight, q, m); returns (L, [(dL/dw, dL/dx) per species], dL/dbext)."""
+    shape = (3, g.nz, g.ny, g.nx)
+    E = torch.zeros(shape, dtype=DT)
+    B = torch.zeros(shape, dtype=DT)
+    b0 = torch.tensor(bext, dtype=DT, requires_grad=True)
+    leaves, sp = [], []
+    for x, w, weight, q, m in species:
+        x0 = torch.tensor(x, dtype=DT, requires_grad=True)
+        w0 = torch.tensor(w, dtype=DT, requires_grad=True)
+        leaves.append((w0, x0))
+        sp.append(Species(x0, w0, torch.tensor(weight, dtype=DT), q, m))
+    E, B, _ = run(g, E, B, sp, b0, nsteps)
+    L = field_energy(g, E, B)
+    L.backward()
+    return float(L.detach()), [(w0.grad.numpy(), x0.grad.numpy()) for w0, x0 in leaves], b0.grad.numpy()

@@ -93,23 +93,6 @@ __device__ __forceinline__ Dual<N> operator*(const Dual<N>& a, double b)
 }
 template <int N>
 __device__ __forceinline__ Dual<N> operator*(double b, const Dual<N>& a) { return a * b; }
-template <int N>
-__device__ __forceinline__ Dual<N> operator/(const Dual<N>& a, const Dual<N>& b)
-{
-    const double q = a.v / b.v;
-    Dual<N> r(q);
-    for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - q * b.d[i]) / b.v;
-    return r;
-}
-template <int N>
-__device__ __forceinline__ Dual<N> sqrt(const Dual<N>& a)
-{
-    const double s = ::sqrt(a.v);
-    Dual<N> r(s);
-    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * (0.5 / s);
-    return r;
-}
-
 __device__ __forceinline__ void grid_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 constexpr int kAdjThreads = 256;

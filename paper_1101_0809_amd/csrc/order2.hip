@@ -10,8 +10,9 @@
 // B^n over the cells the tile's particles can read (offsets -2 .. +2 around
 // each particle cell, plus a margin M for drift since the sort) and
 // accumulates the current over the cells their windows can reach (-3 .. +3,
-// plus M) in LDS, added to the grid once at the end.  A particle further than
-// M cells from its tile reads and adds in global memory instead.
+// plus M) in LDS, added to the grid once at the end; in 3D the two regions
+// are handled by two passes.  A particle further than M cells from its tile
+// reads and adds in global memory instead.
 #include "pic_math.h"
 
 namespace pic {
@@ -19,23 +20,15 @@ namespace {
 
 __device__ __forceinline__ void add_global(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-template <int D>
-struct O2Cfg;
-template <>
-struct O2Cfg<2> {
-    static constexpr int T = kTile2, M = 2, NT = 256;
-};
-template <>
-struct O2Cfg<3> {
-    // 12^3 field cells (83 KB) and 14^3 current cells (66 KB) of LDS
-    static constexpr int T = kTile3, M = 0, NT = 512;
-};
+// The single pass, used in 2D3V (its two regions fit in LDS with margin 2).
+constexpr int kO2M2 = 2, kO2NT2 = 256;
 
 template <int D>
-__global__ __launch_bounds__(O2Cfg<D>::NT) void k_step_o2(GridK g, StepArgs a, const double* __restrict__ fields,
-                                                          const double* __restrict__ bfield, double* __restrict__ Jg)
+__global__ __launch_bounds__(kO2NT2) void k_step_o2(GridK g, StepArgs a, const double* __restrict__ fields,
+                                                    const double* __restrict__ bfield, double* __restrict__ Jg)
 {
-    constexpr int T = O2Cfg<D>::T, M = O2Cfg<D>::M, NT = O2Cfg<D>::NT;
+    static_assert(D == 2, "the 3D order-2 1/2 step runs in two passes");
+    constexpr int T = kTile2, M = kO2M2, NT = kO2NT2;
     constexpr int LF = T + 4 + 2 * M;  // field region: cells T0-2-M .. T0+T+1+M
     constexpr int LJ = T + 6 + 2 * M;  // current region: cells T0-3-M .. T0+T+2+M
     constexpr int NF = D == 3 ? LF * LF * LF : LF * LF;
@@ -453,7 +446,7 @@ hipError_t launch_particle_step_o2(Ctx& c, Species& sp, hipStream_t s)
         hipLaunchKernelGGL(k_push_o2_3d, dim3(c.k.ntiles), dim3(kO2NT3), 0, s, c.k, a, sp.alt, c.fields, c.bn);
         hipLaunchKernelGGL(k_deposit_o2_3d, dim3(c.k.ntiles), dim3(kO2NT3), 0, s, c.k, a, sp.alt, J);
     } else
-        hipLaunchKernelGGL(k_step_o2<2>, dim3(c.k.ntiles), dim3(O2Cfg<2>::NT), 0, s, c.k, a, c.fields, c.bn, J);
+        hipLaunchKernelGGL(k_step_o2<2>, dim3(c.k.ntiles), dim3(kO2NT2), 0, s, c.k, a, c.fields, c.bn, J);
     return hipGetLastError();
 }
 

@@ -151,3 +151,25 @@ def test_step_vjp_matches_directional_difference(dims):
     fd = (functional(h) - functional(-h)) / (2 * h)
     an = sum(np.sum(o * d) for o, d in zip(out, v))
     assert abs(an - fd) <= 1e-7 * max(abs(fd), 1.0), (an, fd)
+
+
+def test_torch_step_with_two_mobile_species_matches_c_oracle():
+    """Electrons and mobile positive ions (q = +1, m = 25) in one run: the
+    torch restatement equals the C oracle after 8 steps (2D3V)."""
+    import torch
+    nx, ny, nz, dt, steps = 8, 6, 1, 0.5, 8
+    xe, we, wte = _case(nx, ny, nz, 40, 31, w_th=0.2)
+    xi, wi, wti = _case(nx, ny, nz, 30, 32, w_th=0.05)
+    xe[2] = 0.0
+    xi[2] = 0.0
+    st = oracle.State(oracle.Grid(nx, ny, nz, dt, bext=(0.0, 0.0, 0.03)),
+                      [oracle.Species(xe, we, wte, q=-1.0, m=1.0), oracle.Species(xi, wi, wti, q=1.0, m=25.0)])
+    st.step(steps)
+    g = ad.Grid(nx, ny, nz, dt)
+    E = torch.zeros((3, nz, ny, nx), dtype=torch.float64)
+    sp = [ad.Species(torch.tensor(xe), torch.tensor(we), torch.tensor(wte), -1.0, 1.0),
+          ad.Species(torch.tensor(xi), torch.tensor(wi), torch.tensor(wti), 1.0, 25.0)]
+    E, B, sp = ad.run(g, E, torch.zeros_like(E), sp, torch.tensor([0.0, 0.0, 0.03], dtype=torch.float64), steps)
+    assert np.max(np.abs(E.numpy() - st.fields[0:3])) <= 1e-13 * np.max(np.abs(st.fields[0:3]))
+    for k in range(2):
+        assert np.max(np.abs(sp[k].w.numpy() - st.species[k].w)) < 1e-13

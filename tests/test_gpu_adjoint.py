@@ -342,3 +342,32 @@ def test_full_size_2d_beams_gradient_matches_central_differences():
         fd = (loss(e.w + h * d) - loss(e.w - h * d)) / (2 * h)
         an = float(np.sum(gw * d))
         assert abs(an - fd) <= 1e-4 * abs(an), (an, fd)
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_adjoint_two_mobile_species(dims):
+    """Electrons and mobile ions (q = +1, m = 25): per-species particle
+    adjoints and dL/dB_ext against the reference gradient, tape and
+    checkpoint modes."""
+    from paper_1101_0809_amd import Sim
+    from paper_1101_0809_amd.adjoint import field_energy_grad
+    box = (16, 12, 1) if dims == 2 else (8, 7, 6)
+    dt = 0.5 if dims == 2 else 0.45
+    xe, we, wte = picgen.beams(box, 300, 51, w_th=0.1, drift=0.15, dims=dims)
+    xi, wi, wti = picgen.beams(box, 200, 52, w_th=0.02, dims=dims)
+    bext = (0.01, 0.0, 0.04)
+    L_ref, grads, gb_ref = ad.loss_and_grad_species(
+        ad.Grid(*box, dt), [(xe, we, wte, -1.0, 1.0), (xi, wi, wti, 1.0, 25.0)], bext, 10)
+    for every in (None, 3):
+        sim = Sim(nx=box[0], ny=box[1], nz=box[2], dt=dt, dims=dims, sort_every=4, bext=bext)
+        sim.add_species(-1.0, 1.0, capacity=300)
+        sim.load(0, xe, we, wte)
+        sim.add_species(1.0, 25.0, capacity=200)
+        sim.load(1, xi, wi, wti)
+        L, gx, gw, gb = field_energy_grad(sim, 10, every=every)
+        assert abs(L - L_ref) <= 1e-12 * L_ref
+        for k in range(2):
+            _close(gw[k].cpu().numpy(), grads[k][0])
+            _close(gx[k].cpu().numpy()[:dims], grads[k][1][:dims])
+        _close(gb.cpu().numpy(), gb_ref)
+        sim.close()
