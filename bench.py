@@ -269,7 +269,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="3d_64cube_8ppc")
+    ap.add_argument("--workload", default=None,
+                    help="workload name (default 3d_64cube_8ppc; 2d3v_256sq_beams with --adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32c"], default="both")
     ap.add_argument("--copy-probe", action="store_true",
@@ -290,8 +291,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.adjoint and args.gpus == 1:
         import picgen
-        name = args.workload if args.workload != "3d_64cube_8ppc" else "2d3v_256sq_beams"
-        wl = picgen.WORKLOADS[name]
+        wl = picgen.WORKLOADS[args.workload or "2d3v_256sq_beams"]
         r = run_adjoint(wl, args.every)
         fwd_step = r["forward_ms"] / wl.steps
         line = {
@@ -337,7 +337,7 @@ def main(argv=None):
         return 2
 
     import picgen
-    wl = picgen.WORKLOADS[args.workload]
+    wl = picgen.WORKLOADS[args.workload or "3d_64cube_8ppc"]
     precs = ["fp64", "fp32c"] if args.precision == "both" else [args.precision]
     if args.order == 2 or args.interp == "conventional":
         precs = ["fp64"]

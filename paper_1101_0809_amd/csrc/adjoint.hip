@@ -323,6 +323,9 @@ __device__ __forceinline__ void deposit_reverse(const double (&dm)[3][4], const 
             ldm[comp][0] += jfac[comp] * (lP[0] + lP[1]);
             ldm[comp][1] += jfac[comp] * lP[1];
             ldm[comp][3] -= jfac[comp] * lP[2];
+            // one component's 48 lambda_J loads in flight at a time: the
+            // scheduler would otherwise hoist all 144 and run out of registers
+            __builtin_amdgcn_sched_barrier(0);
         }
     } else {
         for (int comp = 0; comp < 2; ++comp) {
@@ -705,6 +708,81 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
     flush_bext(sb, lbp, a.lam_bext);
 }
 
+// 3D tile kernel.  The fields, B^n and lambda_J are read from global memory
+// (the tile's neighbourhood stays in L2); lambda_E and lambda_B are
+// accumulated over the field region (cells T0-1-M .. T0+T+M, M = 2: 132 KB)
+// in LDS and added to the grid once at the end, which removes the global
+// atomics that dominated the one-thread-per-particle kernel.  A particle more
+// than M cells outside its tile adds in global memory.
+constexpr int kAdjT3 = kTile3;
+constexpr int kAdjM3 = 2;
+constexpr int kAdjLF3 = kAdjT3 + 2 + 2 * kAdjM3;
+constexpr int kAdjNF3 = kAdjLF3 * kAdjLF3 * kAdjLF3;
+constexpr int kAdjThreads3 = 256;
+
+struct TileAcc3 : GlobalAcc<3> {
+    double* sacc;  // 6 x kAdjNF3
+    int fo;        // particle cell in the field region
+    __device__ TileAcc3(const GridK& g_, const AdjArgs& a_, double* s, int f) : GlobalAcc<3>(g_, a_), sacc(s), fo(f) {}
+    __device__ void add(int comp, int da, int db, int dc, double v) const
+    {
+        atomicAdd(&sacc[comp * kAdjNF3 + fo + da + db * kAdjLF3 + dc * kAdjLF3 * kAdjLF3], v);
+    }
+};
+
+__global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, const int64_t* __restrict__ tile_start,
+                                                            int split)
+{
+    constexpr int T = kAdjT3, M = kAdjM3, LF = kAdjLF3, NF = kAdjNF3, NT = kAdjThreads3;
+    __shared__ double sacc[6 * NF];
+    __shared__ double sb[3];
+    const int unit = xcd_tile(blockIdx.x, g.ntiles * split);
+    const int tile = unit / split, part = unit - tile * split;
+    const int T0[3] = {(tile % g.nt[0]) * T, ((tile / g.nt[0]) % g.nt[1]) * T, (tile / (g.nt[0] * g.nt[1])) * T};
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    for (int e = threadIdx.x; e < 6 * NF; e += NT) sacc[e] = 0.0;
+    if (threadIdx.x < 3) sb[threadIdx.x] = 0.0;
+    __syncthreads();
+    double lbp[3] = {0.0, 0.0, 0.0};
+    const int64_t begin = tile_start[tile], end = tile_start[tile + 1];
+    for (int64_t p = begin + part * NT + threadIdx.x; p < end; p += (int64_t)split * NT) {
+        int i0[3];
+        double d0[3], w0[3], qp;
+        int64_t li;
+        load_particle<3>(a, p, i0, d0, w0, qp, li);
+        int rel[3];
+        bool inside = true;
+        for (int ax = 0; ax < 3; ++ax) {
+            int r = i0[ax] - T0[ax];
+            const int n = g.n[ax];
+            if (r > n / 2) r -= n;
+            if (r < -(n / 2)) r += n;
+            rel[ax] = r;
+            inside = inside && r >= -M && r <= T - 1 + M;
+        }
+        if (inside) {
+            TileAcc3 acc(g, a, sacc, (rel[0] + 1 + M) + (rel[1] + 1 + M) * LF + (rel[2] + 1 + M) * LF * LF);
+            adj_particle<3>(g, a, acc, i0, d0, w0, qp, li, lbp);
+        } else {
+            GlobalAcc<3> acc(g, a);
+            adj_particle<3>(g, a, acc, i0, d0, w0, qp, li, lbp);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 6 * NF; e += NT) {
+        const double v = sacc[e];
+        if (v == 0.0) continue;
+        const int comp = e / NF, r = e - comp * NF;
+        const int gx = wrapi(T0[0] - 1 - M + r % LF, nx);
+        const int gy = wrapi(T0[1] - 1 - M + (r / LF) % LF, ny);
+        const int gz = wrapi(T0[2] - 1 - M + r / (LF * LF), nz);
+        const int64_t cell = ((int64_t)gz * ny + gy) * nx + gx;
+        grid_add(comp < 3 ? &a.lamE[comp * N + cell] : &a.lamB[(comp - 3) * N + cell], v);
+    }
+    flush_bext(sb, lbp, a.lam_bext);
+}
+
 unsigned cells_blocks(int64_t n) { return (unsigned)((n + kCurlThreads - 1) / kCurlThreads); }
 
 }  // namespace
@@ -926,7 +1004,11 @@ hipError_t launch_adjoint_step(const Ctx& c, const void* record, bool by_id, dou
         a.lam_bext = lam_bext;
         a.by_id = by_id ? 1 : 0;
         const unsigned pb = (unsigned)((sp.n + kAdjThreads - 1) / kAdjThreads);
-        if (c.k.dims == 3) {
+        if (c.k.dims == 3 && pv.tiles) {
+            const int split = (int)std::min<int64_t>(8, std::max<int64_t>(1, (512 + c.k.ntiles - 1) / c.k.ntiles));
+            hipLaunchKernelGGL(k_adj_tile3, dim3((unsigned)(c.k.ntiles * split)), dim3(kAdjThreads3), 0, s, c.k, a,
+                               pv.tile_start, split);
+        } else if (c.k.dims == 3) {
             hipLaunchKernelGGL(k_adj_particles<3>, dim3(pb), dim3(kAdjThreads), 0, s, c.k, a);
         } else if (pv.tiles) {
             // enough workgroups to fill the chip: several per tile when tiles are few

@@ -172,7 +172,7 @@ def test_autograd_function_and_central_difference_of_gpu_forward():
     L = field_energy(xt, wt, torch.tensor(weight, device=dev), bt, grid, c["steps"], every=4)
     gx, gw, gb = torch.autograd.grad(3.0 * L, (xt, wt, bt))
     L0, gx0, gw0, gb0 = _gpu_grad(c["box"], 2, c["dt"], x, w, weight, c["bext"], c["steps"], 4)
-    assert abs(float(L) - L0) <= 1e-13 * L0
+    assert abs(float(L.detach()) - L0) <= 1e-13 * L0
     _close(gw.cpu().numpy(), 3.0 * gw0)
     _close(gx.cpu().numpy()[:2], 3.0 * gx0[:2])
     _close(gb.numpy(), 3.0 * gb0)
