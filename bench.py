@@ -13,7 +13,12 @@ durations of the roofline and the phase breakdown.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 10]
 
-prints one JSON line.
+prints one JSON line.  Other measurements, each printing its own line:
+--workload NAME (another workload of picgen.WORKLOADS), --order 2 (the
+alternating order 2 1/2), --interp conventional (the uniform-order gather of
+Eq. wrong1), --adjoint (gradient time over forward time of the 2D3V
+differentiable workload, or of --workload), --copy-probe (a plain device copy
+for scaling rocprofv3 byte counters).
 """
 from __future__ import annotations
 

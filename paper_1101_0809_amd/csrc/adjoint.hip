@@ -18,11 +18,19 @@
 //   lambda_J = -4 pi dt lambda_E',          lambda_B2 = lambda_B' + C lambda_E',
 //   lambda_E = lambda_E' - (1/2) D lambda_B2 + (particles) - (1/2) D lambda_Bn,
 //   lambda_Bn = lambda_B2 + (particles),     lambda_B = lambda_Bn,
-// and per particle the derivatives of its gather, push, move and deposit,
-// evaluated by the same formulas as the step (pic_math.h) on forward-mode dual
-// numbers.  The particle part adds alpha lambda_Ep into lambda_E and beta
-// lambda_Bp into lambda_B (atomics) and sums lambda_Bp into the external-field
-// gradient.
+// and per particle the reverse of its gather, push, move and deposit: the
+// forward values are recomputed by the step's own formulas (pic_math.h); the
+// current and the push are reversed by hand (contractions of lambda_J with the
+// window sums and differences; cross-product identities), and the gather's
+// derivative in the start offsets comes from forward-mode dual numbers.  The
+// particle part adds alpha lambda_Ep into lambda_E and beta lambda_Bp into
+// lambda_B (in LDS per tile, or with atomics) and sums lambda_Bp into the
+// external-field gradient.
+//
+// Kernels: k_adj_seed_b/e (loss seed), k_adj_pre (B^n, lambda_J, lambda_B),
+// k_adj_curl (lambda_E), k_adj_tile2 / k_adj_tile3 (particles by tile),
+// k_adj_particles (particles of an unsorted context), k_copy_segments
+// (records), k_inverse / k_permute (particle adjoints between orders).
 #include <algorithm>
 
 #include "pic_math.h"
