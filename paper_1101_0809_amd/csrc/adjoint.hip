@@ -22,7 +22,9 @@
 // forward values are recomputed by the step's own formulas (pic_math.h); the
 // current and the push are reversed by hand (contractions of lambda_J with the
 // window sums and differences; cross-product identities), and the gather's
-// derivative in the start offsets comes from forward-mode dual numbers.  The
+// derivative in the start offsets comes from forward-mode dual numbers (2D,
+// and the generic kernel) or from separable partial sums over the stencil in
+// a second pass that also does the scatter (3D tile kernel).  The
 // particle part adds alpha lambda_Ep into lambda_E and beta lambda_Bp into
 // lambda_B (in LDS per tile, or with atomics) and sums lambda_Bp into the
 // external-field gradient.
@@ -305,6 +307,7 @@ __device__ __forceinline__ void deposit_reverse(const double (&dm)[3][4], const 
 {
     const double third = 1.0 / 3.0;
     if (D == 3) {
+#pragma unroll
         for (int comp = 0; comp < 3; ++comp) {
             const int u = (comp + 1) % 3, v = (comp + 2) % 3;
             const double P[3] = {dm[comp][0], dm[comp][0] + dm[comp][1], -dm[comp][3]};
@@ -327,12 +330,13 @@ __device__ __forceinline__ void deposit_reverse(const double (&dm)[3][4], const 
                     ldp[v][c] += ltr * dp[u][b];
                     ldm[u][b] += third * ltr * dm[v][c];
                     ldm[v][c] += third * ltr * dm[u][b];
+                    // three lambda_J loads in flight per window column: the reverse
+                    // step runs two waves per SIMD in 256 registers
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             ldm[comp][0] += jfac[comp] * (lP[0] + lP[1]);
             ldm[comp][1] += jfac[comp] * lP[1];
             ldm[comp][3] -= jfac[comp] * lP[2];
-            // one component's 48 lambda_J loads in flight at a time: the
-            // scheduler would otherwise hoist all 144 and run out of registers
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
@@ -385,15 +389,18 @@ template <int D>
 struct GlobalAcc {
     const GridK& g;
     const AdjArgs& a;
-    int xi[3], yj[3], cx[4], cy[4];
-    int64_t zk[3], cz[4];
+    // byte offsets within one plane (a plane is below 4 GiB): the plane base
+    // is uniform once the component is known at compile time, so each load
+    // takes a scalar base and one 32-bit offset register
+    uint32_t xi[3], yj[3], zk[3], cx[4], cy[4], cz[4];
     __device__ GlobalAcc(const GridK& g_, const AdjArgs& a_) : g(g_), a(a_) {}
     __device__ void at(const int i0[3])
     {
+        const uint32_t rx = 8u * (uint32_t)g.n[0], rxy = rx * (uint32_t)g.n[1];
         for (int o = 0; o < 3; ++o) {
-            xi[o] = wrapi(i0[0] + o - 1, g.n[0]);
-            yj[o] = wrapi(i0[1] + o - 1, g.n[1]) * g.n[0];
-            zk[o] = D == 3 ? (int64_t)wrapi(i0[2] + o - 1, g.n[2]) * g.n[0] * g.n[1] : 0;
+            xi[o] = 8u * (uint32_t)wrapi(i0[0] + o - 1, g.n[0]);
+            yj[o] = (uint32_t)wrapi(i0[1] + o - 1, g.n[1]) * rx;
+            zk[o] = D == 3 ? (uint32_t)wrapi(i0[2] + o - 1, g.n[2]) * rxy : 0u;
         }
     }
     __device__ void window(const int i0[3], const int delta[3])
@@ -401,25 +408,33 @@ struct GlobalAcc {
         const int sx = i0[0] + (delta[0] < 0 ? -1 : 0) - 1;
         const int sy = i0[1] + (delta[1] < 0 ? -1 : 0) - 1;
         const int sz = i0[2] + (delta[2] < 0 ? -1 : 0) - 1;
+        const uint32_t rx = 8u * (uint32_t)g.n[0], rxy = rx * (uint32_t)g.n[1];
         for (int o = 0; o < 4; ++o) {
-            cx[o] = wrapi(sx + o, g.n[0]);
-            cy[o] = wrapi(sy + o, g.n[1]) * g.n[0];
-            cz[o] = D == 3 ? (int64_t)wrapi(sz + o, g.n[2]) * g.n[0] * g.n[1] : 0;
+            cx[o] = 8u * (uint32_t)wrapi(sx + o, g.n[0]);
+            cy[o] = (uint32_t)wrapi(sy + o, g.n[1]) * rx;
+            cz[o] = D == 3 ? (uint32_t)wrapi(sz + o, g.n[2]) * rxy : 0u;
         }
+    }
+    static __device__ __forceinline__ const double& at_byte(const double* plane, uint32_t off)
+    {
+        return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(plane) + off);
+    }
+    __device__ const double* fplane(int comp) const
+    {
+        return comp < 3 ? a.E + comp * g.ncell : a.Bn + (comp - 3) * g.ncell;
     }
     __device__ double F(int comp, int da, int db, int dc) const
     {
-        const int64_t cell = zk[dc + 1] + yj[db + 1] + xi[da + 1];
-        return comp < 3 ? a.E[comp * g.ncell + cell] : a.Bn[(comp - 3) * g.ncell + cell];
+        return at_byte(fplane(comp), zk[dc + 1] + yj[db + 1] + xi[da + 1]);
     }
     __device__ double L(int comp, int ix, int iy, int iz) const
     {
-        return a.lamJ[comp * g.ncell + cz[iz] + cy[iy] + cx[ix]];
+        return at_byte(a.lamJ + comp * g.ncell, cz[iz] + cy[iy] + cx[ix]);
     }
     __device__ void add(int comp, int da, int db, int dc, double v) const
     {
-        const int64_t cell = zk[dc + 1] + yj[db + 1] + xi[da + 1];
-        grid_add(comp < 3 ? &a.lamE[comp * g.ncell + cell] : &a.lamB[(comp - 3) * g.ncell + cell], v);
+        double* plane = comp < 3 ? a.lamE + comp * g.ncell : a.lamB + (comp - 3) * g.ncell;
+        grid_add(const_cast<double*>(&at_byte(plane, zk[dc + 1] + yj[db + 1] + xi[da + 1])), v);
     }
 };
 
@@ -559,6 +574,163 @@ __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, A
     for (int k = 0; k < 3; ++k) a.lam_w[k * a.count + li] = lw0[k];
 }
 
+// Derivative in d of the form factor of one axis (Eqs. alphax, betax):
+// node factors 1 - d, d; cell factors (1 - d)^2 / 2, 3/4 - (1/2 - d)^2, d^2 / 2.
+__device__ __forceinline__ Axis<double> form_factor_d(double d)
+{
+    Axis<double> a;
+    a.f[0] = -1.0;
+    a.f[1] = 1.0;
+    a.s[0] = d - 1.0;
+    a.s[1] = 1.0 - 2.0 * d;
+    a.s[2] = d;
+    return a;
+}
+
+// Reverse of one gathered component, lam being the adjoint of its value at
+// the particle: lam times the form factor goes into the component's adjoint
+// at each stencil point (acc.add), and lam times the derivatives of the
+// gathered value in the three offsets into ld0.  The derivatives are
+// separable partial sums over the stencil (innermost z, then y, then x) with
+// one axis's factor replaced by its derivative.
+template <int comp, class Acc>
+__device__ __forceinline__ void gather_comp_reverse(Acc& acc, const Axis<double> (&w)[3], const Axis<double> (&dw)[3],
+                                                    double lam, double (&ld0)[3])
+{
+    constexpr bool NX = comp == 0 || comp == 4 || comp == 5;
+    constexpr bool NY = comp == 1 || comp == 3 || comp == 5;
+    constexpr bool NZ = comp == 2 || comp == 3 || comp == 4;
+    double tx = 0.0, ty = 0.0, tz = 0.0;
+#pragma unroll
+    for (int a = NX ? 0 : -1; a <= 1; ++a) {
+        const double wx = NX ? w[0].f[a] : w[0].s[a + 1];
+        double sa = 0.0, say = 0.0, saz = 0.0;
+#pragma unroll
+        for (int b = NY ? 0 : -1; b <= 1; ++b) {
+            const double wy = NY ? w[1].f[b] : w[1].s[b + 1];
+            const double lxy = lam * wx * wy;
+            double sb = 0.0, sbz = 0.0;
+#pragma unroll
+            for (int c = NZ ? 0 : -1; c <= 1; ++c) {
+                const double wz = NZ ? w[2].f[c] : w[2].s[c + 1];
+                const double f = acc.F(comp, a, b, c);
+                sb += wz * f;
+                sbz += (NZ ? dw[2].f[c] : dw[2].s[c + 1]) * f;
+                acc.add(comp, a, b, c, lxy * wz);
+            }
+            sa += wy * sb;
+            say += (NY ? dw[1].f[b] : dw[1].s[b + 1]) * sb;
+            saz += wy * sbz;
+        }
+        tx += (NX ? dw[0].f[a] : dw[0].s[a + 1]) * sa;
+        ty += wx * say;
+        tz += wx * saz;
+    }
+    ld0[0] += lam * tx;
+    ld0[1] += lam * ty;
+    ld0[2] += lam * tz;
+}
+
+// The 3D particle's part of the reverse step, arranged to keep few values
+// live: a gather of values only feeds the push and the move; the reverse
+// current and the reverse push run on that state; a second pass over the
+// stencil then adds the form factor times lambda_Ep, lambda_Bp into lambda_E,
+// lambda_B and the gathered values' derivatives in the start offsets into
+// lambda_x.  Same result as adj_particle<3> up to rounding order.
+template <class Acc>
+__device__ __forceinline__ void adj_particle3(const GridK& g, const AdjArgs& a, Acc& acc, const int i0[3],
+                                              const double d0[3], const double w0[3], double qp, int64_t li,
+                                              double lbp[3])
+{
+    const double c = g.c, c2 = c * c;
+    acc.at(i0);
+    double Ep[3], Bp[3];
+    {
+        Axis<double> w[3];
+        for (int ax = 0; ax < 3; ++ax) w[ax] = form_factor<double>(d0[ax]);
+        auto F = [&](int comp, int da, int db, int dc) -> double { return acc.F(comp, da, db, dc); };
+        gather3<double>(w, F, Ep, Bp);
+    }
+    for (int k = 0; k < 3; ++k) Bp[k] += g.bext[k];
+
+    // forward push and position advance, values only
+    const double qmdt2 = 0.5 * a.qm * g.dt;
+    double w1[3] = {w0[0], w0[1], w0[2]};
+    push<double>(qmdt2, c2, Ep, Bp, w1);
+    const double inv = 1.0 / ::sqrt(w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2] + c2);
+    double disp[3];
+    for (int ax = 0; ax < 3; ++ax) disp[ax] = w1[ax] * inv * g.cfl[ax];
+    double d1[3] = {0.0, 0.0, 0.0};
+    int delta[3] = {0, 0, 0};
+    StepArgs none{};
+    PosIO<double, 3>::move(none, 0, g, i0, d0, disp, d1, delta, false);
+    __builtin_amdgcn_sched_barrier(0);
+
+    // reverse of the current over the particle's window
+    double ld0[3], ld1[3];
+    {
+        double dm[3][4], dp[3][4], ldm[3][4], ldp[3][4];
+        for (int ax = 0; ax < 3; ++ax) {
+            double s0[3], s1[3];
+            cell_weights<double>(d0[ax], s0);
+            cell_weights<double>(d1[ax], s1);
+            window<double>(s0, s1, delta[ax], dm[ax], dp[ax]);
+            for (int t = 0; t < 4; ++t) ldm[ax][t] = ldp[ax][t] = 0.0;
+        }
+        double jfac[3];
+        for (int k = 0; k < 3; ++k) jfac[k] = g.jscale[k] * qp;
+        acc.window(i0, delta);
+        double ljz = 0.0;
+        auto L = [&](int comp, int ix, int iy, int iz) -> double { return acc.L(comp, ix, iy, iz); };
+        deposit_reverse<3>(dm, dp, jfac, 0.0, L, ldm, ldp, ljz);
+        for (int ax = 0; ax < 3; ++ax) {
+            const int o0 = delta[ax] < 0 ? 1 : 0, o1 = delta[ax] > 0 ? 1 : 0;
+            double ls0[3], ls1[3];
+            for (int k = 0; k < 3; ++k) {
+                ls0[k] = ldp[ax][k + o0] - ldm[ax][k + o0];
+                ls1[k] = ldp[ax][k + o1] + ldm[ax][k + o1];
+            }
+            // x^{n+1} = x^n + V(w^{n+1/2}): d1 = d0 + disp - delta
+            ld1[ax] = a.lam_x[ax * a.count + li] + cell_weights_reverse(d1[ax], ls1);
+            ld0[ax] = cell_weights_reverse(d0[ax], ls0) + ld1[ax];
+        }
+    }
+    const double inv3 = inv * inv * inv;
+    double lw1[3];
+    for (int k = 0; k < 3; ++k) {
+        lw1[k] = a.lam_w[k * a.count + li];
+        for (int ax = 0; ax < 3; ++ax)
+            lw1[k] += ld1[ax] * g.cfl[ax] * ((ax == k ? inv : 0.0) - w1[ax] * w1[k] * inv3);
+    }
+
+    // push
+    double lw0[3], lE[3], lB[3];
+    push_reverse(qmdt2, c2, Ep, Bp, w0, lw1, lw0, lE, lB);
+    for (int k = 0; k < 3; ++k) lbp[k] += lB[k];
+    __builtin_amdgcn_sched_barrier(0);
+
+    // gather, reversed
+    Axis<double> w[3], dw[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        w[ax] = form_factor<double>(d0[ax]);
+        dw[ax] = form_factor_d(d0[ax]);
+    }
+    gather_comp_reverse<0>(acc, w, dw, lE[0], ld0);
+    __builtin_amdgcn_sched_barrier(0);
+    gather_comp_reverse<1>(acc, w, dw, lE[1], ld0);
+    __builtin_amdgcn_sched_barrier(0);
+    gather_comp_reverse<2>(acc, w, dw, lE[2], ld0);
+    __builtin_amdgcn_sched_barrier(0);
+    gather_comp_reverse<3>(acc, w, dw, lB[0], ld0);
+    __builtin_amdgcn_sched_barrier(0);
+    gather_comp_reverse<4>(acc, w, dw, lB[1], ld0);
+    __builtin_amdgcn_sched_barrier(0);
+    gather_comp_reverse<5>(acc, w, dw, lB[2], ld0);
+
+    for (int ax = 0; ax < 3; ++ax) a.lam_x[ax * a.count + li] = ld0[ax];
+    for (int k = 0; k < 3; ++k) a.lam_w[k * a.count + li] = lw0[k];
+}
+
 template <int D>
 __device__ __forceinline__ void load_particle(const AdjArgs& a, int64_t p, int i0[3], double d0[3],
                                               double w0[3], double& qp, int64_t& li)
@@ -603,7 +775,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_particles(GridK g, AdjArgs 
         int64_t li;
         load_particle<D>(a, p, i0, d0, w0, qp, li);
         GlobalAcc<D> acc(g, a);
-        adj_particle<D>(g, a, acc, i0, d0, w0, qp, li, lbp);
+        if constexpr (D == 3) adj_particle3(g, a, acc, i0, d0, w0, qp, li, lbp);
+        else adj_particle<D>(g, a, acc, i0, d0, w0, qp, li, lbp);
     }
     flush_bext(sb, lbp, a.lam_bext);
 }
@@ -721,12 +894,14 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
 // accumulated over the field region (cells T0-1-M .. T0+T+M, M = 2: 132 KB)
 // in LDS and added to the grid once at the end, which removes the global
 // atomics that dominated the one-thread-per-particle kernel.  A particle more
-// than M cells outside its tile adds in global memory.
+// than M cells outside its tile adds in global memory.  The particle work
+// (adj_particle3) fits 256 registers, so the 512 threads run as two waves per
+// SIMD, which hides the latency of the field and lambda_J loads.
 constexpr int kAdjT3 = kTile3;
 constexpr int kAdjM3 = 2;
 constexpr int kAdjLF3 = kAdjT3 + 2 + 2 * kAdjM3;
 constexpr int kAdjNF3 = kAdjLF3 * kAdjLF3 * kAdjLF3;
-constexpr int kAdjThreads3 = 256;
+constexpr int kAdjThreads3 = 512;
 
 struct TileAcc3 : GlobalAcc<3> {
     double* sacc;  // 6 x kAdjNF3
@@ -771,10 +946,10 @@ __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, 
         }
         if (inside) {
             TileAcc3 acc(g, a, sacc, (rel[0] + 1 + M) + (rel[1] + 1 + M) * LF + (rel[2] + 1 + M) * LF * LF);
-            adj_particle<3>(g, a, acc, i0, d0, w0, qp, li, lbp);
+            adj_particle3(g, a, acc, i0, d0, w0, qp, li, lbp);
         } else {
             GlobalAcc<3> acc(g, a);
-            adj_particle<3>(g, a, acc, i0, d0, w0, qp, li, lbp);
+            adj_particle3(g, a, acc, i0, d0, w0, qp, li, lbp);
         }
     }
     __syncthreads();

@@ -489,6 +489,8 @@ static int adjoint_ready(Ctx& c)
     if (c.k.field_form != 0) return fail(&c, PIC_EINVAL, "the adjoint covers the B form only");
     if (c.g.order != 1 || c.g.interp != 0)
         return fail(&c, PIC_EINVAL, "the adjoint covers the alternating order 1 1/2 only");
+    if (c.k.ncell * (int64_t)sizeof(double) >= ((int64_t)1 << 32))
+        return fail(&c, PIC_EINVAL, "the adjoint needs one field plane below 4 GiB (fewer than 2^29 cells)");
     return PIC_OK;
 }
 
