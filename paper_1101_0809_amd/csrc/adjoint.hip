@@ -244,6 +244,7 @@ struct AdjArgs {
     double* lam_x;       // 3 x count, by particle id (by_id) or storage position
     double* lam_w;       // 3 x count, likewise
     double* lam_bext;    // 3, accumulated
+    double* scr[6];      // per storage position, n each: lambda_Ep, lambda_Bp (3D tile kernel)
     int by_id;
 };
 
@@ -295,82 +296,98 @@ __device__ __forceinline__ void push_reverse(double qmdt2, double c2, const doub
     }
 }
 
-// Reverse of the quarter-form current (Eq. current as in deposit3 and
-// deposit2): L(comp, ix, iy, iz) returns lambda_J at a window position; the
-// derivatives of sum lambda_J J with respect to the window differences dm and
-// sums dp are added into ldm, ldp (and, in 2D, with respect to the J^z factor
-// into ljz).
+// 2D reverse of the quarter-form current (Eq. current as in deposit2):
+// L(comp, ix, iy, 0) returns lambda_J at a window position; the derivatives
+// of sum lambda_J J with respect to the window differences dm and sums dp are
+// added into ldm, ldp, and with respect to the J^z factor into ljz.
 template <int D, class LJ>
 __device__ __forceinline__ void deposit_reverse(const double (&dm)[3][4], const double (&dp)[3][4],
                                                 const double jfac[3], double jz, LJ L,
                                                 double (&ldm)[3][4], double (&ldp)[3][4], double& ljz)
 {
+    static_assert(D == 2, "the 3D reverse current is deposit_reverse3");
     const double third = 1.0 / 3.0;
-    if (D == 3) {
+    for (int comp = 0; comp < 2; ++comp) {
+        const int u = 1 - comp;
+        const double K = 2.0 * jfac[comp];
+        const double P[3] = {dm[comp][0], dm[comp][0] + dm[comp][1], -dm[comp][3]};
+        double lP[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) {
+            double lb = 0.0;
+            for (int t = 0; t < 3; ++t) {
+                int ij[2];
+                ij[comp] = t + 1;
+                ij[u] = b;
+                const double l = L(comp, ij[0], ij[1], 0);
+                lP[t] += l * dp[u][b];
+                lb += l * P[t];
+            }
+            ldp[u][b] += K * lb;
+        }
+        ldm[comp][0] += K * (lP[0] + lP[1]);
+        ldm[comp][1] += K * lP[1];
+        ldm[comp][3] -= K * lP[2];
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            const double l = L(2, a, b, 0);
+            ljz += l * (dp[0][a] * dp[1][b] + third * dm[0][a] * dm[1][b]);
+            const double lj = jz * l;
+            ldp[0][a] += lj * dp[1][b];
+            ldp[1][b] += lj * dp[0][a];
+            ldm[0][a] += third * lj * dm[1][b];
+            ldm[1][b] += third * lj * dm[0][a];
+        }
+}
+
+// 3D reverse of the quarter-form current (Eq. current as in deposit3).  J of
+// component comp at window position (t+1 along comp, b, c across) is jfac P_t
+// (dp_u[b] dp_v[c] + dm_u[b] dm_v[c] / 3); L(comp, ix, iy, iz) returns lambda_J
+// there.  The derivatives of sum lambda_J J with respect to the window sums
+// are added into ldp, and three times those with respect to the differences
+// into ldm3: with jfac folded into P and the transverse product taken three
+// times over, the inner loop has no 1/3 and no jfac product.
+template <class LJ>
+__device__ __forceinline__ void deposit_reverse3(const double (&dm)[3][4], const double (&dp)[3][4],
+                                                 const double jfac[3], LJ L, double (&ldm3)[3][4],
+                                                 double (&ldp)[3][4])
+{
 #pragma unroll
-        for (int comp = 0; comp < 3; ++comp) {
-            const int u = (comp + 1) % 3, v = (comp + 2) % 3;
-            const double P[3] = {dm[comp][0], dm[comp][0] + dm[comp][1], -dm[comp][3]};
-            double lP[3] = {0.0, 0.0, 0.0};
-            for (int b = 0; b < 4; ++b)
-                for (int c = 0; c < 4; ++c) {
-                    const double tr = dp[u][b] * dp[v][c] + third * dm[u][b] * dm[v][c];
-                    double ltr = 0.0;
-                    for (int t = 0; t < 3; ++t) {
-                        int ijk[3];
-                        ijk[comp] = t + 1;
-                        ijk[u] = b;
-                        ijk[v] = c;
-                        const double l = L(comp, ijk[0], ijk[1], ijk[2]);
-                        lP[t] += l * tr;
-                        ltr += l * P[t];
-                    }
-                    ltr *= jfac[comp];
-                    ldp[u][b] += ltr * dp[v][c];
-                    ldp[v][c] += ltr * dp[u][b];
-                    ldm[u][b] += third * ltr * dm[v][c];
-                    ldm[v][c] += third * ltr * dm[u][b];
-                    // three lambda_J loads in flight per window column: the reverse
-                    // step runs two waves per SIMD in 256 registers
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            ldm[comp][0] += jfac[comp] * (lP[0] + lP[1]);
-            ldm[comp][1] += jfac[comp] * lP[1];
-            ldm[comp][3] -= jfac[comp] * lP[2];
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
-        for (int comp = 0; comp < 2; ++comp) {
-            const int u = 1 - comp;
-            const double K = 2.0 * jfac[comp];
-            const double P[3] = {dm[comp][0], dm[comp][0] + dm[comp][1], -dm[comp][3]};
-            double lP[3] = {0.0, 0.0, 0.0};
-            for (int b = 0; b < 4; ++b) {
-                double lb = 0.0;
+    for (int comp = 0; comp < 3; ++comp) {
+        const int u = (comp + 1) % 3, v = (comp + 2) % 3;
+        const double P[3] = {jfac[comp] * dm[comp][0], jfac[comp] * (dm[comp][0] + dm[comp][1]),
+                             -jfac[comp] * dm[comp][3]};
+        double lP3[3] = {0.0, 0.0, 0.0};  // sum over b, c of lambda_J times 3 x the transverse product
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const double dp3 = 3.0 * dp[u][b];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double tr3 = dp3 * dp[v][c] + dm[u][b] * dm[v][c];
+                double ltr = 0.0;
+#pragma unroll
                 for (int t = 0; t < 3; ++t) {
-                    int ij[2];
-                    ij[comp] = t + 1;
-                    ij[u] = b;
-                    const double l = L(comp, ij[0], ij[1], 0);
-                    lP[t] += l * dp[u][b];
-                    lb += l * P[t];
+                    int ijk[3];
+                    ijk[comp] = t + 1;
+                    ijk[u] = b;
+                    ijk[v] = c;
+                    const double l = L(comp, ijk[0], ijk[1], ijk[2]);
+                    lP3[t] += l * tr3;
+                    ltr += l * P[t];
                 }
-                ldp[u][b] += K * lb;
+                ldp[u][b] += ltr * dp[v][c];
+                ldp[v][c] += ltr * dp[u][b];
+                ldm3[u][b] += ltr * dm[v][c];
+                ldm3[v][c] += ltr * dm[u][b];
+                // three lambda_J reads in flight per window column: the
+                // reverse step runs two waves per SIMD in 256 registers
+                __builtin_amdgcn_sched_barrier(0);
             }
-            ldm[comp][0] += K * (lP[0] + lP[1]);
-            ldm[comp][1] += K * lP[1];
-            ldm[comp][3] -= K * lP[2];
         }
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) {
-                const double l = L(2, a, b, 0);
-                ljz += l * (dp[0][a] * dp[1][b] + third * dm[0][a] * dm[1][b]);
-                const double lj = jz * l;
-                ldp[0][a] += lj * dp[1][b];
-                ldp[1][b] += lj * dp[0][a];
-                ldm[0][a] += third * lj * dm[1][b];
-                ldm[1][b] += third * lj * dm[0][a];
-            }
+        ldm3[comp][0] += jfac[comp] * (lP3[0] + lP3[1]);
+        ldm3[comp][1] += jfac[comp] * lP3[1];
+        ldm3[comp][3] -= jfac[comp] * lP3[2];
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -461,15 +478,17 @@ __device__ __forceinline__ void scatter_comp(Acc& acc, const Axis<double> (&w)[3
     }
 }
 
-// The particle's part of the reverse step: recompute its gather, push and
+// The 2D particle's part of the reverse step: recompute its gather, push and
 // move, take lambda_J over its current window back to its start and end
 // offsets and new momentum, then through the push to its old momentum and the
-// fields it gathered; add those into lambda_E, lambda_B (acc) and lbp.
+// fields it gathered; add those into lambda_E, lambda_B (acc) and lbp.  The
+// gather's derivatives in the start offsets come from dual numbers.
 template <int D, class Acc>
 __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, Acc& acc, const int i0[3],
                                              const double d0[3], const double w0[3], double qp, int64_t li,
                                              double lbp[3])
 {
+    static_assert(D == 2, "the 3D particle's reverse step is adj_particle3");
     const double c = g.c, c2 = c * c;
     acc.at(i0);
     // gather, with the derivatives in the start offsets d0
@@ -479,8 +498,7 @@ __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, A
     if (D == 2) ax0[2] = form_factor<DG>(DG(0.0));
     auto F = [&](int comp, int da, int db, int dc) -> double { return acc.F(comp, da, db, dc); };
     DG Eg[3], Bg[3];
-    if (D == 3) gather3<DG>(ax0, F, Eg, Bg);
-    else gather2<DG>(ax0, F, Eg, Bg);
+    gather2<DG>(ax0, F, Eg, Bg);
     double Ep[3], Bp[3];
     for (int k = 0; k < 3; ++k) {
         Ep[k] = Eg[k].v;
@@ -589,11 +607,11 @@ __device__ __forceinline__ Axis<double> form_factor_d(double d)
 
 // Reverse of one gathered component, lam being the adjoint of its value at
 // the particle: lam times the form factor goes into the component's adjoint
-// at each stencil point (acc.add), and lam times the derivatives of the
+// at each stencil point (acc.add, when SCATTER), and lam times the derivatives of the
 // gathered value in the three offsets into ld0.  The derivatives are
 // separable partial sums over the stencil (innermost z, then y, then x) with
 // one axis's factor replaced by its derivative.
-template <int comp, class Acc>
+template <int comp, bool SCATTER, class Acc>
 __device__ __forceinline__ void gather_comp_reverse(Acc& acc, const Axis<double> (&w)[3], const Axis<double> (&dw)[3],
                                                     double lam, double (&ld0)[3])
 {
@@ -608,7 +626,7 @@ __device__ __forceinline__ void gather_comp_reverse(Acc& acc, const Axis<double>
 #pragma unroll
         for (int b = NY ? 0 : -1; b <= 1; ++b) {
             const double wy = NY ? w[1].f[b] : w[1].s[b + 1];
-            const double lxy = lam * wx * wy;
+            const double lxy = SCATTER ? lam * wx * wy : 0.0;
             double sb = 0.0, sbz = 0.0;
 #pragma unroll
             for (int c = NZ ? 0 : -1; c <= 1; ++c) {
@@ -616,7 +634,7 @@ __device__ __forceinline__ void gather_comp_reverse(Acc& acc, const Axis<double>
                 const double f = acc.F(comp, a, b, c);
                 sb += wz * f;
                 sbz += (NZ ? dw[2].f[c] : dw[2].s[c + 1]) * f;
-                acc.add(comp, a, b, c, lxy * wz);
+                if constexpr (SCATTER) acc.add(comp, a, b, c, lxy * wz);
             }
             sa += wy * sb;
             say += (NY ? dw[1].f[b] : dw[1].s[b + 1]) * sb;
@@ -636,11 +654,14 @@ __device__ __forceinline__ void gather_comp_reverse(Acc& acc, const Axis<double>
 // current and the reverse push run on that state; a second pass over the
 // stencil then adds the form factor times lambda_Ep, lambda_Bp into lambda_E,
 // lambda_B and the gathered values' derivatives in the start offsets into
-// lambda_x.  Same result as adj_particle<3> up to rounding order.
-template <class Acc>
+// lambda_x.  Without SCATTER the second pass only takes the derivatives and
+// lambda_Ep, lambda_Bp are returned in lEB for a later scatter.  The
+// derivatives of the gathered values are separable partial sums over the
+// stencil (gather_comp_reverse), not dual numbers.
+template <bool SCATTER, class Acc>
 __device__ __forceinline__ void adj_particle3(const GridK& g, const AdjArgs& a, Acc& acc, const int i0[3],
                                               const double d0[3], const double w0[3], double qp, int64_t li,
-                                              double lbp[3])
+                                              double lbp[3], double lEB[6])
 {
     const double c = g.c, c2 = c * c;
     acc.at(i0);
@@ -670,6 +691,7 @@ __device__ __forceinline__ void adj_particle3(const GridK& g, const AdjArgs& a, 
     double ld0[3], ld1[3];
     {
         double dm[3][4], dp[3][4], ldm[3][4], ldp[3][4];
+#pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             double s0[3], s1[3];
             cell_weights<double>(d0[ax], s0);
@@ -679,16 +701,20 @@ __device__ __forceinline__ void adj_particle3(const GridK& g, const AdjArgs& a, 
         }
         double jfac[3];
         for (int k = 0; k < 3; ++k) jfac[k] = g.jscale[k] * qp;
+        const double third = 1.0 / 3.0;
         acc.window(i0, delta);
-        double ljz = 0.0;
         auto L = [&](int comp, int ix, int iy, int iz) -> double { return acc.L(comp, ix, iy, iz); };
-        deposit_reverse<3>(dm, dp, jfac, 0.0, L, ldm, ldp, ljz);
+        deposit_reverse3(dm, dp, jfac, L, ldm, ldp);  // ldm holds 3 x the difference adjoints
+#pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            const int o0 = delta[ax] < 0 ? 1 : 0, o1 = delta[ax] > 0 ? 1 : 0;
+            // start weights sit one window cell right when delta < 0, end
+            // weights when delta > 0 (two-way selects, no indexed access)
+            const bool o0 = delta[ax] < 0, o1 = delta[ax] > 0;
             double ls0[3], ls1[3];
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
-                ls0[k] = ldp[ax][k + o0] - ldm[ax][k + o0];
-                ls1[k] = ldp[ax][k + o1] + ldm[ax][k + o1];
+                ls0[k] = o0 ? ldp[ax][k + 1] - third * ldm[ax][k + 1] : ldp[ax][k] - third * ldm[ax][k];
+                ls1[k] = o1 ? ldp[ax][k + 1] + third * ldm[ax][k + 1] : ldp[ax][k] + third * ldm[ax][k];
             }
             // x^{n+1} = x^n + V(w^{n+1/2}): d1 = d0 + disp - delta
             ld1[ax] = a.lam_x[ax * a.count + li] + cell_weights_reverse(d1[ax], ls1);
@@ -715,17 +741,21 @@ __device__ __forceinline__ void adj_particle3(const GridK& g, const AdjArgs& a, 
         w[ax] = form_factor<double>(d0[ax]);
         dw[ax] = form_factor_d(d0[ax]);
     }
-    gather_comp_reverse<0>(acc, w, dw, lE[0], ld0);
+    gather_comp_reverse<0, SCATTER>(acc, w, dw, lE[0], ld0);
     __builtin_amdgcn_sched_barrier(0);
-    gather_comp_reverse<1>(acc, w, dw, lE[1], ld0);
+    gather_comp_reverse<1, SCATTER>(acc, w, dw, lE[1], ld0);
     __builtin_amdgcn_sched_barrier(0);
-    gather_comp_reverse<2>(acc, w, dw, lE[2], ld0);
+    gather_comp_reverse<2, SCATTER>(acc, w, dw, lE[2], ld0);
     __builtin_amdgcn_sched_barrier(0);
-    gather_comp_reverse<3>(acc, w, dw, lB[0], ld0);
+    gather_comp_reverse<3, SCATTER>(acc, w, dw, lB[0], ld0);
     __builtin_amdgcn_sched_barrier(0);
-    gather_comp_reverse<4>(acc, w, dw, lB[1], ld0);
+    gather_comp_reverse<4, SCATTER>(acc, w, dw, lB[1], ld0);
     __builtin_amdgcn_sched_barrier(0);
-    gather_comp_reverse<5>(acc, w, dw, lB[2], ld0);
+    gather_comp_reverse<5, SCATTER>(acc, w, dw, lB[2], ld0);
+    for (int k = 0; k < 3; ++k) {
+        lEB[k] = lE[k];
+        lEB[3 + k] = lB[k];
+    }
 
     for (int ax = 0; ax < 3; ++ax) a.lam_x[ax * a.count + li] = ld0[ax];
     for (int k = 0; k < 3; ++k) a.lam_w[k * a.count + li] = lw0[k];
@@ -775,7 +805,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_particles(GridK g, AdjArgs 
         int64_t li;
         load_particle<D>(a, p, i0, d0, w0, qp, li);
         GlobalAcc<D> acc(g, a);
-        if constexpr (D == 3) adj_particle3(g, a, acc, i0, d0, w0, qp, li, lbp);
+        double lEB[6];
+        if constexpr (D == 3) adj_particle3<true>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
         else adj_particle<D>(g, a, acc, i0, d0, w0, qp, li, lbp);
     }
     flush_bext(sb, lbp, a.lam_bext);
@@ -889,72 +920,156 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
     flush_bext(sb, lbp, a.lam_bext);
 }
 
-// 3D tile kernel.  The fields, B^n and lambda_J are read from global memory
-// (the tile's neighbourhood stays in L2); lambda_E and lambda_B are
-// accumulated over the field region (cells T0-1-M .. T0+T+M, M = 2: 132 KB)
-// in LDS and added to the grid once at the end, which removes the global
-// atomics that dominated the one-thread-per-particle kernel.  A particle more
-// than M cells outside its tile adds in global memory.  The particle work
-// (adj_particle3) fits 256 registers, so the 512 threads run as two waves per
-// SIMD, which hides the latency of the field and lambda_J loads.
+// 3D tile kernel, in two phases over the tile's particles that share one LDS
+// area.  Phase 1 stages E, B^n over the field region (cells T0-1-M .. T0+T+M,
+// 83 KB) and lambda_J over the particles' windows (T0-2-M .. T0+T+1+M, 66 KB)
+// and runs each particle's reverse step from LDS, except the scatter:
+// lambda_Ep, lambda_Bp go to a scratch row per particle.  Phase 2 reuses the
+// area for lambda_E, lambda_B over the field region, scatters every
+// particle's lambda_Ep, lambda_Bp into it with LDS atomics, and adds it to
+// the grid once.  A particle more than M = 1 cell outside its tile runs
+// entirely in phase 1 from global memory, with global atomics.  The particle
+// work fits 256 registers, so the 512 threads run as two waves per SIMD.
 constexpr int kAdjT3 = kTile3;
-constexpr int kAdjM3 = 2;
+constexpr int kAdjM3 = 1;
 constexpr int kAdjLF3 = kAdjT3 + 2 + 2 * kAdjM3;
+constexpr int kAdjLJ3 = kAdjT3 + 4 + 2 * kAdjM3;
 constexpr int kAdjNF3 = kAdjLF3 * kAdjLF3 * kAdjLF3;
+constexpr int kAdjNJ3 = kAdjLJ3 * kAdjLJ3 * kAdjLJ3;
 constexpr int kAdjThreads3 = 512;
+static_assert((6 * kAdjNF3 + 3 * kAdjNJ3 + 3) * 8 <= 160 * 1024, "3D reverse-step LDS over 160 KB");
 
-struct TileAcc3 : GlobalAcc<3> {
+// Phase-1 reads: fields and lambda_J in LDS (the particle within M of its tile).
+struct TileRead3 {
+    const double* sf;  // 6 x kAdjNF3
+    const double* sj;  // 3 x kAdjNJ3
+    int rel[3];        // particle cell relative to the tile origin
+    int fo;            // particle cell in the field region
+    int jo;            // window start in the lambda_J region
+    __device__ TileRead3(const double* f, const double* j, const int r[3]) : sf(f), sj(j)
+    {
+        for (int ax = 0; ax < 3; ++ax) rel[ax] = r[ax];
+        fo = (r[0] + 1 + kAdjM3) + (r[1] + 1 + kAdjM3) * kAdjLF3 + (r[2] + 1 + kAdjM3) * kAdjLF3 * kAdjLF3;
+    }
+    __device__ void at(const int[3]) {}
+    __device__ double F(int comp, int da, int db, int dc) const
+    {
+        return sf[comp * kAdjNF3 + fo + da + db * kAdjLF3 + dc * kAdjLF3 * kAdjLF3];
+    }
+    __device__ void window(const int[3], const int delta[3])
+    {
+        int o[3];
+        for (int ax = 0; ax < 3; ++ax) o[ax] = rel[ax] + 1 + kAdjM3 + (delta[ax] < 0 ? -1 : 0);
+        jo = o[0] + o[1] * kAdjLJ3 + o[2] * kAdjLJ3 * kAdjLJ3;
+    }
+    __device__ double L(int comp, int ix, int iy, int iz) const
+    {
+        return sj[comp * kAdjNJ3 + jo + ix + iy * kAdjLJ3 + iz * kAdjLJ3 * kAdjLJ3];
+    }
+};
+
+// Phase-2 adds: lambda_E, lambda_B accumulated in LDS.
+struct TileAdd3 {
     double* sacc;  // 6 x kAdjNF3
-    int fo;        // particle cell in the field region
-    __device__ TileAcc3(const GridK& g_, const AdjArgs& a_, double* s, int f) : GlobalAcc<3>(g_, a_), sacc(s), fo(f) {}
+    int fo;
     __device__ void add(int comp, int da, int db, int dc, double v) const
     {
         atomicAdd(&sacc[comp * kAdjNF3 + fo + da + db * kAdjLF3 + dc * kAdjLF3 * kAdjLF3], v);
     }
 };
 
+// Cell and offsets of particle p and its cell relative to the tile origin;
+// true when within M cells of the tile (the LDS regions cover it).
+__device__ __forceinline__ bool tile_place3(const GridK& g, const AdjArgs& a, int64_t p, const int T0[3], int i0[3],
+                                            double d0[3], int rel[3])
+{
+    bool inside = true;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double x = a.pos[ax][p];
+        const double fl = floor(x);
+        i0[ax] = (int)fl;
+        d0[ax] = x - fl;
+        int r = i0[ax] - T0[ax];
+        const int n = g.n[ax];
+        if (r > n / 2) r -= n;
+        if (r < -(n / 2)) r += n;
+        rel[ax] = r;
+        inside = inside && r >= -kAdjM3 && r <= kAdjT3 - 1 + kAdjM3;
+    }
+    return inside;
+}
+
 __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, const int64_t* __restrict__ tile_start,
                                                             int split)
 {
-    constexpr int T = kAdjT3, M = kAdjM3, LF = kAdjLF3, NF = kAdjNF3, NT = kAdjThreads3;
-    __shared__ double sacc[6 * NF];
+    constexpr int T = kAdjT3, M = kAdjM3, LF = kAdjLF3, LJ = kAdjLJ3, NF = kAdjNF3, NJ = kAdjNJ3, NT = kAdjThreads3;
+    __shared__ double lds[6 * NF + 3 * NJ];
     __shared__ double sb[3];
+    double* const sf = lds;  // phase 1: E, B^n; phase 2: lambda_E, lambda_B
+    double* const sj = lds + 6 * NF;
     const int unit = xcd_tile(blockIdx.x, g.ntiles * split);
     const int tile = unit / split, part = unit - tile * split;
     const int T0[3] = {(tile % g.nt[0]) * T, ((tile / g.nt[0]) % g.nt[1]) * T, (tile / (g.nt[0] * g.nt[1])) * T};
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    for (int e = threadIdx.x; e < 6 * NF; e += NT) sacc[e] = 0.0;
+    for (int e = threadIdx.x; e < 6 * NF; e += NT) {
+        const int comp = e / NF, r = e - comp * NF;
+        const int gx = wrapi(T0[0] - 1 - M + r % LF, nx);
+        const int gy = wrapi(T0[1] - 1 - M + (r / LF) % LF, ny);
+        const int gz = wrapi(T0[2] - 1 - M + r / (LF * LF), nz);
+        const int64_t cell = ((int64_t)gz * ny + gy) * nx + gx;
+        sf[e] = comp < 3 ? a.E[comp * N + cell] : a.Bn[(comp - 3) * N + cell];
+    }
+    for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
+        const int comp = e / NJ, r = e - comp * NJ;
+        const int gx = wrapi(T0[0] - 2 - M + r % LJ, nx);
+        const int gy = wrapi(T0[1] - 2 - M + (r / LJ) % LJ, ny);
+        const int gz = wrapi(T0[2] - 2 - M + r / (LJ * LJ), nz);
+        sj[e] = a.lamJ[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
+    }
     if (threadIdx.x < 3) sb[threadIdx.x] = 0.0;
     __syncthreads();
+
+    // phase 1
     double lbp[3] = {0.0, 0.0, 0.0};
     const int64_t begin = tile_start[tile], end = tile_start[tile + 1];
     for (int64_t p = begin + part * NT + threadIdx.x; p < end; p += (int64_t)split * NT) {
-        int i0[3];
-        double d0[3], w0[3], qp;
+        int i0[3], rel[3];
+        double d0[3], w0[3], qp, lEB[6];
         int64_t li;
         load_particle<3>(a, p, i0, d0, w0, qp, li);
-        int rel[3];
-        bool inside = true;
-        for (int ax = 0; ax < 3; ++ax) {
-            int r = i0[ax] - T0[ax];
-            const int n = g.n[ax];
-            if (r > n / 2) r -= n;
-            if (r < -(n / 2)) r += n;
-            rel[ax] = r;
-            inside = inside && r >= -M && r <= T - 1 + M;
-        }
+        const bool inside = tile_place3(g, a, p, T0, i0, d0, rel);
         if (inside) {
-            TileAcc3 acc(g, a, sacc, (rel[0] + 1 + M) + (rel[1] + 1 + M) * LF + (rel[2] + 1 + M) * LF * LF);
-            adj_particle3(g, a, acc, i0, d0, w0, qp, li, lbp);
+            TileRead3 acc(sf, sj, rel);
+            adj_particle3<false>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
+            for (int k = 0; k < 6; ++k) a.scr[k][p] = lEB[k];
         } else {
             GlobalAcc<3> acc(g, a);
-            adj_particle3(g, a, acc, i0, d0, w0, qp, li, lbp);
+            adj_particle3<true>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
         }
     }
     __syncthreads();
+
+    // phase 2
+    for (int e = threadIdx.x; e < 6 * NF; e += NT) sf[e] = 0.0;
+    __syncthreads();
+    for (int64_t p = begin + part * NT + threadIdx.x; p < end; p += (int64_t)split * NT) {
+        int i0[3], rel[3];
+        double d0[3];
+        if (!tile_place3(g, a, p, T0, i0, d0, rel)) continue;
+        Axis<double> w[3];
+        for (int ax = 0; ax < 3; ++ax) w[ax] = form_factor<double>(d0[ax]);
+        const TileAdd3 acc{sf, (rel[0] + 1 + M) + (rel[1] + 1 + M) * LF + (rel[2] + 1 + M) * LF * LF};
+        scatter_comp<3, 0>(acc, w, a.scr[0][p]);
+        scatter_comp<3, 1>(acc, w, a.scr[1][p]);
+        scatter_comp<3, 2>(acc, w, a.scr[2][p]);
+        scatter_comp<3, 3>(acc, w, a.scr[3][p]);
+        scatter_comp<3, 4>(acc, w, a.scr[4][p]);
+        scatter_comp<3, 5>(acc, w, a.scr[5][p]);
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < 6 * NF; e += NT) {
-        const double v = sacc[e];
+        const double v = sf[e];
         if (v == 0.0) continue;
         const int comp = e / NF, r = e - comp * NF;
         const int gx = wrapi(T0[0] - 1 - M + r % LF, nx);
@@ -1186,6 +1301,11 @@ hipError_t launch_adjoint_step(const Ctx& c, const void* record, bool by_id, dou
         a.lam_w = lam_w[i];
         a.lam_bext = lam_bext;
         a.by_id = by_id ? 1 : 0;
+        // the spare particle copy is free between sorts: lambda_Ep, lambda_Bp rows
+        for (int k = 0; k < 3; ++k) {
+            a.scr[k] = static_cast<double*>(sp.alt.pos[k]);
+            a.scr[3 + k] = static_cast<double*>(sp.alt.mom[k]);
+        }
         const unsigned pb = (unsigned)((sp.n + kAdjThreads - 1) / kAdjThreads);
         if (c.k.dims == 3 && pv.tiles) {
             const int split = (int)std::min<int64_t>(8, std::max<int64_t>(1, (512 + c.k.ntiles - 1) / c.k.ntiles));
