@@ -245,6 +245,7 @@ struct AdjArgs {
     double* lam_w;       // 3 x count, likewise
     double* lam_bext;    // 3, accumulated
     double* scr[6];      // per storage position, n each: lambda_Ep, lambda_Bp (3D tile kernel)
+    int64_t* qslot;      // per storage position: 16 x class rank + class, or -1 (3D tile kernel)
     int by_id;
 };
 
@@ -930,6 +931,16 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
 // the grid once.  A particle more than M = 1 cell outside its tile runs
 // entirely in phase 1 from global memory, with global atomics.  The particle
 // work fits 256 registers, so the 512 threads run as two waves per SIMD.
+//
+// Phase 2 hands particles to lanes by class, the residue of the particle's
+// field-region cell modulo 16: phase 1 ranks each particle within its class
+// (LDS counters; rank and class kept in the spare copy's id row), a short
+// pass writes the 16-bit tile offsets into an LDS queue grouped by class,
+// and phase 2 takes slot s = 16 r + c as the r-th particle of class c.  The
+// 16 lanes of one LDS pass then hold 16 distinct classes, so the same
+// stencil offset lands in 16 distinct banks and the atomics do not conflict.
+// A block with more than kAdjQ3 particles in its tile, or a tile of more
+// than 65536, scatters in storage order instead.
 constexpr int kAdjT3 = kTile3;
 constexpr int kAdjM3 = 1;
 constexpr int kAdjLF3 = kAdjT3 + 2 + 2 * kAdjM3;
@@ -937,7 +948,10 @@ constexpr int kAdjLJ3 = kAdjT3 + 4 + 2 * kAdjM3;
 constexpr int kAdjNF3 = kAdjLF3 * kAdjLF3 * kAdjLF3;
 constexpr int kAdjNJ3 = kAdjLJ3 * kAdjLJ3 * kAdjLJ3;
 constexpr int kAdjThreads3 = 512;
-static_assert((6 * kAdjNF3 + 3 * kAdjNJ3 + 3) * 8 <= 160 * 1024, "3D reverse-step LDS over 160 KB");
+constexpr int kAdjC3 = 16;      // lane classes: 16 lanes of 8-byte values per LDS pass
+constexpr int kAdjQ3 = 7168;    // class-queue entries (16-bit tile offsets)
+static_assert((6 * kAdjNF3 + 3 * kAdjNJ3 + 3) * 8 + 2 * kAdjC3 * 4 + kAdjQ3 * 2 <= 160 * 1024,
+              "3D reverse-step LDS over 160 KB");
 
 // Phase-1 reads: fields and lambda_J in LDS (the particle within M of its tile).
 struct TileRead3 {
@@ -1003,8 +1017,12 @@ __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, 
                                                             int split)
 {
     constexpr int T = kAdjT3, M = kAdjM3, LF = kAdjLF3, LJ = kAdjLJ3, NF = kAdjNF3, NJ = kAdjNJ3, NT = kAdjThreads3;
+    constexpr int C = kAdjC3;
+    static_assert((C & (C - 1)) == 0 && NT % 64 == 0, "16-lane groups of one class set per wave");
     __shared__ double lds[6 * NF + 3 * NJ];
     __shared__ double sb[3];
+    __shared__ unsigned int qn[C], qoff[C];
+    __shared__ unsigned short queue[kAdjQ3];
     double* const sf = lds;  // phase 1: E, B^n; phase 2: lambda_E, lambda_B
     double* const sj = lds + 6 * NF;
     const int unit = xcd_tile(blockIdx.x, g.ntiles * split);
@@ -1028,6 +1046,7 @@ __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, 
         sj[e] = a.lamJ[comp * N + ((int64_t)gz * ny + gy) * nx + gx];
     }
     if (threadIdx.x < 3) sb[threadIdx.x] = 0.0;
+    if (threadIdx.x < C) qn[threadIdx.x] = 0u;
     __syncthreads();
 
     // phase 1
@@ -1043,17 +1062,57 @@ __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, 
             TileRead3 acc(sf, sj, rel);
             adj_particle3<false>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
             for (int k = 0; k < 6; ++k) a.scr[k][p] = lEB[k];
+            const int cls = acc.fo & (C - 1);
+            a.qslot[p] = (int64_t)atomicAdd(&qn[cls], 1u) * C + cls;
         } else {
             GlobalAcc<3> acc(g, a);
             adj_particle3<true>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
+            a.qslot[p] = -1;
         }
     }
     __syncthreads();
 
-    // phase 2
+    // the class queue (or storage order when it does not fit)
+    unsigned int rows = 0, total = 0;
+    for (int k = 0; k < C; ++k) {
+        rows = qn[k] > rows ? qn[k] : rows;
+        total += qn[k];
+    }
+    const bool classed = total <= (unsigned)kAdjQ3 && end - begin <= 65536;
+    if (threadIdx.x == 0) {
+        unsigned int o = 0;
+        for (int k = 0; k < C; ++k) {
+            qoff[k] = o;
+            o += qn[k];
+        }
+    }
     for (int e = threadIdx.x; e < 6 * NF; e += NT) sf[e] = 0.0;
     __syncthreads();
-    for (int64_t p = begin + part * NT + threadIdx.x; p < end; p += (int64_t)split * NT) {
+    if (classed)
+        for (int64_t p = begin + part * NT + threadIdx.x; p < end; p += (int64_t)split * NT) {
+            const int64_t q = a.qslot[p];
+            if (q >= 0) queue[qoff[q & (C - 1)] + q / C] = (unsigned short)(p - begin);
+        }
+    __syncthreads();
+
+    // phase 2
+    int64_t nslot = (int64_t)rows * C;
+    if (!classed) {
+        // storage order: the strides of phase 1
+        const int64_t rem = end - begin - (int64_t)part * NT, stride = (int64_t)split * NT;
+        nslot = rem > 0 ? (rem + stride - 1) / stride * NT : 0;
+    }
+    for (int64_t sl = threadIdx.x; sl < nslot; sl += NT) {
+        int64_t p;
+        if (classed) {
+            const int cls = (int)(sl & (C - 1));
+            const unsigned int r = (unsigned int)(sl / C);
+            if (r >= qn[cls]) continue;
+            p = begin + queue[qoff[cls] + r];
+        } else {
+            p = begin + part * NT + (sl / NT) * split * NT + sl % NT;
+            if (p >= end) continue;
+        }
         int i0[3], rel[3];
         double d0[3];
         if (!tile_place3(g, a, p, T0, i0, d0, rel)) continue;
@@ -1306,6 +1365,7 @@ hipError_t launch_adjoint_step(const Ctx& c, const void* record, bool by_id, dou
             a.scr[k] = static_cast<double*>(sp.alt.pos[k]);
             a.scr[3 + k] = static_cast<double*>(sp.alt.mom[k]);
         }
+        a.qslot = sp.alt.id;
         const unsigned pb = (unsigned)((sp.n + kAdjThreads - 1) / kAdjThreads);
         if (c.k.dims == 3 && pv.tiles) {
             const int split = (int)std::min<int64_t>(8, std::max<int64_t>(1, (512 + c.k.ntiles - 1) / c.k.ntiles));
