@@ -21,7 +21,7 @@ constexpr int kThreads = 256;
 constexpr int kBlocks = 1024;  // reduction workgroups
 constexpr int kCheck = 16;
 
-// device scalars: [0] r.r  [1] p.Ap  [4] b.b  [5] sum rho  [6] new r.r
+// device scalars: [0] r.r  [1] p.Ap  [2] target r.r  [4] b.b  [5] sum rho  [6] new r.r
 
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
@@ -108,15 +108,18 @@ __global__ __launch_bounds__(kThreads) void k_cg_apply(GridK g, const double* __
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// alpha = r.r / p.Ap (0 once the residual vanished); phi += alpha p;
-// r -= alpha Ap; partial new r.r
+// alpha = r.r / p.Ap; phi += alpha p; r -= alpha Ap; partial new r.r.  Once
+// r.r has reached the target the iterate is frozen (alpha = 0): the host
+// checks every kCheck iterations, and iterations past the rounding floor of
+// this singular (periodic) system make p.Ap a rounding residue, alpha
+// arbitrary and the residual grow again.
 __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t n, const double* __restrict__ s,
                                                         const double* __restrict__ pp, const double* __restrict__ ap,
                                                         double* __restrict__ phi, double* __restrict__ r,
                                                         double* __restrict__ part)
 {
     __shared__ double sh[kThreads];
-    const double alpha = s[1] > 0.0 ? s[0] / s[1] : 0.0;
+    const double alpha = s[0] > s[2] && s[1] > 0.0 ? s[0] / s[1] : 0.0;
     double v = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
         phi[p] += alpha * pp[p];
@@ -128,11 +131,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(int64_t n, const double*
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// beta = new r.r / old r.r; p = r + beta p (reads s[0] old, s[6] new)
+// beta = new r.r / old r.r; p = r + beta p (reads s[0] old, s[6] new); p is
+// left as it is once the iterate is frozen
 __global__ __launch_bounds__(kThreads) void k_cg_direction(int64_t n, double* __restrict__ s,
                                                            const double* __restrict__ r, double* __restrict__ pp)
 {
-    const double beta = s[0] > 0.0 ? s[6] / s[0] : 0.0;
+    if (!(s[0] > s[2])) return;
+    const double beta = s[6] / s[0];
     for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads)
         pp[p] = r[p] + beta * pp[p];
 }
@@ -140,6 +145,11 @@ __global__ __launch_bounds__(kThreads) void k_cg_direction(int64_t n, double* __
 __global__ void k_set(double* s, int dst, int src)
 {
     if (threadIdx.x == 0) s[dst] = s[src];
+}
+// s[dst] = f s[src]
+__global__ void k_scale(double* s, int dst, int src, double f)
+{
+    if (threadIdx.x == 0) s[dst] = f * s[src];
 }
 
 // E from the potential (Eq. egradphidis)
@@ -194,6 +204,7 @@ hipError_t solve_poisson(Ctx& c, double* rho, bool neutralize, double tol, int64
     hipLaunchKernelGGL(k_cg_init, dim3(gb), dim3(kThreads), 0, s, n, rho, sc, phi, r, pp, part);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, s, part, nb, sc, 4);
     hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, sc, 0, 4);  // r.r = b.b at the start
+    hipLaunchKernelGGL(k_scale, dim3(1), dim3(64), 0, s, sc, 2, 4, tol * tol);  // target r.r
     double host[7] = {0, 0, 0, 0, 0, 0, 0};
     hipError_t e = hipMemcpyAsync(host, sc, sizeof(host), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

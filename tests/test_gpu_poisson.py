@@ -56,20 +56,26 @@ def test_poisson_field_matches_reference(dims):
 
 def test_poisson_with_colocated_ions_gives_zero_field():
     """With ions at the electron positions the total charge vanishes cell by
-    cell and so does the field."""
+    cell up to the rounding of the two deposits, and so does the field.  The
+    right side is then rounding noise, which conjugate gradients resolve in a
+    few dozen iterations; iterating on past that (the host checks only every
+    16) once made the solve diverge, so the solve must stop at the tolerance.
+    Three contexts: the deposit's atomics round differently in each."""
     from paper_1101_0809_amd import Sim
     wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=8, ny=8, nz=8, ppc=2)
     e = picgen.electrons(wl)
     ion = picgen.ions_like(wl, e)
-    sim = Sim(nx=8, ny=8, nz=8, dt=wl.dt)
-    sim.add_species(e.q, e.m, e.n)
-    sim.load(0, e.x, e.w, e.weight)
-    sim.add_species(ion.q, ion.m, 0, mobile=False)
-    sim.load(1, ion.x, ion.w, ion.weight)
-    sim.solve_poisson(neutralize=False)
-    F = sim.fields_numpy()
-    assert np.max(np.abs(F[:3])) <= 1e-12 * e.weight[0]
-    sim.close()
+    for _ in range(3):
+        sim = Sim(nx=8, ny=8, nz=8, dt=wl.dt)
+        sim.add_species(e.q, e.m, e.n)
+        sim.load(0, e.x, e.w, e.weight)
+        sim.add_species(ion.q, ion.m, 0, mobile=False)
+        sim.load(1, ion.x, ion.w, ion.weight)
+        it, res = sim.solve_poisson(neutralize=False)
+        assert res <= 1e-13 and it < 200, (it, res)
+        F = sim.fields_numpy()
+        assert np.max(np.abs(F[:3])) <= 1e-12 * e.weight[0]
+        sim.close()
 
 
 def test_poisson_fullsize_64cube():
