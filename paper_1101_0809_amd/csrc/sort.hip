@@ -49,8 +49,11 @@ __device__ __forceinline__ uint32_t class_major_local(int lx, int ly, int lz)
     return (uint32_t)cls * (T * T * T / C) + idx;
 }
 
+// Sort key of particle p.  lut (3D, may be null) holds class_major_local of
+// the T^3 tile-local cells, x fastest.
 template <class R, int D, int T>
-__device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, int64_t p)
+__device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, int64_t p,
+                                           const uint32_t* lut = nullptr)
 {
     int i[3] = {0, 0, 0};
     if (sizeof(R) == 4) {
@@ -63,7 +66,9 @@ __device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, 
     const int tx = i[0] / T, ty = i[1] / T, tz = D == 3 ? i[2] / T : 0;
     const uint32_t tile = ((uint32_t)tz * g.nt[1] + ty) * g.nt[0] + tx;
     const uint32_t lx = i[0] - tx * T, ly = i[1] - ty * T, lz = D == 3 ? i[2] - tz * T : 0;
-    const uint32_t local = D == 3 ? class_major_local<lane_classes<R>()>((int)lx, (int)ly, (int)lz) : ly * T + lx;
+    uint32_t local = ly * T + lx;
+    if (D == 3)
+        local = lut ? lut[(lz * T + ly) * T + lx] : class_major_local<lane_classes<R>()>((int)lx, (int)ly, (int)lz);
     return tile * (uint32_t)(D == 3 ? T * T * T : T * T) + local;
 }
 
@@ -102,16 +107,20 @@ __global__ __launch_bounds__(1024) void k_histogram_tiled(GridK g, PartArrays a,
     constexpr int TPD = D == 3 ? T * T * T : T * T;
     constexpr int NTH = 1024, U = 4;  // threads, particles of a thread in flight
     __shared__ uint32_t cnt[TPD];
+    __shared__ uint32_t lut[D == 3 ? TPD : 1];  // class-major local keys, computed once per tile
     const int t = blockIdx.x;
     const int64_t b = ts[t], e = ts[t + 1];
     const uint32_t k0 = (uint32_t)t * TPD;
-    for (int c = threadIdx.x; c < TPD; c += NTH) cnt[c] = 0;
+    for (int c = threadIdx.x; c < TPD; c += NTH) {
+        cnt[c] = 0;
+        if (D == 3) lut[c] = class_major_local<lane_classes<R>()>(c % T, (c / T) % T, c / (T * T));
+    }
     __syncthreads();
     for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += U * NTH) {
         uint32_t k[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (p0 + u * NTH < e) k[u] = key_of<R, D, T>(g, a, p0 + u * NTH);
+            if (p0 + u * NTH < e) k[u] = key_of<R, D, T>(g, a, p0 + u * NTH, D == 3 ? lut : nullptr);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t p = p0 + u * NTH;
