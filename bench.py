@@ -245,9 +245,11 @@ def roofline(res, precision, wl, copy_gbs=None, order=1, interp="alternating"):
             "frac_of_copy": None if copy_gbs is None else round(achieved / copy_gbs, 4)}
 
 
-def cpu_baseline(wl, sample_steps: int = 1, order: int = 1, interp: str = "alternating"):
-    """The FP64 oracle as it stands, serial, on the host: one step of the full
-    workload (all particles, full grid)."""
+def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int = 1,
+                 interp: str = "alternating"):
+    """The FP64 oracle as it stands, serial, on the host: whole steps of the
+    full workload (all particles, full grid), as many as take min_seconds
+    (at most max_steps)."""
     import oracle
     import picgen
 
@@ -258,7 +260,10 @@ def cpu_baseline(wl, sample_steps: int = 1, order: int = 1, interp: str = "alter
                       [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m),
                        oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=False)])
     t0 = time.perf_counter()
-    st.step(sample_steps)
+    sample_steps = 0
+    while sample_steps < max_steps and (sample_steps == 0 or time.perf_counter() - t0 < min_seconds):
+        st.step(1)
+        sample_steps += 1
     dt = time.perf_counter() - t0
     return {"value": round(e.n * sample_steps / dt, 1), "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle",
