@@ -929,7 +929,9 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
 // area for lambda_E, lambda_B over the field region, scatters every
 // particle's lambda_Ep, lambda_Bp into it with LDS atomics, and adds it to
 // the grid once.  A particle more than M = 1 cell outside its tile runs
-// entirely in phase 1 from global memory, with global atomics.  The particle
+// entirely in phase 1 from global memory, with global atomics, after the
+// others: it is queued in the class queue's array (idle until phase 2), so
+// that a wave runs the LDS form or the global one, not both.  The particle
 // work fits 256 registers, so the 512 threads run as two waves per SIMD.
 //
 // Phase 2 hands particles to lanes by class, the residue of the particle's
@@ -1021,8 +1023,8 @@ __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, 
     static_assert((C & (C - 1)) == 0 && NT % 64 == 0, "16-lane groups of one class set per wave");
     __shared__ double lds[6 * NF + 3 * NJ];
     __shared__ double sb[3];
-    __shared__ unsigned int qn[C], qoff[C];
-    __shared__ unsigned short queue[kAdjQ3];
+    __shared__ unsigned int qn[C], qoff[C], nout;
+    __shared__ unsigned short queue[kAdjQ3];  // phase 1: the particles off the tile; phase 2: the class queue
     double* const sf = lds;  // phase 1: E, B^n; phase 2: lambda_E, lambda_B
     double* const sj = lds + 6 * NF;
     const int unit = xcd_tile(blockIdx.x, g.ntiles * split);
@@ -1047,6 +1049,7 @@ __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, 
     }
     if (threadIdx.x < 3) sb[threadIdx.x] = 0.0;
     if (threadIdx.x < C) qn[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) nout = 0u;
     __syncthreads();
 
     // phase 1
@@ -1065,10 +1068,28 @@ __global__ __launch_bounds__(kAdjThreads3) void k_adj_tile3(GridK g, AdjArgs a, 
             const int cls = acc.fo & (C - 1);
             a.qslot[p] = (int64_t)atomicAdd(&qn[cls], 1u) * C + cls;
         } else {
-            GlobalAcc<3> acc(g, a);
-            adj_particle3<true>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
+            // drifted more than one cell out of the tile: queued, so that a
+            // wave runs the LDS form or the global one, not both
+            const unsigned int slot = end - begin <= 65536 ? atomicAdd(&nout, 1u) : (unsigned int)kAdjQ3;
+            if (slot < (unsigned int)kAdjQ3) {
+                queue[slot] = (unsigned short)(p - begin);
+            } else {
+                GlobalAcc<3> acc(g, a);
+                adj_particle3<true>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
+            }
             a.qslot[p] = -1;
         }
+    }
+    __syncthreads();
+    const unsigned int nq = nout < (unsigned int)kAdjQ3 ? nout : (unsigned int)kAdjQ3;
+    for (unsigned int q = threadIdx.x; q < nq; q += NT) {
+        const int64_t p = begin + queue[q];
+        int i0[3];
+        double d0[3], w0[3], qp, lEB[6];
+        int64_t li;
+        load_particle<3>(a, p, i0, d0, w0, qp, li);
+        GlobalAcc<3> acc(g, a);
+        adj_particle3<true>(g, a, acc, i0, d0, w0, qp, li, lbp, lEB);
     }
     __syncthreads();
 
