@@ -931,7 +931,8 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(2))
 // the grid once.  A particle more than M = 1 cell outside its tile runs
 // entirely in phase 1 from global memory, with global atomics, after the
 // others: it is queued in the class queue's array (idle until phase 2), so
-// that a wave runs the LDS form or the global one, not both.  The particle
+// that a wave runs the LDS form or the global one, not both (inline when
+// that array is full or the tile holds more than 65536).  The particle
 // work fits 256 registers, so the 512 threads run as two waves per SIMD.
 //
 // Phase 2 hands particles to lanes by class, the residue of the particle's
@@ -952,7 +953,7 @@ constexpr int kAdjNJ3 = kAdjLJ3 * kAdjLJ3 * kAdjLJ3;
 constexpr int kAdjThreads3 = 512;
 constexpr int kAdjC3 = 16;      // lane classes: 16 lanes of 8-byte values per LDS pass
 constexpr int kAdjQ3 = 7168;    // class-queue entries (16-bit tile offsets)
-static_assert((6 * kAdjNF3 + 3 * kAdjNJ3 + 3) * 8 + 2 * kAdjC3 * 4 + kAdjQ3 * 2 <= 160 * 1024,
+static_assert((6 * kAdjNF3 + 3 * kAdjNJ3 + 3) * 8 + (2 * kAdjC3 + 1) * 4 + kAdjQ3 * 2 <= 160 * 1024,
               "3D reverse-step LDS over 160 KB");
 
 // Phase-1 reads: fields and lambda_J in LDS (the particle within M of its tile).
