@@ -147,6 +147,54 @@ def test_step_vjp_crowded_tile_scatters_in_storage_order():
     sim.close()
 
 
+def test_step_vjp_particles_off_their_tile():
+    """3D reverse step of a state six steps after its sort (hot beams, 24 x 16
+    x 16 cells, 12 tiles, no re-sort): a few percent of the particles lie more
+    than one cell outside the tile of their sorted slot, where the tile
+    kernel queues them and runs them on global memory after the others.
+    Against the oracle's one-step vector-Jacobian product of that state."""
+    from paper_1101_0809_amd import Sim
+    box, dt, n = (24, 16, 16), 0.45, 4000
+    x, w, weight = picgen.beams(box, n, 91, w_th=0.5, drift=0.3, dims=3)
+    shape = (box[2], box[1], box[0])
+    f = _fields(shape, 92, 0.05)
+    bext = (0.02, 0.01, -0.03)
+    sim = Sim(nx=box[0], ny=box[1], nz=box[2], dt=dt, dims=3, bext=bext, fields=f)
+    sim.add_species(-1.0, 1.0, capacity=n)
+    sim.load(0, x, w, weight)
+    sim.sort()
+    sim.step(6)
+    F = sim.fields_numpy()
+    xs, ws, wts, ids = sim.particles(0)
+    assert np.array_equal(ids, np.arange(n))
+    # the state really has particles more than one cell off the tile they
+    # were sorted into (the sort put each in the tile of its load position),
+    # with the kernel's periodic offset convention
+    rel = np.floor(xs) - np.floor(x / 8) * 8
+    for ax, nax in enumerate(box):
+        rel[ax] = np.where(rel[ax] > nax // 2, rel[ax] - nax, rel[ax])
+        rel[ax] = np.where(rel[ax] < -(nax // 2), rel[ax] + nax, rel[ax])
+    off = int(((rel < -1) | (rel > 8)).any(axis=0).sum())
+    assert off >= 20, off
+    rng = np.random.Generator(np.random.PCG64(93))
+    lam = [rng.normal(size=(3,) + shape), rng.normal(size=(3,) + shape),
+           rng.normal(size=(3, n)), rng.normal(size=(3, n))]
+    ref = ad.step_vjp(ad.Grid(*box, dt), F[:3], F[3:6], xs, ws, wts, -1.0, 1.0, bext, *lam)
+    dev = torch.device("cuda:0")
+    lf = torch.tensor(np.concatenate([lam[0], lam[1]]).reshape(-1), device=dev)
+    lx = torch.tensor(lam[2], device=dev)
+    lw = torch.tensor(lam[3], device=dev)
+    lb = torch.zeros(3, dtype=torch.float64, device=dev)
+    sim.adjoint_step(lf, [lx], [lw], lb)
+    got = lf.cpu().numpy().reshape((6,) + shape)
+    _close(got[:3], ref[0], 1e-12)
+    _close(got[3:], ref[1], 1e-12)
+    _close(lx.cpu().numpy(), ref[2], 1e-12)
+    _close(lw.cpu().numpy(), ref[3], 1e-12)
+    _close(lb.cpu().numpy(), ref[4], 1e-12)
+    sim.close()
+
+
 CASES = {
     # 2D3V beams in B_z, several sorts and checkpoint segments
     "2d_8x8": dict(box=(8, 8, 1), dims=2, dt=0.5, n=64, seed=17, w_th=0.05, drift=0.2,
