@@ -525,6 +525,7 @@ __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, A
             dm[ax][t] = dp[ax][t] = 0.0;
             ldm[ax][t] = ldp[ax][t] = 0.0;
         }
+#pragma unroll
     for (int ax = 0; ax < D; ++ax) {
         double s0[3], s1[3];
         cell_weights<double>(d0[ax], s0);
@@ -542,12 +543,16 @@ __device__ __forceinline__ void adj_particle(const GridK& g, const AdjArgs& a, A
 
     // back through the window to the start and end offsets
     double gd0[3] = {0.0, 0.0, 0.0}, gd1[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-        const int o0 = delta[ax] < 0 ? 1 : 0, o1 = delta[ax] > 0 ? 1 : 0;
+        // start weights sit one window cell right when delta < 0, end weights
+        // when delta > 0 (two-way selects, no indexed access)
+        const bool o0 = delta[ax] < 0, o1 = delta[ax] > 0;
         double ls0[3], ls1[3];
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
-            ls0[k] = ldp[ax][k + o0] - ldm[ax][k + o0];
-            ls1[k] = ldp[ax][k + o1] + ldm[ax][k + o1];
+            ls0[k] = o0 ? ldp[ax][k + 1] - ldm[ax][k + 1] : ldp[ax][k] - ldm[ax][k];
+            ls1[k] = o1 ? ldp[ax][k + 1] + ldm[ax][k + 1] : ldp[ax][k] + ldm[ax][k];
         }
         gd0[ax] = cell_weights_reverse(d0[ax], ls0);
         gd1[ax] = cell_weights_reverse(d1[ax], ls1);
