@@ -507,16 +507,16 @@ __device__ __forceinline__ void gather2_o2(const Axis2<R> (&w)[3], Acc F, R E[3]
 template <class R>
 __device__ __forceinline__ void window5(const R s0[4], const R s1[4], int shift, R dm[5], R dp[5])
 {
+    // start (end) weights one window cell right when shift < 0 (> 0); two-way
+    // selects, since a store at a run-time index becomes a chain of compares
     const bool o0 = shift < 0, o1 = shift > 0;
     R a[5], b[5];
+#pragma unroll
     for (int t = 0; t < 5; ++t) {
-        a[t] = R(0);
-        b[t] = R(0);
+        a[t] = o0 ? (t > 0 ? s0[t - 1] : R(0)) : (t < 4 ? s0[t] : R(0));
+        b[t] = o1 ? (t > 0 ? s1[t - 1] : R(0)) : (t < 4 ? s1[t] : R(0));
     }
-    for (int k = 0; k < 4; ++k) {
-        a[k + (o0 ? 1 : 0)] = s0[k];
-        b[k + (o1 ? 1 : 0)] = s1[k];
-    }
+#pragma unroll
     for (int t = 0; t < 5; ++t) {
         dm[t] = b[t] - a[t];
         dp[t] = b[t] + a[t];
