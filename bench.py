@@ -1,17 +1,22 @@
 """Throughput benchmark: particle-steps per second of the charge-conserving PIC
-step on one MI355X, FP64 and FP32-compensated, with the roofline position of
+step on one MI355X, FP32-compensated and FP64, with the roofline position of
 the particle kernel and the FP64 CPU oracle timed on the host beside it.
 
-Workload (default): 3D3V, 64^3 periodic cells, 8 electrons per cell
-(2,097,152 electrons), Gaussian momenta w_th = 0.1 c, co-located immobile ions,
-dt = 0.45 dx/c, particles re-sorted by cell every 10 steps.  One "step" is the
-whole step: both B half steps, particle kernel (gather, push, deposit) and E
-update, plus the periodic sort when due.  Inputs are resident on the GPU
-before the timed region starts.  The K timed steps carry no per-phase events;
-K further steps with HIP events around each phase give the per-kernel
-durations of the roofline and the phase breakdown.
+Workload (default): the largest single-GPU one, 3D3V on 256^3 periodic cells
+with 32 electrons and 32 mobile ions (mass ratio 100) per cell, 1,073,741,824
+particles, bi-Maxwellian electrons w_th = (0.3, 0.05, 0.05) c, ions
+w_th = 0.005 c, dt = 0.45 dx/c, particles re-sorted by cell every 20 steps;
+drawn on the GPU from seeded generators.  Its stated mode, FP32-compensated,
+leads the line; FP64 runs beside it on the same workload, and the FP32c error
+against FP64 after the same steps is reported.  One "step" is the whole step:
+both B half steps, the particle kernel of each species (gather, push,
+deposit) and the E update, plus the periodic sort when due.  Inputs are
+resident on the GPU before the timed region starts.  The K timed steps carry
+no per-phase events; a second pass of one sort period with HIP events around
+each phase gives the per-kernel durations of the roofline and the phase
+breakdown.
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 10]
+    python bench.py [--gpus 1] [--steps 40] [--warmup 5]
 
 prints one JSON line.  Other measurements, each printing its own line:
 --workload NAME (another workload of picgen.WORKLOADS), --order 2 (the
@@ -34,6 +39,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+DEFAULT_WORKLOAD = "3d_256cube_weibel"
+# the precision a workload is stated in leads its line; the other runs beside it
+HEADLINE_PRECISION = {"3d_256cube_weibel": "fp32c"}
 
 
 def particle_bytes(precision: str, dims: int) -> int:
@@ -51,22 +59,71 @@ def grid_bytes_particle_kernel() -> int:
     return 9 * 8
 
 
-def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1, interp: str = "alternating"):
-    import numpy as np
+DEVICE_DRAW = 1 << 26  # species at least this large are drawn on the GPU (picgen.device_chunks)
+
+
+def load_workload(sim, wl):
+    """Electrons, plus ions co-located with them: a second mobile species when
+    the workload's ions move, else the immobile background.  Large species
+    are drawn on the GPU in seeded chunks, the others on the host.  Returns
+    the indices of the mobile species."""
+    import picgen
+
+    n = wl.n_electrons
+    se = sim.add_species(-1.0, 1.0, n)
+    si = sim.add_species(1.0, wl.ion_mass, n if wl.ions_mobile else 0, mobile=wl.ions_mobile)
+    if n >= DEVICE_DRAW:
+        for sp, ions in ((se, False), (si, True)):
+            for x, w, wt in picgen.device_chunks(wl, sim.device, ions=ions):
+                sim.load(sp, x, w, wt)
+                del x, w, wt
+    else:
+        e = picgen.electrons(wl)
+        ion = picgen.ions_like(wl, e)
+        sim.load(se, e.x, e.w, e.weight)
+        sim.load(si, ion.x, ion.w, ion.weight)
+    return [se, si] if wl.ions_mobile else [se]
+
+
+def sampled_state(sim, species, per_species: int = 16384):
+    """E, B (host copies) and, per mobile species, about per_species particles
+    (those whose id is a multiple of a stride), in id order: (x, w) host
+    arrays.  For comparing two runs of one workload."""
+    import ctypes
+
     import torch
 
-    import picgen
+    F = sim.fields_numpy()[:6].copy()
+    parts = []
+    for sp in species:
+        n = sim.count(sp)
+        stride = max(1, n // per_species)
+        x = torch.empty((3, n), dtype=torch.float64, device=sim.device)
+        w = torch.empty((3, n), dtype=torch.float64, device=sim.device)
+        pid = torch.empty(n, dtype=torch.int64, device=sim.device)
+        sim._check(sim.lib.pic_get_particles(sim.ctx, sp, ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(w.data_ptr()), None,
+                                              ctypes.c_void_p(pid.data_ptr()),
+                                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        idx = torch.nonzero(pid % stride == 0).flatten()
+        order = torch.argsort(pid[idx])
+        idx = idx[order]
+        parts.append((x[:, idx].cpu().numpy(), w[:, idx].cpu().numpy()))
+        del x, w, pid, idx, order
+        torch.cuda.empty_cache()
+    return F, parts
+
+
+def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1, interp: str = "alternating",
+            sample: bool = False):
+    import torch
+
     from paper_1101_0809_amd import Sim
 
-    e = picgen.electrons(wl)
-    ion = picgen.ions_like(wl, e)
     sim = Sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=wl.dims, precision=precision,
-              sort_every=wl.sort_every, bext=wl.bext, order=order, interp=interp)
-    s = sim.add_species(e.q, e.m, e.n)
-    sim.load(s, e.x, e.w, e.weight)
-    si = sim.add_species(ion.q, ion.m, 0, mobile=False)
-    sim.load(si, ion.x, ion.w, ion.weight)
-    del e, ion
+              sort_every=wl.sort_every, bext=wl.bext, order=order, interp=interp, source=wl.source)
+    species = load_workload(sim, wl)
+    torch.cuda.empty_cache()
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -78,18 +135,54 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1, interp:
     stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
-    # second pass of as many steps with HIP events around every phase, on the
-    # stream the kernels run on: per-kernel durations for the roofline
-    sim.timing_start(steps)
-    sim.step(steps)
+    # a second pass with HIP events around every phase, on the stream the
+    # kernels run on: per-kernel durations for the roofline.  It spans one
+    # sort period (at least 20 steps), so the sort share is the run's.
+    tsteps = max(min(steps, max(20, wl.sort_every)), 1)
+    sim.timing_start(tsteps)
+    sim.step(tsteps)
     torch.cuda.synchronize()
     phases = sim.timing_stop()
     fallback = sim.fallback_fraction()
+    migrant = sim.migrant_fraction()
     d = sim.diagnostics()
-    n = sim.count(s)
+    counts = [sim.count(s) for s in species]
+    snap = sampled_state(sim, species) if sample else None
     sim.close()
-    return {"n": n, "ms_per_step": total_ms / steps, "phases": phases, "diag": d,
-            "fallback": fallback}
+    del sim
+    torch.cuda.empty_cache()
+    return {"n": sum(counts), "counts": counts, "ms_per_step": total_ms / steps, "phases": phases,
+            "diag": d, "fallback": fallback, "migrant": migrant, "sample": snap, "steps_total": warmup + steps + tsteps}
+
+
+def precision_error(r32, r64):
+    """FP32c against FP64 on the same workload after the same steps: relative
+    2-norm error of E and of B, and the largest momentum and position error
+    of the sampled particles (matched by id)."""
+    import numpy as np
+
+    F32, P32 = r32["sample"]
+    F64, P64 = r64["sample"]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    out = {"E_rel_l2": rel(F32[:3], F64[:3]), "B_rel_l2": rel(F32[3:6], F64[3:6])}
+    werr, xerr, m = 0.0, 0.0, 0
+    for (x32, w32), (x64, w64) in zip(P32, P64):
+        if w64.size == 0:
+            continue
+        werr = max(werr, float(np.max(np.abs(w32 - w64)) / np.max(np.abs(w64))))
+        dx = x32 - x64
+        for a, n in enumerate(F64.shape[1:][::-1]):
+            dx[a] -= n * np.round(dx[a] / n)
+        xerr = max(xerr, float(np.max(np.abs(dx))))
+        m += w64.shape[1]
+    d32, d64 = r32["diag"], r64["diag"]
+    out.update({"w_rel_max": werr, "x_abs_max_cells": xerr, "sampled_particles": m,
+                "kinetic_rel": abs(d32["kinetic"] - d64["kinetic"]) / abs(d64["kinetic"]),
+                "field_energy_rel": abs(d32["field_e"] + d32["field_b"] - d64["field_e"] - d64["field_b"])
+                / abs(d64["field_e"] + d64["field_b"]),
+                "after_steps": r64["steps_total"],
+                "sample": "fields: all cells; particles: about 16384 per species (ids on a fixed stride)"})
+    return out
 
 
 def adjoint_bytes(dims: int):
@@ -225,9 +318,15 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
 
 
 def roofline(res, precision, wl, copy_gbs=None, order=1, interp="alternating"):
-    per_launch_ms = res["phases"]["particles"] / max(1, res["phases"]["steps"])
+    """Position of the particle kernel against the HBM roofline.  One launch
+    advances one mobile species: its particles' state is read and written
+    once and the grid's E, B^n read and J written once.  achieved = those
+    algorithmic bytes per launch over the launch's average duration (HIP
+    events on the kernels' stream)."""
+    nlaunch = len(res["counts"])
+    per_launch_ms = res["phases"]["particles"] / max(1, res["phases"]["steps"]) / nlaunch
     bytes_launch = (res["n"] * particle_bytes(precision, wl.dims)
-                    + wl.ncell * grid_bytes_particle_kernel())
+                    + nlaunch * wl.ncell * grid_bytes_particle_kernel()) / nlaunch
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     kernel = "k_particle_step3" if wl.dims == 3 else "k_particle_step"
     traffic = measured_traffic(precision, wl.name)
@@ -239,48 +338,85 @@ def roofline(res, precision, wl, copy_gbs=None, order=1, interp="alternating"):
         traffic = None
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "bytes_per_launch": bytes_launch,
+            "traffic": traffic, "bytes_per_launch": int(bytes_launch),
+            "bytes_per_particle_step": round(bytes_launch * nlaunch / res["n"], 2),
+            "launches_per_step": nlaunch,
             "avg_launch_ms": round(per_launch_ms, 5),
             "copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
             "frac_of_copy": None if copy_gbs is None else round(achieved / copy_gbs, 4)}
 
 
-def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int = 1,
-                 interp: str = "alternating"):
-    """The FP64 oracle as it stands, serial, on the host: whole steps of the
-    full workload (all particles, full grid), as many as take min_seconds
-    (at most max_steps)."""
+def _oracle_state(wl, e, ion, order=1, interp="alternating"):
     import oracle
+
+    sp = [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m)] if e is not None else []
+    if ion is not None:
+        sp.append(oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=wl.ions_mobile))
+    return oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext, order=order,
+                                    interp=1 if interp == "conventional" else 0, source=wl.source), sp)
+
+
+def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int = 1,
+                 interp: str = "alternating", full_limit: int = 1 << 22, sample_n: int = 1 << 20):
+    """The FP64 oracle as it stands, serial, on the host.  A workload of at
+    most full_limit mobile particles runs whole steps (all particles, full
+    grid), as many as take min_seconds (at most max_steps).  A larger one is
+    sampled: one step of the full grid without particles (the field updates)
+    and one step of the full grid with sample_n electrons (and as many ions
+    when they move) drawn from the workload's distributions; the per-particle
+    time of the second, with the grid time of the first, gives the rate of a
+    step of the whole workload."""
     import picgen
 
-    e = picgen.electrons(wl)
-    ion = picgen.ions_like(wl, e)
-    st = oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext, order=order,
-                                  interp=1 if interp == "conventional" else 0),
-                      [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m),
-                       oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=False)])
+    host = (f"host {platform.processor() or platform.machine()} "
+            f"({os.cpu_count()} logical CPUs, 1 used)")
+    if wl.n_particles <= full_limit:
+        e = picgen.electrons(wl)
+        ion = picgen.ions_like(wl, e)
+        st = _oracle_state(wl, e, ion, order, interp)
+        t0 = time.perf_counter()
+        sample_steps = 0
+        while sample_steps < max_steps and (sample_steps == 0 or time.perf_counter() - t0 < min_seconds):
+            st.step(1)
+            sample_steps += 1
+        dt = time.perf_counter() - t0
+        return {"value": round(wl.n_particles * sample_steps / dt, 1), "unit": "particle-steps/s",
+                "cores": 1, "kind": "oracle",
+                "sample": f"{sample_steps} full step(s) of the same workload ({wl.n_particles} particles, "
+                          f"order {order} 1/2, {interp} interpolation, {wl.nx}x{wl.ny}x{wl.nz} grid), "
+                          f"serial C oracle, {dt:.1f} s, {host}"}
+    grid_only = _oracle_state(wl, None, None, order, interp)
     t0 = time.perf_counter()
-    sample_steps = 0
-    while sample_steps < max_steps and (sample_steps == 0 or time.perf_counter() - t0 < min_seconds):
-        st.step(1)
-        sample_steps += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(e.n * sample_steps / dt, 1), "unit": "particle-steps/s", "cores": 1,
+    grid_only.step(1)
+    t_grid = time.perf_counter() - t0
+    del grid_only
+    small = wl.scaled(ppc=1)
+    e = picgen.electrons(small, n=sample_n)
+    e.weight[:] = wl.weight
+    ion = picgen.ions_like(wl, e)
+    st = _oracle_state(wl, e, ion, order, interp)
+    ns = sample_n * (2 if wl.ions_mobile else 1)
+    t0 = time.perf_counter()
+    st.step(1)
+    t_step = time.perf_counter() - t0
+    t_pp = max(t_step - t_grid, 1e-12) / ns
+    t_full = t_grid + wl.n_particles * t_pp
+    return {"value": round(wl.n_particles / t_full, 1), "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{sample_steps} full step(s) of the same workload ({e.n} particles, order {order} 1/2, "
-                      f"{interp} interpolation, "
-                      f"{wl.nx}x{wl.ny}x{wl.nz} grid), serial C oracle, {dt:.1f} s, "
-                      f"host {platform.processor() or platform.machine()} "
-                      f"({os.cpu_count()} logical CPUs, 1 used)"}
+            "sample": f"full {wl.nx}x{wl.ny}x{wl.nz} grid: one oracle step without particles "
+                      f"({t_grid:.2f} s, the field updates) and one with {ns} particles drawn from the "
+                      f"workload's distributions ({t_step:.2f} s); rate of the whole workload "
+                      f"({wl.n_particles} particles) = N / (grid time + N x per-particle time), "
+                      f"serial C oracle, order {order} 1/2, {interp} interpolation, {host}"}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=None,
-                    help="workload name (default 3d_64cube_8ppc; 2d3v_256sq_beams with --adjoint)")
+                    help=f"workload name (default {DEFAULT_WORKLOAD}; 2d3v_256sq_beams with --adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32c"], default="both")
     ap.add_argument("--copy-probe", action="store_true",
@@ -347,17 +483,23 @@ def main(argv=None):
         return 2
 
     import picgen
-    wl = picgen.WORKLOADS[args.workload or "3d_64cube_8ppc"]
-    precs = ["fp64", "fp32c"] if args.precision == "both" else [args.precision]
+    wl = picgen.WORKLOADS[args.workload or DEFAULT_WORKLOAD]
+    head = HEADLINE_PRECISION.get(wl.name, "fp64")
+    other = "fp64" if head == "fp32c" else "fp32c"
+    precs = [head, other] if args.precision == "both" else [args.precision]
     if args.order == 2 or args.interp == "conventional":
         precs = ["fp64"]
     results = {}
     for p in precs:
-        results[p] = run_gpu(wl, p, args.steps, args.warmup, args.order, args.interp)
+        print(f"# {wl.name} {p}: loading {wl.n_particles} particles, {args.warmup} + {args.steps} steps",
+              file=sys.stderr, flush=True)
+        results[p] = run_gpu(wl, p, args.steps, args.warmup, args.order, args.interp,
+                             sample=len(precs) == 2)
         r = results[p]
-        print(f"# {p}: {r['ms_per_step']:.4f} ms/step, particle kernel "
-              f"{r['phases']['particles'] / max(1, r['phases']['steps']):.4f} ms, "
-              f"gauss_rel {r['diag']['gauss_rel']:.2e}, fallback {r['fallback']:.4f}",
+        print(f"# {p}: {r['ms_per_step']:.4f} ms/step, particle kernels "
+              f"{r['phases']['particles'] / max(1, r['phases']['steps']):.4f} ms/step, "
+              f"gauss_rel {r['diag']['gauss_rel']:.2e}, fallback {r['fallback']:.6f}, "
+              f"migrants {r['migrant']:.6f}",
               file=sys.stderr, flush=True)
     copy_gbs = copy_bandwidth()
     main_p = precs[0]
@@ -377,22 +519,31 @@ def main(argv=None):
         "dtype": "f64" if main_p == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny, wl.nz], "particles": r["n"],
-                   "ppc": wl.ppc, "dt": wl.dt, "sort_every": wl.sort_every,
+                   "particles_per_species": r["counts"], "ppc": wl.ppc,
+                   "mobile_ions": wl.ions_mobile, "dt": wl.dt, "sort_every": wl.sort_every,
                    "precision": main_p, "order": f"{args.order} 1/2", "interp": args.interp,
                    "parallelism": "none (1 GPU)"},
         "roofline": roofline(r, main_p, wl, copy_gbs, args.order, args.interp),
         "phases_ms_per_step": {k: round(v / max(1, r["phases"]["steps"]), 5)
                                for k, v in r["phases"].items() if k != "steps"},
         "checks": {"gauss_rel": r["diag"]["gauss_rel"], "nonfinite": r["diag"]["nonfinite"],
-                   "fallback_fraction": r["fallback"]},
+                   "fallback_fraction": r["fallback"], "migrant_fraction": r["migrant"]},
     }
-    if "fp32c" in results and main_p != "fp32c":
-        r32 = results["fp32c"]
-        v32 = r32["n"] * 1000.0 / r32["ms_per_step"]
-        line["fp32c"] = {"value": round(v32, 1), "ms_per_step": round(r32["ms_per_step"], 5),
-                         "speedup_vs_fp64": round(v32 / value, 3),
-                         "roofline": roofline(r32, "fp32c", wl, copy_gbs),
-                         "gauss_rel": r32["diag"]["gauss_rel"]}
+    if len(precs) == 2:
+        ro = results[other]
+        vo = ro["n"] * 1000.0 / ro["ms_per_step"]
+        v64, v32 = (vo, value) if other == "fp64" else (value, vo)
+        line[other] = {"value": round(vo, 1), "ms_per_step": round(ro["ms_per_step"], 5),
+                       "roofline": roofline(ro, other, wl, copy_gbs),
+                       "phases_ms_per_step": {k: round(v / max(1, ro["phases"]["steps"]), 5)
+                                              for k, v in ro["phases"].items() if k != "steps"},
+                       "gauss_rel": ro["diag"]["gauss_rel"], "fallback_fraction": ro["fallback"],
+                       "migrant_fraction": ro["migrant"]}
+        line["fp32c_speedup_vs_fp64"] = round(v32 / v64, 3)
+        line["fp32c_error_vs_fp64"] = precision_error(results["fp32c"], results["fp64"])
+    line["context"] = {"paper": "about 2.1e5 particles advanced per second of CPU time per processor "
+                                "(FP64, order 1 1/2, 64^3 grid, 2 electrons per cell; Section 5); "
+                                "another machine, not a target"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, order=args.order, interp=args.interp)
     print(json.dumps(line), flush=True)

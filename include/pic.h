@@ -123,7 +123,7 @@ typedef struct pic_species_desc {
     int32_t mobile;      /* 0: immobile background charge, deposited once into a
                             fixed density and never pushed; 1: pushed and deposited */
     int32_t reserved;    /* must be 0 */
-    int64_t capacity;    /* maximum particle count of this species */
+    int64_t capacity;    /* maximum particle count of this species (below 2^32) */
 } pic_species_desc;
 
 typedef struct pic_sizes {
@@ -312,9 +312,16 @@ int pic_get_particles(pic_ctx* ctx, int species, double* x, double* w, double* w
 int pic_sort(pic_ctx* ctx, void* stream);
 
 /* Tuning of the particle-step kernel: fraction of particle updates that took
- * the global-memory path (outside their tile's LDS region) during the last
+ * the global-memory path (grid gathers and global atomics) during the last
  * pic_step call, or -1 if not recorded.  Synchronizes the stream. */
 double pic_last_fallback_fraction(pic_ctx* ctx, void* stream);
+
+/* Tuning of the 3D particle step: fraction of particle updates during the
+ * last pic_step call that were made by the migrant pass (particles found more
+ * than one cell outside their sorted tile, advanced with the LDS tiles of
+ * the tile that holds them now), or -1 if not recorded.  Synchronizes the
+ * stream. */
+double pic_last_migrant_fraction(pic_ctx* ctx, void* stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each pic_step
  * (a profiling aid; events only, no device memory).  pic_timing_start begins

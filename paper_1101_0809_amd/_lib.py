@@ -21,7 +21,8 @@ PIC_AUX = 8192  # source line length (include/pic.h)
 EXPORTS = (
     "pic_query_sizes", "pic_init_grid", "pic_add_species", "pic_load_particles", "pic_step",
     "pic_deposit_J", "pic_field_solve", "pic_diagnostics", "pic_particle_count",
-    "pic_get_particles", "pic_sort", "pic_last_fallback_fraction", "pic_timing_start",
+    "pic_get_particles", "pic_sort", "pic_last_fallback_fraction", "pic_last_migrant_fraction",
+    "pic_timing_start",
     "pic_timing_stop", "pic_get_host_state", "pic_set_host_state", "pic_destroy",
     "pic_adjoint_seed_field_energy", "pic_adjoint_step", "pic_adjoint_record_bytes",
     "pic_adjoint_record", "pic_adjoint_step_record", "pic_adjoint_step_record_ordered",
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
         "pic_get_particles": (I, [P, I, P, P, P, P, P]),
         "pic_sort": (I, [P, P]),
         "pic_last_fallback_fraction": (D, [P, P]),
+        "pic_last_migrant_fraction": (D, [P, P]),
         "pic_timing_start": (I, [P, I]),
         "pic_timing_stop": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),
         "pic_get_host_state": (I, [P, ctypes.POINTER(HostState)]),

@@ -168,6 +168,7 @@ size_t workspace_bytes(const GridK& k, uint32_t nkeys)
     b += align_up(3 * (size_t)k.ncell * 8, kAlign);                      // B^n for the particles
     b += align_up(3 * (size_t)k.ncell * 8, kAlign);                      // adjoint scratch
     if (k.field_form == 1) b += align_up(3 * (size_t)k.ncell * 8, kAlign);  // vector potential
+    b += align_up((size_t)k.ntiles * 4, kAlign);                         // migrant bucket counters
     b += align_up(2 * (size_t)PIC_AUX * 8, kAlign);                      // source line (last)
     return b;
 }
@@ -316,6 +317,7 @@ int pic_init_grid(const pic_grid_desc* g, void* fields, size_t field_bytes, void
     c.bn = (double*)take(3 * (size_t)k.ncell * 8);
     c.adj = (double*)take(3 * (size_t)k.ncell * 8);
     if (k.field_form == 1) c.avec = (double*)take(3 * (size_t)k.ncell * 8);
+    c.mig_n = (unsigned int*)take((size_t)k.ntiles * 4);
     c.k.aux = (double*)take(2 * (size_t)PIC_AUX * 8);  // last: its place is documented
     hipError_t e = hipMemset(c.rho_bg, 0, (size_t)k.ncell * 8);
     if (e == hipSuccess && c.avec) {  // A = 0 and B = curl_h A = 0
@@ -324,6 +326,7 @@ int pic_init_grid(const pic_grid_desc* g, void* fields, size_t field_bytes, void
     }
     if (e == hipSuccess) e = hipMemset(c.k.aux, 0, 2 * (size_t)PIC_AUX * 8);
     if (e == hipSuccess) e = hipMemset(c.counters, 0, 8 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(c.mig_n, 0, (size_t)k.ntiles * 4);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         delete ctx;
@@ -339,8 +342,9 @@ int pic_add_species(pic_ctx* ctx, const pic_species_desc* s, void* buffer, size_
     if (!ctx || !s || !species) return fail(ctx ? &ctx->c : nullptr, PIC_EINVAL, "null argument");
     Ctx& c = ctx->c;
     if (c.nsp >= kMaxSpecies) return fail(&c, PIC_ESTATE, "at most 4 species");
-    if (!(s->m > 0) || !isfinite(s->q) || s->capacity < 0 || s->reserved != 0)
-        return fail(&c, PIC_EINVAL, "species needs m > 0, finite q, capacity >= 0, reserved 0");
+    if (!(s->m > 0) || !isfinite(s->q) || s->capacity < 0 || s->capacity > (int64_t)UINT32_MAX ||
+        s->reserved != 0)
+        return fail(&c, PIC_EINVAL, "species needs m > 0, finite q, 0 <= capacity < 2^32, reserved 0");
     Species& sp = c.sp[c.nsp];
     sp = Species{};
     sp.d = *s;
@@ -413,7 +417,7 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
     // fallback statistics of this call (pic_last_fallback_fraction), zeroed
     // by the first field kernel of the call
     if (nsteps == 0) {
-        e = zero_counters(c.counters + 1, 2, s);
+        e = zero_counters(c.counters + 1, 3, s);
         if (e != hipSuccess) return hip_fail(&c, e, "step");
     }
     for (int it = 0; it < nsteps; ++it) {
@@ -427,8 +431,8 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
         mark(0);
         if (e == hipSuccess)
             e = c.k.field_form == 1
-                    ? launch_field_half_a_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 2 : 0)
-                    : launch_field_half_b_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 2 : 0);
+                    ? launch_field_half_a_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 3 : 0)
+                    : launch_field_half_b_pair(c, s, it == 0 ? c.counters + 1 : nullptr, it == 0 ? 3 : 0);
         mark(1);
         for (int i = 0; i < c.nsp && e == hipSuccess; ++i)
             if (c.sp[i].d.mobile) e = launch_particle_step(c, c.sp[i], s);
@@ -689,6 +693,18 @@ double pic_last_fallback_fraction(pic_ctx* ctx, void* stream)
     if (hipStreamSynchronize(s) != hipSuccess) return -1.0;
     if (h[1] == 0) return -1.0;
     return (double)h[0] / (double)h[1];
+}
+
+double pic_last_migrant_fraction(pic_ctx* ctx, void* stream)
+{
+    if (!ctx) return -1.0;
+    Ctx& c = ctx->c;
+    unsigned long long h[3] = {0, 0, 0};
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(h, c.counters + 1, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return -1.0;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1.0;
+    if (h[1] == 0) return -1.0;
+    return (double)h[2] / (double)h[1];
 }
 
 int pic_timing_start(pic_ctx* ctx, int max_steps)

@@ -233,32 +233,35 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 // first plane and store planes 1..11 only.  The FP64 current tile covers
 // T0-3 .. T0+10 (14 cells per axis) with plane stride kJPlane3.  A cell's
 // field and current base indices then share their residue modulo 32, and that
-// residue modulo C (16 in FP64, 32 in FP32) is the cell's lane class.  The
-// kernel hands particles to lanes by class, so that the LDS reads and atomics
-// of 16 consecutive lanes (one LDS pass for 8-byte values) fall in 16
-// distinct bank pairs.
+// residue modulo C (16 in FP64, 32 in FP32) is the cell's lane class.  Lanes
+// of one LDS pass that hold cells of distinct classes read and add in
+// distinct banks.
 //
-// Passes over the tile:
-//   1. every slot: the particle's cell is read and classified (the loads of
-//      several slots of a thread in flight at once), and the particle
-//      appended to the class queue, column = its class;
-//   2. the class queue, row by row, then the particles pass 1 could not
-//      queue: each particle is advanced and, if it stays in its cell, deposits
-//      its 54 non-zero contributions; one that crosses a cell face is appended
-//      to the crossing queue;
-//   3. the crossing queue, in the order of a class map (column = class of the
-//      window's first cell), in sections by crossing axis: a particle that
-//      crossed along one axis deposits the 75 non-zero contributions of its
-//      window, one that crossed along several all 144.
-// Class-queue entry (row r, column k) is slot k + C r of the tile's range in
-// one of two spare-copy arrays (rows below n_t / C in the first), so the lanes
-// of one pass hold distinct classes; particles of the tile that sit in cells
-// of their slot's class also sit in queue order close to their slot, which
-// keeps the pass-2 loads nearly coalesced.  A particle outside the tile
-// region, or one whose class column is full, goes to the list of the others
-// (the spare copy's third momentum array) and is advanced after the queue with
-// global memory or uncoordinated LDS accesses (correct, only slower).  The
-// spare copy is idle between sorts.
+// The tile's particles are taken in chunks of NT consecutive storage slots,
+// so that every load and store of a chunk stays within a few cache lines per
+// array however far the particles have drifted since the last sort.  For each
+// chunk:
+//   (a) every slot's cell is classified (the load was issued during the
+//       previous chunk).  A particle within M cells of the tile takes a rank
+//       in its class (LDS atomic); any other particle has left the tile's
+//       region and is appended to the migrant bucket of the tile that now
+//       holds its cell, for k_migrants3;
+//   (b) one wave turns the class counts into rows: row r holds the rank-r
+//       particle of every class that has one, in class order;
+//   (c) each particle writes its slot into the chunk's permutation at its
+//       row position, so consecutive lanes hold distinct classes;
+//   (d) lane t advances the particle at permutation entry t: gather (LDS),
+//       push, move (state stored), and, if it stays in its cell, its 54
+//       non-zero current contributions; a particle that crosses a cell face
+//       is appended to the crossing queue, with its place in a class map
+//       (column = class of its window's first cell).
+// After the chunks, pass 3 deposits the crossing particles' windows in
+// class-map order, in sections by crossing axis (75 contributions for one
+// axis, 144 for several); the entries a full map column could not take
+// follow in arrival order.  Migrants whose bucket was full are advanced with
+// global memory (gather from the grid, global atomics).  Last, the non-zero
+// current entries are flushed with global FP64 atomics.  The spare particle
+// copy holds the crossing queue and the overflow list (idle between sorts).
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a field component
 {
@@ -267,6 +270,202 @@ __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a 
 __host__ __device__ constexpr int fnodez(int comp) { return comp >= 2 && comp <= 4 ? 1 : 0; }
 constexpr int kFieldPlanes3 = 69;  // 12 + 12 + 11 + 11 + 11 + 12
 constexpr int64_t kUnmapped = (int64_t)1 << 62;  // crossing entry not in the class map
+constexpr int kRowMax = 128;  // class rows ordered per chunk; higher ranks follow in arrival order
+constexpr unsigned kMigLds = 64;  // a migrant bucket this full is advanced with LDS tiles
+
+// Stage E^n and B^n of the 3D tile region into LDS, with SK loads of a thread
+// in flight before their stores (one load at a time would wait out the
+// memory latency once per value).
+template <class R, int NT>
+__device__ __forceinline__ void stage_fields3(const GridK& g, const int T0[3], const double* __restrict__ fields,
+                                              const double* __restrict__ bfield, R* sf, bool small)
+{
+    constexpr int T = kTile3, M = kMargin3;
+    constexpr int LF = T + 2 + 2 * M;
+    constexpr int SFY = kFieldRow3, SFZ = kFieldPlane3;
+    constexpr int NV = kFieldPlanes3 * LF * LF;
+    constexpr int SK = 7;
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
+    for (int e0 = threadIdx.x; e0 < NV; e0 += SK * NT) {
+        double v[SK];
+        int li[SK];
+#pragma unroll
+        for (int u = 0; u < SK; ++u) {
+            const int e = e0 + u * NT;
+            li[u] = -1;
+            if (e < NV) {
+                const int pl = e / (LF * LF);
+                const int rr = e - pl * (LF * LF);
+                const int ly = rr / LF;
+                const int lx = rr - ly * LF;
+                const int comp = pl < 12 ? 0 : (pl < 24 ? 1 : (pl < 35 ? 2 : (pl < 46 ? 3 : (pl < 57 ? 4 : 5))));
+                const int lz = pl - fplane0(comp) + fnodez(comp);
+                const int gx = wr(T0[0] - 1 - M + lx, nx);
+                const int gy = wr(T0[1] - 1 - M + ly, ny);
+                const int gz = wr(T0[2] - 1 - M + lz, nz);
+                v[u] = (comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[((int64_t)gz * ny + gy) * nx + gx];
+                li[u] = pl * SFZ + ly * SFY + lx;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SK; ++u)
+            if (li[u] >= 0) sf[li[u]] = (R)v[u];
+    }
+}
+
+// Flush the LDS current tile of a 3D tile into the grid's J (the plane
+// padding is never written).
+template <class R, int NT, class LJT>
+__device__ __forceinline__ void flush_current3(const GridK& g, const int T0[3], const LJT& sj,
+                                               double* __restrict__ Jg, bool small)
+{
+    constexpr int M = kMargin3;
+    constexpr int LJ = kTile3 + 4 + 2 * M;
+    constexpr int SJZ = kJPlane3;
+    constexpr int NJ = LJ * SJZ;
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
+    for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
+        const double v = sj.get(e);
+        if (v == 0.0) continue;
+        const int comp = e / NJ;
+        const int r = e - comp * NJ;
+        const int lz = r / SJZ;
+        const int rr = r - lz * SJZ;
+        const int ly = rr / LJ;
+        const int lx = rr - ly * LJ;
+        const int gx = wr(T0[0] - 2 - M + lx, nx);
+        const int gy = wr(T0[1] - 2 - M + ly, ny);
+        const int gz = wr(T0[2] - 2 - M + lz, nz);
+        global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
+    }
+}
+
+// Position of cell i0 relative to the tile at T0, periodic-corrected; true if
+// within M cells of the tile (inside its LDS regions).
+__device__ __forceinline__ bool relative3(const GridK& g, const int T0[3], const int i0[3], int rel[3])
+{
+    constexpr int T = kTile3, M = kMargin3;
+    bool in = true;
+    for (int ax = 0; ax < 3; ++ax) {
+        int r = i0[ax] - T0[ax];
+        const int n = g.n[ax];
+        if (r > n / 2) r -= n;
+        if (r < -(n / 2)) r += n;
+        rel[ax] = r;
+        in = in && (r >= -M) && (r <= T - 1 + M);
+    }
+    return in;
+}
+
+// Tile that holds cell i (clamped into the grid, so that any input names a tile).
+__device__ __forceinline__ int tile_of3(const GridK& g, const int i[3])
+{
+    int t[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const int c = i[ax] < 0 ? 0 : (i[ax] >= g.n[ax] ? g.n[ax] - 1 : i[ax]);
+        t[ax] = c / kTile3;
+    }
+    return (t[2] * g.nt[1] + t[1]) * g.nt[0] + t[0];
+}
+
+// Gather from the LDS field tile, push and move one particle whose cell is at
+// rel (inside the tile region); stores w and the new position.  Returns the
+// start form factors, the end offsets, the cell shift and the macro charge.
+template <class R>
+__device__ __forceinline__ void advance_lds3(const GridK& g, const StepArgs& a, const R* sf, int64_t p,
+                                             const int i0[3], const R d0[3], const int rel[3], Axis<R> (&ax0)[3],
+                                             R d1[3], int delta[3], R& qp)
+{
+    constexpr int M = kMargin3;
+    constexpr int SFY = kFieldRow3, SFZ = kFieldPlane3;
+    R w[3];
+    for (int ax = 0; ax < 3; ++ax) w[ax] = ((const R*)a.mom[ax])[p];
+    qp = (R)a.q * ((const R*)a.weight)[p];
+    for (int ax = 0; ax < 3; ++ax) ax0[ax] = form_factor<R>(d0[ax]);
+    R E[3], B[3];
+    const int base = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SFY + (rel[2] + 1 + M) * SFZ;
+    auto F = [&](int comp, int da, int db, int dc) -> R {
+        return sf[(fplane0(comp) - fnodez(comp)) * SFZ + base + da + db * SFY + dc * SFZ];
+    };
+    gather3<R>(ax0, F, E, B);
+    for (int ax = 0; ax < 3; ++ax) B[ax] += (R)g.bext[ax];
+    const R c2 = (R)g.c * (R)g.c;
+    push<R>((R)(0.5 * a.qm * g.dt), c2, E, B, w);
+    for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
+    const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
+    R disp[3];
+    for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * (R)g.cfl[ax];
+    for (int ax = 0; ax < 3; ++ax) delta[ax] = 0;
+    PosIO<R, 3>::move(a, p, g, i0, d0, disp, d1, delta, true);
+}
+
+// The whole step of one particle on global memory: gather from the grid
+// (wrapped indices), push, move, and the full current window with global
+// atomics.  Correct for any position; used only where the LDS tiles do not
+// cover the particle.
+template <class R>
+__device__ __forceinline__ void advance_global3(const GridK& g, const StepArgs& a, int64_t p,
+                                                const double* __restrict__ fields,
+                                                const double* __restrict__ bfield, double* __restrict__ Jg)
+{
+    const int64_t N = g.ncell;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    int i0[3];
+    R d0[3];
+    PosIO<R, 3>::load(a, p, i0, d0);
+    R w[3];
+    for (int ax = 0; ax < 3; ++ax) w[ax] = ((const R*)a.mom[ax])[p];
+    const R qp = (R)a.q * ((const R*)a.weight)[p];
+    Axis<R> ax0[3];
+    for (int ax = 0; ax < 3; ++ax) ax0[ax] = form_factor<R>(d0[ax]);
+    R E[3], B[3];
+    {
+        int xi[3], yj[3];
+        int64_t zk[3];
+        for (int o = 0; o < 3; ++o) {
+            xi[o] = wrapi(i0[0] + o - 1, nx);
+            yj[o] = wrapi(i0[1] + o - 1, ny) * nx;
+            zk[o] = (int64_t)wrapi(i0[2] + o - 1, nz) * nx * ny;
+        }
+        auto F = [&](int comp, int da, int db, int dc) -> R {
+            return (R)(comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[zk[dc + 1] + yj[db + 1] + xi[da + 1]];
+        };
+        gather3<R>(ax0, F, E, B);
+    }
+    for (int ax = 0; ax < 3; ++ax) B[ax] += (R)g.bext[ax];
+    const R c2 = (R)g.c * (R)g.c;
+    push<R>((R)(0.5 * a.qm * g.dt), c2, E, B, w);
+    for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
+    const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
+    R disp[3];
+    for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * (R)g.cfl[ax];
+    R d1[3];
+    int delta[3] = {0, 0, 0};
+    PosIO<R, 3>::move(a, p, g, i0, d0, disp, d1, delta, true);
+    R jfac[3];
+    for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+    R dm[3][4], dp[3][4];
+    for (int ax = 0; ax < 3; ++ax) {
+        R s1[3];
+        cell_weights<R>(d1[ax], s1);
+        window<R>(ax0[ax].s, s1, delta[ax], dm[ax], dp[ax]);
+    }
+    int xi[4], yj[4];
+    int64_t zk[4];
+    for (int o = 0; o < 4; ++o) {
+        xi[o] = wrapi(i0[0] + (delta[0] < 0 ? -1 : 0) - 1 + o, nx);
+        yj[o] = wrapi(i0[1] + (delta[1] < 0 ? -1 : 0) - 1 + o, ny) * nx;
+        zk[o] = (int64_t)wrapi(i0[2] + (delta[2] < 0 ? -1 : 0) - 1 + o, nz) * nx * ny;
+    }
+    auto S = [&](int comp, int ix, int iy, int iz, R v) {
+        global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
+    };
+    deposit3<R>(dm, dp, jfac, S);
+}
 
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, const double* __restrict__ fields,
@@ -275,281 +474,191 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     constexpr int T = kTile3, M = kMargin3;
     constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
     constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
-    constexpr int SFY = kFieldRow3, SFZ = kFieldPlane3;
     constexpr int SJY = LJ, SJZ = kJPlane3;
     constexpr int NJ = LJ * SJZ;  // per current component
     constexpr int C = lane_classes<R>();
     constexpr int CJ = 16;  // classes of the FP64 current tile
-    static_assert(NT % C == 0 && NT % CJ == 0, "slots of one lane keep their class");
+    static_assert(NT % 256 == 0 && NT <= 65536 && kRowMax == 128, "chunk layout");
     static_assert(LF == 12 && LJ == 14 && fplane0(5) + 12 == kFieldPlanes3, "layout of the 3D tile");
-    __shared__ R sf[kFieldPlanes3 * SFZ];
+    __shared__ R sf[kFieldPlanes3 * kFieldPlane3];
     __shared__ LdsJ<R, 3 * NJ> sj;
-    __shared__ unsigned int qd_n[C];
+    __shared__ uint16_t cperm[NT];         // chunk order: lane -> slot offset in the chunk
+    __shared__ uint16_t rstart[kRowMax];   // first chunk position of each class row
+    __shared__ uint32_t rmask[kRowMax];    // classes present in each row
+    __shared__ unsigned int ccnt[C];       // particles of each class in the chunk
+    __shared__ unsigned int c_rows, c_tail;
     __shared__ unsigned int qc_n[4 * CJ];  // crossing map: 4 sections (axis 0, 1, 2, several) x CJ classes
     __shared__ unsigned int qc_total, qc_unmapped;
-    __shared__ unsigned int qo_n;  // particles of pass 1 not in the class queue
-    __shared__ unsigned int n_fallback;
+    __shared__ unsigned int qo_n;  // migrants whose bucket was full
+    __shared__ unsigned int n_migrant;
 
     const int tile = xcd_tile(blockIdx.x, g.ntiles);
     const int tx = tile % g.nt[0];
     const int ty = (tile / g.nt[0]) % g.nt[1];
     const int tz = tile / (g.nt[0] * g.nt[1]);
     const int T0[3] = {tx * T, ty * T, tz * T};
-    const int64_t N = g.ncell;
-    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const bool small = nx < LJ || ny < LJ || nz < LJ;
-    auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
+    const bool small = g.n[0] < LJ || g.n[1] < LJ || g.n[2] < LJ;
 
-    // 1. stage E^n and B^n (B^n from bfield) into LDS, with SK loads of a thread in flight before
-    //    their stores (one load at a time would wait out the memory latency
-    //    once per value)
-    {
-        constexpr int NV = kFieldPlanes3 * LF * LF;
-        constexpr int SK = 7;
-        for (int e0 = threadIdx.x; e0 < NV; e0 += SK * NT) {
-            double v[SK];
-            int li[SK];
-#pragma unroll
-            for (int u = 0; u < SK; ++u) {
-                const int e = e0 + u * NT;
-                li[u] = -1;
-                if (e < NV) {
-                    const int pl = e / (LF * LF);
-                    const int rr = e - pl * (LF * LF);
-                    const int ly = rr / LF;
-                    const int lx = rr - ly * LF;
-                    const int comp = pl < 12 ? 0 : (pl < 24 ? 1 : (pl < 35 ? 2 : (pl < 46 ? 3 : (pl < 57 ? 4 : 5))));
-                    const int lz = pl - fplane0(comp) + fnodez(comp);
-                    const int gx = wr(T0[0] - 1 - M + lx, nx);
-                    const int gy = wr(T0[1] - 1 - M + ly, ny);
-                    const int gz = wr(T0[2] - 1 - M + lz, nz);
-                    v[u] = (comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[((int64_t)gz * ny + gy) * nx + gx];
-                    li[u] = pl * SFZ + ly * SFY + lx;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < SK; ++u)
-                if (li[u] >= 0) sf[li[u]] = (R)v[u];
-        }
-    }
-    // 2. clear the LDS current tile and the queue counters
+    // 1. stage E^n and B^n (B^n from bfield) into LDS
+    stage_fields3<R, NT>(g, T0, fields, bfield, sf, small);
+    // 2. clear the LDS current tile, the class counts and the queue counters
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
-    if (threadIdx.x < C) qd_n[threadIdx.x] = 0;
+    if (threadIdx.x < C) ccnt[threadIdx.x] = 0;
     if (threadIdx.x < 4 * CJ) qc_n[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
-        n_fallback = 0;
         qc_total = 0;
         qc_unmapped = 0;
         qo_n = 0;
+        n_migrant = 0;
     }
     __syncthreads();
 
-    const R c = (R)g.c;
-    const R c2 = c * c;
-    const R qmdt2 = (R)(0.5 * a.qm * g.dt);
-    const R cfl[3] = {(R)g.cfl[0], (R)g.cfl[1], (R)g.cfl[2]};
-    const R bext[3] = {(R)g.bext[0], (R)g.bext[1], (R)g.bext[2]};
     const int64_t begin = a.tile_start[tile], end = a.tile_start[tile + 1];
     const int nt = (int)(end - begin);
-    const unsigned capd = (unsigned)(nt / C), capc = (unsigned)(nt / (4 * CJ));
-    uint32_t* qdisp = (uint32_t*)a.qdisp + begin;
-    uint32_t* qdisp2 = (uint32_t*)a.qdisp2 + begin;
+    const unsigned capc = (unsigned)(nt / (4 * CJ));
     uint32_t* qmap = (uint32_t*)a.qmap + begin;
     uint32_t* qother = (uint32_t*)a.qother + begin;
-    unsigned int my_fallback = 0;
+    unsigned my_migrant = 0;
 
-    // position of a cell relative to the tile, periodic-corrected; inside the
-    // tile region if within M cells of the tile
-    auto relative = [&](const int i0[3], int rel[3]) {
-        bool in = true;
-        for (int ax = 0; ax < 3; ++ax) {
-            int r = i0[ax] - T0[ax];
-            const int n = g.n[ax];
-            if (r > n / 2) r -= n;
-            if (r < -(n / 2)) r += n;
-            rel[ax] = r;
-            in = in && (r >= -M) && (r <= T - 1 + M);
-        }
-        return in;
-    };
-
-    // 3. pass 1: classify every particle, with the cell loads of PU slots of a
-    //    thread in flight at once, into the class queue -- or, outside the tile
-    //    region or with its column full, into the list of the others
-    {
-        constexpr int PU = 4;
-        for (int b0 = threadIdx.x; b0 < nt; b0 += PU * NT) {
-            int ci[PU][3];
-#pragma unroll
-            for (int u = 0; u < PU; ++u)
-                if (b0 + u * NT < nt) PosIO<R, 3>::cell(a, begin + b0 + u * NT, ci[u]);
-#pragma unroll
-            for (int u = 0; u < PU; ++u) {
-                const int sl = b0 + u * NT;
-                if (sl >= nt) continue;
-                int rel[3];
-                bool queued = false;
-                if (relative(ci[u], rel)) {
-                    const int cls = cell_class3(rel[0], rel[1], rel[2], C);
-                    const unsigned r = atomicAdd(&qd_n[cls], 1u);
-                    if (r < 2 * capd) {
-                        if (r < capd) qdisp[cls + C * r] = (uint32_t)sl;
-                        else qdisp2[cls + C * (r - capd)] = (uint32_t)sl;
-                        queued = true;
-                    }
-                }
-                if (!queued) qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
-            }
-        }
-        __syncthreads();
-    }
-
-    // 4. pass 2: the class queue row by row, then the others
-    {
-        unsigned rows = 0;
-        for (int k = 0; k < C; ++k) rows = max(rows, min(qd_n[k], 2 * capd));
-        const int nclass = (int)rows * C;
-        const int nslot = nclass + (int)qo_n;
-        // slot offset of the particle at queue position q, or -1 for a hole
-        auto entry = [&](int q) -> int {
-            if (q >= nslot) return -1;
-            if (q < nclass) {
-                const unsigned row = (unsigned)(q / C);
-                if (row >= min(qd_n[q & (C - 1)], 2 * capd)) return -1;
-                return (int)(row < capd ? qdisp[q] : qdisp2[q - C * (int)capd]);
-            }
-            return (int)qother[q - nclass];
-        };
-        int next = entry(threadIdx.x);  // read one round ahead
-        for (int sl = threadIdx.x; sl < nslot; sl += NT) {
-            const int off = next;
-            next = entry(sl + NT);
-            if (off < 0) continue;
-            const int64_t p = begin + off;
-            int i0[3];
-            R d0[3];
-            PosIO<R, 3>::load(a, p, i0, d0);
+    // 3. the chunks
+    int ci[3] = {0, 0, 0};
+    if ((int)threadIdx.x < nt) PosIO<R, 3>::cell(a, begin + threadIdx.x, ci);
+    for (int cb = 0; cb < nt; cb += NT) {
+        const int sl = cb + (int)threadIdx.x;
+        // (a) classify
+        int cls = 0;
+        unsigned rk = 0;
+        bool in = false;
+        if (sl < nt) {
             int rel[3];
-            const bool inside = relative(i0, rel);
-
-            R w[3];
-            for (int ax = 0; ax < 3; ++ax) w[ax] = ((const R*)a.mom[ax])[p];
-            const R qp = (R)a.q * ((const R*)a.weight)[p];
-            Axis<R> ax0[3];
-            for (int ax = 0; ax < 3; ++ax) ax0[ax] = form_factor<R>(d0[ax]);
-
-            R E[3], B[3];
-            if (inside) {
-                const int base = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SFY + (rel[2] + 1 + M) * SFZ;
-                auto F = [&](int comp, int da, int db, int dc) -> R {
-                    return sf[(fplane0(comp) - fnodez(comp)) * SFZ + base + da + db * SFY + dc * SFZ];
-                };
-                gather3<R>(ax0, F, E, B);
+            in = relative3(g, T0, ci, rel);
+            if (in) {
+                cls = cell_class3(rel[0], rel[1], rel[2], C);
+                rk = atomicAdd(&ccnt[cls], 1u);
             } else {
-                ++my_fallback;
-                int xi[3], yj[3];
-                int64_t zk[3];
-                for (int o = 0; o < 3; ++o) {
-                    xi[o] = wrapi(i0[0] + o - 1, nx);
-                    yj[o] = wrapi(i0[1] + o - 1, ny) * nx;
-                    zk[o] = (int64_t)wrapi(i0[2] + o - 1, nz) * nx * ny;
-                }
-                auto F = [&](int comp, int da, int db, int dc) -> R {
-                    return (R)(comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[zk[dc + 1] + yj[db + 1] + xi[da + 1]];
-                };
-                gather3<R>(ax0, F, E, B);
-            }
-            for (int ax = 0; ax < 3; ++ax) B[ax] += bext[ax];
-
-            push<R>(qmdt2, c2, E, B, w);
-            for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
-
-            const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
-            R disp[3];
-            for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * cfl[ax];
-            R d1[3];
-            int delta[3] = {0, 0, 0};
-            PosIO<R, 3>::move(a, p, g, i0, d0, disp, d1, delta, true);
-
-            R jfac[3];
-            for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
-            int s[3];
-            for (int ax = 0; ax < 3; ++ax) s[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
-            // a crossing particle inside the tile region is queued: its entry
-            // densely, in arrival order, and its place in the class map
-            const bool still = (delta[0] | delta[1] | delta[2]) == 0;
-            const bool enq = inside && !still;
-            const unsigned long long mask = __ballot(enq);
-            if (mask) {
-                const int lane = threadIdx.x & 63;
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned int qbase = 0;
-                if (lane == leader) qbase = atomicAdd(&qc_total, (unsigned int)__popcll(mask));
-                qbase = __shfl(qbase, leader, 64);
-                if (enq) {
-                    const unsigned e = qbase + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-                    for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
-                    int64_t word = p - begin;
-                    for (int ax = 0; ax < 3; ++ax) {
-                        word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
-                        word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
-                    }
-                    // map section: the crossing axis if there is one, 3 if several
-                    const int nax = (delta[0] != 0) + (delta[1] != 0) + (delta[2] != 0);
-                    const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
-                    const int jw = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
-                    const int col = sec * CJ + (jw & (CJ - 1));
-                    const unsigned r = atomicAdd(&qc_n[col], 1u);
-                    if (r < capc) {
-                        qmap[col + 4 * CJ * r] = e;
-                    } else {
-                        word |= kUnmapped;
-                        atomicAdd(&qc_unmapped, 1u);
-                    }
-                    a.qword[begin + e] = word;
+                const int dt = tile_of3(g, ci);
+                const unsigned r = atomicAdd(&a.mig_n[dt], 1u);
+                if (r < a.mig_cap) {
+                    a.mig[(int64_t)dt * a.mig_cap + r] = (uint32_t)(begin + sl);
+                    ++my_migrant;
+                } else {
+                    qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
                 }
             }
-            if (inside) {
-                if (still) {
-                    R s1[3][3], s0[3][3];
-                    for (int ax = 0; ax < 3; ++ax) {
-                        cell_weights<R>(d1[ax], s1[ax]);
-                        for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
-                    }
-                    const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
-                    auto S = [&](int comp, int ix, int iy, int iz, R v) {
-                        sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
-                    };
-                    deposit3_still<R>(s0, s1, jfac, S);
-                }
-                continue;
-            }
-            // outside the tile region: global atomics
-            R dm[3][4], dp[3][4];
-            for (int ax = 0; ax < 3; ++ax) {
-                R s1[3];
-                cell_weights<R>(d1[ax], s1);
-                window<R>(ax0[ax].s, s1, delta[ax], dm[ax], dp[ax]);
-            }
-            int xi[4], yj[4];
-            int64_t zk[4];
-            for (int o = 0; o < 4; ++o) {
-                xi[o] = wrapi(T0[0] + s[0] + o, nx);
-                yj[o] = wrapi(T0[1] + s[1] + o, ny) * nx;
-                zk[o] = (int64_t)wrapi(T0[2] + s[2] + o, nz) * nx * ny;
-            }
-            auto S = [&](int comp, int ix, int iy, int iz, R v) {
-                global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
-            };
-            deposit3<R>(dm, dp, jfac, S);
         }
         __syncthreads();
+        // (b) class rows: row r holds the rank-r particle of each class that has one
+        if (threadIdx.x < 64) {
+            const int lane = (int)threadIdx.x;
+            uint32_t m0 = 0, m1 = 0;
+            for (int k = 0; k < C; ++k) {
+                const unsigned n = ccnt[k];
+                m0 |= (n > (unsigned)lane ? 1u : 0u) << k;
+                m1 |= (n > (unsigned)(lane + 64) ? 1u : 0u) << k;
+            }
+            const unsigned c0 = (unsigned)__popc(m0), c1 = (unsigned)__popc(m1);
+            unsigned s0 = c0, s1 = c1;
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned t0 = __shfl_up(s0, o, 64);
+                const unsigned t1 = __shfl_up(s1, o, 64);
+                if (lane >= o) {
+                    s0 += t0;
+                    s1 += t1;
+                }
+            }
+            const unsigned tot0 = __shfl(s0, 63, 64);
+            rstart[lane] = (uint16_t)(s0 - c0);
+            rstart[lane + 64] = (uint16_t)(tot0 + s1 - c1);
+            rmask[lane] = m0;
+            rmask[lane + 64] = m1;
+            if (lane == 63) {
+                c_rows = tot0 + s1;
+                c_tail = 0;
+            }
+        }
+        __syncthreads();
+        // (c) chunk order
+        if (in) {
+            const unsigned pos = rk < (unsigned)kRowMax
+                                     ? (unsigned)rstart[rk] + (unsigned)__popc(rmask[rk] & ((1u << cls) - 1u))
+                                     : c_rows + atomicAdd(&c_tail, 1u);
+            cperm[pos] = (uint16_t)threadIdx.x;
+        }
+        if (threadIdx.x < C) ccnt[threadIdx.x] = 0;
+        __syncthreads();
+        const int ninside = (int)(c_rows + c_tail);
+        // the next chunk's cells load while this chunk is advanced
+        if (sl + NT < nt) PosIO<R, 3>::cell(a, begin + sl + NT, ci);
+        if ((int)threadIdx.x >= ninside) continue;
+        // (d) advance
+        const int64_t p = begin + cb + cperm[threadIdx.x];
+        int i0[3];
+        R d0[3];
+        PosIO<R, 3>::load(a, p, i0, d0);
+        int rel[3];
+        relative3(g, T0, i0, rel);
+        Axis<R> ax0[3];
+        R d1[3], qp;
+        int delta[3];
+        advance_lds3<R>(g, a, sf, p, i0, d0, rel, ax0, d1, delta, qp);
+        R jfac[3];
+        for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+        const bool still = (delta[0] | delta[1] | delta[2]) == 0;
+        if (still) {
+            R s1[3][3], s0[3][3];
+            for (int ax = 0; ax < 3; ++ax) {
+                cell_weights<R>(d1[ax], s1[ax]);
+                for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
+            }
+            const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
+            auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
+            };
+            deposit3_still<R>(s0, s1, jfac, S);
+        }
+        // a crossing particle is queued: its entry densely, in arrival order,
+        // and its place in the class map
+        const unsigned long long mask = __ballot(!still);
+        if (mask) {
+            const int lane = threadIdx.x & 63;
+            const int leader = __ffsll((long long)mask) - 1;
+            unsigned int qbase = 0;
+            if (lane == leader) qbase = atomicAdd(&qc_total, (unsigned int)__popcll(mask));
+            qbase = __shfl(qbase, leader, 64);
+            if (!still) {
+                const unsigned e = qbase + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+                for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
+                int64_t word = p - begin;
+                for (int ax = 0; ax < 3; ++ax) {
+                    word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
+                    word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
+                }
+                // map section: the crossing axis if there is one, 3 if several
+                const int nax = (delta[0] != 0) + (delta[1] != 0) + (delta[2] != 0);
+                const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
+                int s[3];
+                for (int ax = 0; ax < 3; ++ax) s[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
+                const int jw = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
+                const int col = sec * CJ + (jw & (CJ - 1));
+                const unsigned r = atomicAdd(&qc_n[col], 1u);
+                if (r < capc) {
+                    qmap[col + 4 * CJ * r] = e;
+                } else {
+                    word |= kUnmapped;
+                    atomicAdd(&qc_unmapped, 1u);
+                }
+                a.qword[begin + e] = word;
+            }
+        }
     }
-    if (my_fallback) atomicAdd(&n_fallback, my_fallback);
+    if (my_migrant) atomicAdd(&n_migrant, my_migrant);
+    __syncthreads();
 
-    // 5. pass 3: the crossing queue -- the class map's four sections (a
-    //    particle that crossed along one axis deposits its 75 non-zero
-    //    contributions, one that crossed along several its full window), then,
+    // 4. migrants whose bucket was full: global memory
+    for (int q = threadIdx.x; q < (int)qo_n; q += NT)
+        advance_global3<R>(g, a, begin + qother[q], fields, bfield, Jg);
+
+    // 5. pass 3: the crossing queue -- the class map's four sections, then,
     //    only if a map column was full, the unmapped entries in arrival order
     {
         auto cross = [&](int64_t e, int sec) {
@@ -593,7 +702,6 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         // wave runs a single deposit variant
         {
             constexpr int NG = NT / 64 / 4;  // waves per group
-            static_assert(NT % 256 == 0, "four equal groups of waves");
             const int wv = threadIdx.x >> 6;
             const int sec = wv & 3;
             const int gt = (wv >> 2) * 64 + (threadIdx.x & 63);
@@ -616,24 +724,95 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         __syncthreads();
     }
 
-    // 6. flush the LDS current tile (the plane padding is never written)
-    for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
-        const double v = sj.get(e);
-        if (v == 0.0) continue;
-        const int comp = e / NJ;
-        const int r = e - comp * NJ;
-        const int lz = r / SJZ;
-        const int rr = r - lz * SJZ;
-        const int ly = rr / LJ;
-        const int lx = rr - ly * LJ;
-        const int gx = wr(T0[0] - 2 - M + lx, nx);
-        const int gy = wr(T0[1] - 2 - M + ly, ny);
-        const int gz = wr(T0[2] - 2 - M + lz, nz);
-        global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
-    }
+    // 6. flush the LDS current tile
+    flush_current3<R, NT>(g, T0, sj, Jg, small);
     if (threadIdx.x == 0 && a.counters) {
-        atomicAdd(&a.counters[1], (unsigned long long)n_fallback);
+        atomicAdd(&a.counters[1], (unsigned long long)qo_n);
         atomicAdd(&a.counters[2], (unsigned long long)(end - begin));
+        atomicAdd(&a.counters[3], (unsigned long long)n_migrant);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Migrants: the particles that the step kernel found outside their sorted
+// tile's region, advanced by the workgroup of the tile that now holds their
+// cell.  A bucket of at least kMigLds particles stages the tile's fields and
+// current in LDS as the step kernel does (every migrant lies inside its new
+// tile, so it always fits); a smaller one takes the global-memory path.  The
+// bucket counter is cleared for the next launch.
+// ---------------------------------------------------------------------------
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_migrants3(GridK g, StepArgs a, const double* __restrict__ fields,
+                                                 const double* __restrict__ bfield, double* __restrict__ Jg)
+{
+    constexpr int T = kTile3, M = kMargin3;
+    constexpr int LJ = T + 4 + 2 * M;
+    constexpr int SJY = LJ, SJZ = kJPlane3;
+    constexpr int NJ = LJ * SJZ;
+    __shared__ R sf[kFieldPlanes3 * kFieldPlane3];
+    __shared__ LdsJ<R, 3 * NJ> sj;
+    __shared__ unsigned int n_global;
+
+    const int tile = xcd_tile(blockIdx.x, g.ntiles);
+    const unsigned cnt = min(a.mig_n[tile], a.mig_cap);
+    if (cnt == 0) return;
+    const uint32_t* bucket = a.mig + (int64_t)tile * a.mig_cap;
+    if (cnt < kMigLds) {
+        for (unsigned q = threadIdx.x; q < cnt; q += NT) advance_global3<R>(g, a, bucket[q], fields, bfield, Jg);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.mig_n[tile] = 0;
+            if (a.counters) atomicAdd(&a.counters[1], (unsigned long long)cnt);
+        }
+        return;
+    }
+    const int tx = tile % g.nt[0];
+    const int ty = (tile / g.nt[0]) % g.nt[1];
+    const int tz = tile / (g.nt[0] * g.nt[1]);
+    const int T0[3] = {tx * T, ty * T, tz * T};
+    const bool small = g.n[0] < LJ || g.n[1] < LJ || g.n[2] < LJ;
+    stage_fields3<R, NT>(g, T0, fields, bfield, sf, small);
+    for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
+    if (threadIdx.x == 0) n_global = 0;
+    __syncthreads();
+    unsigned my_global = 0;
+    for (unsigned q = threadIdx.x; q < cnt; q += NT) {
+        const int64_t p = bucket[q];
+        int i0[3];
+        R d0[3];
+        PosIO<R, 3>::load(a, p, i0, d0);
+        int rel[3];
+        if (!relative3(g, T0, i0, rel)) {  // not a cell of this tile (non-finite input): global memory
+            advance_global3<R>(g, a, p, fields, bfield, Jg);
+            ++my_global;
+            continue;
+        }
+        Axis<R> ax0[3];
+        R d1[3], qp;
+        int delta[3];
+        advance_lds3<R>(g, a, sf, p, i0, d0, rel, ax0, d1, delta, qp);
+        R jfac[3];
+        for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+        R dm[3][4], dp[3][4];
+        for (int ax = 0; ax < 3; ++ax) {
+            R s1[3];
+            cell_weights<R>(d1[ax], s1);
+            window<R>(ax0[ax].s, s1, delta[ax], dm[ax], dp[ax]);
+        }
+        int s[3];
+        for (int ax = 0; ax < 3; ++ax) s[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
+        const int jb = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
+        auto S = [&](int comp, int ix, int iy, int iz, R v) {
+            sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
+        };
+        deposit3<R>(dm, dp, jfac, S);
+    }
+    if (my_global) atomicAdd(&n_global, my_global);
+    __syncthreads();
+    flush_current3<R, NT>(g, T0, sj, Jg, small);
+    if (threadIdx.x == 0) {
+        a.mig_n[tile] = 0;
+        if (a.counters && n_global) atomicAdd(&a.counters[1], (unsigned long long)n_global);
     }
 }
 
@@ -908,7 +1087,7 @@ __global__ __launch_bounds__(256) void k_rho_raw(GridK g, const double* __restri
 }
 
 template <class R>
-StepArgs step_args(const Species& sp, unsigned long long* counters)
+StepArgs step_args(const Ctx& c, const Species& sp, unsigned long long* counters)
 {
     StepArgs a{};
     for (int ax = 0; ax < 3; ++ax) {
@@ -921,11 +1100,14 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
     a.q = sp.d.q;
     a.qm = sp.d.q / sp.d.m;
     a.counters = counters;
+    // migrant buckets: the species' sort scratch (key .. src, idle between
+    // sorts), an equal share per tile; counters in the workspace
+    a.mig = sp.key;
+    a.mig_cap = (uint32_t)(((size_t)((char*)sp.tile_start - (char*)sp.key) / 4) / (size_t)c.k.ntiles);
+    a.mig_n = c.mig_n;
     for (int ax = 0; ax < 3; ++ax) a.qd0[ax] = sp.alt.pos[ax];
     a.qword = sp.alt.id;
-    a.qdisp = sp.alt.mom[0];
     a.qmap = (void*)sp.alt.weight;
-    a.qdisp2 = sp.alt.mom[1];
     a.qother = sp.alt.mom[2];
     return a;
 }
@@ -933,6 +1115,7 @@ StepArgs step_args(const Species& sp, unsigned long long* counters)
 // Threads per workgroup of each instantiation.
 constexpr int kThreads3 = 768;    // FP64: 3 waves per SIMD, <= 170 VGPRs
 constexpr int kThreads3f = 1024;  // FP32: 4 waves per SIMD
+constexpr int kThreadsMig = 256;  // migrant pass: buckets hold a few hundred particles
 constexpr int kThreads2 = 256;
 constexpr int kMargin2 = 2;
 
@@ -948,18 +1131,24 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
     double* J = c.fields + 6 * c.k.ncell;
     const dim3 grid(c.k.ntiles);
     if (c.g.precision == PIC_FP64) {
-        StepArgs a = step_args<double>(sp, c.counters);
-        if (c.k.dims == 3)
+        StepArgs a = step_args<double>(c, sp, c.counters);
+        if (c.k.dims == 3) {
             hipLaunchKernelGGL((k_particle_step3<double, kThreads3>), grid, dim3(kThreads3), 0, s, c.k, a,
                                c.fields, c.bn, J);
+            hipLaunchKernelGGL((k_migrants3<double, kThreadsMig>), grid, dim3(kThreadsMig), 0, s, c.k, a,
+                               c.fields, c.bn, J);
+        }
         else
             hipLaunchKernelGGL((k_particle_step<double, 2, kTile2, kMargin2, kThreads2>), grid,
                                dim3(kThreads2), 0, s, c.k, a, c.fields, c.bn, J);
     } else {
-        StepArgs a = step_args<float>(sp, c.counters);
-        if (c.k.dims == 3)
+        StepArgs a = step_args<float>(c, sp, c.counters);
+        if (c.k.dims == 3) {
             hipLaunchKernelGGL((k_particle_step3<float, kThreads3f>), grid, dim3(kThreads3f), 0, s, c.k, a,
                                c.fields, c.bn, J);
+            hipLaunchKernelGGL((k_migrants3<float, kThreadsMig>), grid, dim3(kThreadsMig), 0, s, c.k, a,
+                               c.fields, c.bn, J);
+        }
         else
             hipLaunchKernelGGL((k_particle_step<float, 2, kTile2, kMargin2, kThreads2>), grid,
                                dim3(kThreads2), 0, s, c.k, a, c.fields, c.bn, J);

@@ -116,7 +116,8 @@ struct Ctx {
     double* adj = nullptr;      // adjoint scratch (3 planes): lambda_J of a reverse step
     double* avec = nullptr;     // vector potential A^{n-1/2} (3 planes, field form 1 only)
     unsigned long long* counters = nullptr;  // [0] range errors, [1] fallback particles,
-                                             // [2] particles processed
+                                             // [2] particles processed, [3] migrants
+    unsigned int* mig_n = nullptr;  // per-tile migrant bucket counters (3D particle step)
     uint32_t nkeys = 0;
     Species sp[kMaxSpecies];
     int nsp = 0;

@@ -764,13 +764,17 @@ struct StepArgs {
     // start offsets qd0[a] and one packed word per entry
     void* qd0[3];
     int64_t* qword;
-    // 3D: class queue of the tile's particles (32-bit slot offsets), in the
-    // spare copy's first two momentum arrays, and the class map of the
-    // crossing queue (32-bit entry offsets), in its weight array
-    void* qdisp;
+    // 3D: the class map of the crossing queue (32-bit entry offsets), in the
+    // spare copy's weight array, and the migrants whose bucket was full
+    // (32-bit slot offsets), in its third momentum array
     void* qmap;
-    void* qdisp2;
-    void* qother;  // the particles pass 1 could not class-queue, in the third momentum array
+    void* qother;
+    // 3D migrant buckets: mig_cap particle indices per tile at mig + tile *
+    // mig_cap, filled through the per-tile counters mig_n (zero between
+    // launches: the migrant kernel clears the counter it reads)
+    uint32_t* mig;
+    unsigned int* mig_n;
+    uint32_t mig_cap;
 };
 
 __device__ __forceinline__ int wrapi(int v, int n)

@@ -226,6 +226,9 @@ class Sim:
     def fallback_fraction(self) -> float:
         return float(self.lib.pic_last_fallback_fraction(self.ctx, _stream()))
 
+    def migrant_fraction(self) -> float:
+        return float(self.lib.pic_last_migrant_fraction(self.ctx, _stream()))
+
     # -- checkpoint ------------------------------------------------------
     def state_dict(self) -> dict:
         """Everything needed to continue the run: byte copies of the caller

@@ -42,6 +42,7 @@ class Workload:
     ions_mobile: bool = False
     ion_mass: float = 100.0
     ion_w_th: float = 0.005
+    source: tuple = None   # (plane, amplitude, omega, ramp time): +x E^y plane wave
     seed: int = BASE_SEED
 
     @property
@@ -57,6 +58,11 @@ class Workload:
     @property
     def n_electrons(self) -> int:
         return self.ppc * self.occupied_cells
+
+    @property
+    def n_particles(self) -> int:
+        """Mobile particles: the electrons, plus as many ions when they move."""
+        return self.n_electrons * (2 if self.ions_mobile else 1)
 
     @property
     def weight(self) -> float:
@@ -76,6 +82,7 @@ WORKLOADS = {
                                sort_every=10, seed=BASE_SEED + 2),
     "3d_128cube_slab": Workload("3d_128cube_slab", 128, 128, 128, 3, 0.45, 16, (0.01,) * 3,
                                 0.1 * 2 * math.pi / 20.0, 200, sort_every=10, slab=(32, 96),
+                                source=(8, 2 * math.pi / 20.0, 2 * math.pi / 20.0, 20.0),
                                 seed=BASE_SEED + 3),
     "2d3v_256sq_beams": Workload("2d3v_256sq_beams", 256, 256, 1, 2, 0.5, 16, (0.02,) * 3, 0.02,
                                  200, drift=0.2, bext=(0.0, 0.0, 0.02), sort_every=20,
