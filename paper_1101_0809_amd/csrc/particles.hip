@@ -372,6 +372,41 @@ __device__ __forceinline__ int tile_of3(const GridK& g, const int i[3])
     return (t[2] * g.nt[1] + t[1]) * g.nt[0] + t[0];
 }
 
+// Code (ox+1) + 3(oy+1) + 9(oz+1) of the tile that holds cell i, at tile offset
+// (ox, oy, oz) in {-1, 0, 1}^3 from tile (tx, ty, tz) with periodic wrap, or -1
+// if it is further away.
+__device__ __forceinline__ int neighbour_code3(const GridK& g, int tx, int ty, int tz, const int i[3])
+{
+    int c[3];
+    for (int ax = 0; ax < 3; ++ax) c[ax] = i[ax] < 0 ? 0 : (i[ax] >= g.n[ax] ? g.n[ax] - 1 : i[ax]);
+    const int t[3] = {tx, ty, tz};
+    int code = 0, mul = 1;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int nt = g.nt[ax];
+        int o = c[ax] / kTile3 - t[ax];
+        if (o > nt / 2) o -= nt;
+        if (o < -(nt / 2)) o += nt;
+        if (o < -1 || o > 1) return -1;
+        code += (o + 1) * mul;
+        mul *= 3;
+    }
+    return code;
+}
+
+// The tile at neighbour code `code` of tile (tx, ty, tz).
+__device__ __forceinline__ int neighbour_tile3(const GridK& g, int tx, int ty, int tz, int code)
+{
+    const int t[3] = {tx, ty, tz};
+    int d[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const int nt = g.nt[ax];
+        int v = t[ax] + code % 3 - 1;
+        code /= 3;
+        d[ax] = v < 0 ? v + nt : (v >= nt ? v - nt : v);
+    }
+    return (d[2] * g.nt[1] + d[1]) * g.nt[0] + d[0];
+}
+
 // Gather from the LDS field tile, push and move one particle whose cell is at
 // rel (inside the tile region); stores w and the new position.  Returns the
 // start form factors, the end offsets, the cell shift and the macro charge.
@@ -487,6 +522,8 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     __shared__ uint32_t rmask[kRowMax];    // classes present in each row
     __shared__ unsigned int ccnt[C];       // particles of each class in the chunk
     __shared__ unsigned int c_rows, c_tail;
+    __shared__ unsigned int mg_n[27];      // migrants of the chunk per neighbour tile
+    __shared__ unsigned int mg_base[27];   // their first bucket slot
     __shared__ unsigned int qc_n[4 * CJ];  // crossing map: 4 sections (axis 0, 1, 2, several) x CJ classes
     __shared__ unsigned int qc_total, qc_unmapped;
     __shared__ unsigned int qo_n;  // migrants whose bucket was full
@@ -504,6 +541,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     // 2. clear the LDS current tile, the class counts and the queue counters
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
     if (threadIdx.x < C) ccnt[threadIdx.x] = 0;
+    if (threadIdx.x < 27) mg_n[threadIdx.x] = 0;
     if (threadIdx.x < 4 * CJ) qc_n[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         qc_total = 0;
@@ -526,7 +564,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     for (int cb = 0; cb < nt; cb += NT) {
         const int sl = cb + (int)threadIdx.x;
         // (a) classify
-        int cls = 0;
+        int cls = 0, mcode = -1;
         unsigned rk = 0;
         bool in = false;
         if (sl < nt) {
@@ -536,17 +574,33 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
                 cls = cell_class3(rel[0], rel[1], rel[2], C);
                 rk = atomicAdd(&ccnt[cls], 1u);
             } else {
-                const int dt = tile_of3(g, ci);
-                const unsigned r = atomicAdd(&a.mig_n[dt], 1u);
-                if (r < a.mig_cap) {
-                    a.mig[(int64_t)dt * a.mig_cap + r] = (uint32_t)(begin + sl);
-                    ++my_migrant;
+                // a neighbour tile takes a rank in the chunk's count for it;
+                // a tile further away reserves its bucket slot at once
+                mcode = neighbour_code3(g, tx, ty, tz, ci);
+                if (mcode >= 0) {
+                    rk = atomicAdd(&mg_n[mcode], 1u);
                 } else {
-                    qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
+                    const int dt = tile_of3(g, ci);
+                    const unsigned r = atomicAdd(&a.mig_n[dt], 1u);
+                    if (r < a.mig_cap) {
+                        a.mig[(int64_t)dt * a.mig_cap + r] = (uint32_t)(begin + sl);
+                        ++my_migrant;
+                    } else {
+                        qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
+                    }
                 }
             }
         }
         __syncthreads();
+        // (b') one bucket reservation per neighbour tile that receives migrants
+        if (threadIdx.x >= 64 && threadIdx.x < 64 + 27) {
+            const int code = (int)threadIdx.x - 64;
+            const unsigned m = mg_n[code];
+            if (m) {
+                mg_n[code] = 0;
+                mg_base[code] = atomicAdd(&a.mig_n[neighbour_tile3(g, tx, ty, tz, code)], m);
+            }
+        }
         // (b) class rows: row r holds the rank-r particle of each class that has one
         if (threadIdx.x < 64) {
             const int lane = (int)threadIdx.x;
@@ -577,7 +631,16 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
             }
         }
         __syncthreads();
-        // (c) chunk order
+        // (c) chunk order; migrants take their bucket slots
+        if (mcode >= 0) {
+            const unsigned r = mg_base[mcode] + rk;
+            if (r < a.mig_cap) {
+                a.mig[(int64_t)neighbour_tile3(g, tx, ty, tz, mcode) * a.mig_cap + r] = (uint32_t)(begin + sl);
+                ++my_migrant;
+            } else {
+                qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
+            }
+        }
         if (in) {
             const unsigned pos = rk < (unsigned)kRowMax
                                      ? (unsigned)rstart[rk] + (unsigned)__popc(rmask[rk] & ((1u << cls) - 1u))
@@ -1115,7 +1178,8 @@ StepArgs step_args(const Ctx& c, const Species& sp, unsigned long long* counters
 // Threads per workgroup of each instantiation.
 constexpr int kThreads3 = 768;    // FP64: 3 waves per SIMD, <= 170 VGPRs
 constexpr int kThreads3f = 1024;  // FP32: 4 waves per SIMD
-constexpr int kThreadsMig = 256;  // migrant pass: buckets hold a few hundred particles
+constexpr int kThreadsMig = 768;   // migrant pass, FP64 (as many waves as the step kernel)
+constexpr int kThreadsMigf = 1024; // migrant pass, FP32
 constexpr int kThreads2 = 256;
 constexpr int kMargin2 = 2;
 
@@ -1146,7 +1210,7 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
         if (c.k.dims == 3) {
             hipLaunchKernelGGL((k_particle_step3<float, kThreads3f>), grid, dim3(kThreads3f), 0, s, c.k, a,
                                c.fields, c.bn, J);
-            hipLaunchKernelGGL((k_migrants3<float, kThreadsMig>), grid, dim3(kThreadsMig), 0, s, c.k, a,
+            hipLaunchKernelGGL((k_migrants3<float, kThreadsMigf>), grid, dim3(kThreadsMigf), 0, s, c.k, a,
                                c.fields, c.bn, J);
         }
         else

@@ -283,6 +283,10 @@ def test_gyration_on_gpu():
     uy = ((a @ a) * (c[0] - b[0]) + (b @ b) * (a[0] - c[0]) + (c @ c) * (b[0] - a[0])) / d
     r = np.hypot(pts[:, 0] - ux, pts[:, 1] - uy)
     assert np.max(np.abs(r - R)) < 1e-11
+    # Eq. (1): dw/dt = (q/m)(u/c x B); with q < 0 and B along +z the electron
+    # turns counter-clockwise seen from +z, theta per step
+    ang = np.unwrap(np.arctan2(pts[:, 1] - uy, pts[:, 0] - ux))
+    assert np.allclose(np.diff(ang), theta, atol=1e-11)
 
 
 def test_load_rejects_out_of_range():
@@ -455,6 +459,15 @@ def _sampled_step_check(sim, g, qm, dims, n_axis, tol, rng_seed=99, nsample=2000
             assert abs(_wrapdiff(xn[a], x1[a, k], n_axis[a])) <= tol * n_axis[a], (k, a)
 
 
+def test_64cube_fullsize_elementwise_fp64():
+    """The 64^3 x 8 workload (2,097,152 electrons, co-located ions) at full
+    size in FP64: 12 steps across the sort at step 10, then all six field
+    planes and every particle (by id) against the oracle's 12 steps."""
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(steps=12)
+    sim, st, _ = _run_pair(wl, "fp64", wl.steps)
+    _compare(sim, st, wl, 1e-12, 1e-12, 1e-12)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_256sq_beams_fullsize_sampled(precision):
     """The 256^2 2D3V two-stream workload (1,048,576 electrons, drifts +-0.2 c,
@@ -499,8 +512,9 @@ def test_256cube_weibel_fullsize_sampled():
     assert sim.count(se) == n and sim.count(si) == n
     sim.step(2)
     g = oracle.Grid(256, 256, 256, wl.dt)
-    # the electron step: sampled check (one more step is taken inside)
+    # sampled checks, electrons then ions (one more step is taken inside each)
     _sampled_step_check(sim, g, -1.0, 3, (256, 256, 256), 2e-6, nsample=800, species=se)
+    _sampled_step_check(sim, g, 1.0 / wl.ion_mass, 3, (256, 256, 256), 2e-6, nsample=800, species=si)
     d = sim.diagnostics()
     assert d["gauss_rel"] <= 1e-6, d
     assert d["nonfinite"] == 0 and d["n_particles"] == 2 * n
@@ -615,6 +629,62 @@ def test_128cube_slab_laser_fullsize_sampled(precision):
     assert d["gauss_rel"] <= (1e-12 if precision == "fp64" else 1e-6), d
     assert d["nonfinite"] == 0
     assert d["field_e"] > 0.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_residual_diagnostics_match_oracle(precision):
+    """pic_diagnostics' charge and field checks against the oracle's own
+    definitions -- the Gauss residual R = div_h E - 4 pi rho (Eq. chargelaw)
+    with rho of Eq. rho, div_h B at the nodes, the total charge -- on a state
+    where every one of them is far from zero: random initial E and B (so R^0
+    and div B are non-zero), hot electrons and an immobile background placed
+    apart from them (net charge), a ragged grid of several tiles.  After the
+    steps E is overwritten in the GPU's field buffer with a perturbed copy,
+    so that R^n - R^0 is non-zero as well.  The oracle evaluates everything
+    from the GPU's fields and stored particles; both sides are FP64."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(777))
+    nx, ny, nz, dt = 13, 10, 11, 0.45
+    F0 = np.zeros((9, nz, ny, nx))
+    F0[:6] = rng.normal(0.0, 1e-3, (6, nz, ny, nx))
+    ne, ni = 3000, 2000
+    xe = np.stack([rng.uniform(0, nn, ne) for nn in (nx, ny, nz)])
+    we = rng.normal(0.0, 0.3, (3, ne))
+    wte = np.full(ne, 0.01)
+    xi = np.stack([rng.uniform(0, nn, ni) for nn in (nx, ny, nz)])
+    wti = np.full(ni, 0.013)
+    sim = _sim(nx=nx, ny=ny, nz=nz, dt=dt, dims=3, precision=precision, sort_every=4, fields=F0)
+    se = sim.add_species(-1.0, 1.0, ne)
+    sim.load(se, xe, we, wte)
+    si = sim.add_species(1.0, 100.0, 0, mobile=False)
+    sim.load(si, xi, np.zeros_like(xi), wti)
+    x0, _, w0, _ = sim.particles(se)            # the stored start state (FP32 mode: rounded)
+    sim.step(6)
+    F = sim.fields_numpy()
+    F[0:3] += rng.normal(0.0, 1e-4, (3, nz, ny, nx))
+    sim.fields[0:3].copy_(torch.from_numpy(np.ascontiguousarray(F[0:3])).to(sim.device))
+    d = sim.diagnostics()
+    x1, _, w1, _ = sim.particles(se)
+    g = oracle.Grid(nx, ny, nz, dt)
+    wti_stored = wti.astype(np.float32).astype(np.float64) if precision == "fp32c" else wti
+    ions = oracle.Species(xi, np.zeros_like(xi), wti_stored, q=1.0, m=100.0, mobile=False)
+    rho_bg = oracle.State(g, [ions]).rho()
+    rho_m0 = oracle.State(g, [oracle.Species(x0, np.zeros_like(x0), w0, q=-1.0)]).rho()
+    rho_m1 = oracle.State(g, [oracle.Species(x1, np.zeros_like(x1), w1, q=-1.0)]).rho()
+    R0 = oracle.State(g, [], fields=F0).gauss_residual(rho_m0 + rho_bg)
+    st1 = oracle.State(g, [], fields=F)
+    R1 = st1.gauss_residual(rho_m1 + rho_bg)
+    gauss_abs = np.max(np.abs(R1 - R0))
+    rho_max = np.max(np.abs(4 * np.pi * rho_m1))
+    divb = np.max(np.abs(st1.div_b()))
+    charge = np.sum(rho_m1 + rho_bg)
+    assert gauss_abs > 1e-4 and divb > 1e-4 and abs(charge) > 1.0   # all far from zero
+    assert d["gauss_abs"] == pytest.approx(gauss_abs, rel=1e-12)
+    assert d["rho_mobile_max"] == pytest.approx(rho_max, rel=1e-12)
+    assert d["gauss_rel"] == pytest.approx(gauss_abs / rho_max, rel=1e-12)
+    assert d["divb_max"] == pytest.approx(divb, rel=1e-12)
+    assert d["charge"] == pytest.approx(charge, rel=1e-12)
+    assert d["nonfinite"] == 0 and d["n_particles"] == ne
 
 
 @pytest.mark.parametrize("dims", [3, 2])

@@ -286,6 +286,21 @@ def test_push_pure_electric_kick():
         assert np.allclose(w1, w - 0.25 * E, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("qm", [-1.0, 1.0])
+def test_push_rotation_sense(qm):
+    """Eq. (1): dw/dt = (q/m)(E + u/c x B).  In a pure magnetic field along +z
+    the Appendix's rotation turns w by theta = 2 atan(|q/m| (dt/2) B / gamma)
+    about +z when q < 0 (counter-clockwise) and about -z when q > 0: the
+    exact image of w = (w0, 0, 0) is w0 (cos theta, -sign(q) sin theta, 0).
+    Swapping the order of a cross product in the push reverses the turn."""
+    dt, c, b, w0 = 0.3, 1.0, 0.7, 0.6
+    gam = math.sqrt(1.0 + w0 * w0)
+    theta = 2.0 * math.atan(abs(qm) * 0.5 * dt * b / gam)
+    w1 = oracle.push(qm, dt, c, np.zeros(3), np.array([0.0, 0.0, b]), np.array([w0, 0.0, 0.0]))
+    ref = w0 * np.array([math.cos(theta), -math.copysign(1.0, qm) * math.sin(theta), 0.0])
+    assert np.allclose(w1, ref, rtol=0, atol=1e-15)
+
+
 @pytest.mark.parametrize("order,interp", [(1, 0), (2, 0), (1, 1)])
 def test_gather_partition_of_unity(order, interp):
     """Uniform grid fields are reproduced exactly at any position (Eq. one),
@@ -392,6 +407,39 @@ def test_conventional_interpolation_conserves_charge_but_not_energy():
     assert defects[1] > 30 * defects[0], defects
 
 
+def test_half_step_energy_term_is_half_the_work_of_a_step():
+    """Section 4.1: the particle energy at t^n is K^{n-1/2} plus the half-step
+    term H^n = sum (q dt / 2) u^{n-1/2} . E(x^n).  Over the step that follows,
+    E^n does the work K^{n+1/2} - K^{n-1/2} = sum q dt u^n . E(x^n) (the
+    magnetic rotation does none), so H^n equals half of it up to O(dt^2)
+    terms.  A coherent Langmuir oscillation (Section 5: one electron per cell
+    of doubled charge, all drifting at 0.1 c, co-located ions, 8^3 cells)
+    moves energy between particles and field within each step; the term must
+    follow that exchange in sign and size, and with it the total energy is
+    conserved far better than without it.  A sign error in H fails both."""
+    n, dt = 8, 0.5
+    wl = picgen.Workload("langmuir", n, n, n, 3, dt, 1, (0.0,) * 3, 0.05, 120, seed=31)
+    e = picgen.electrons(wl)
+    e.w[0] += 0.1
+    weight = 2.0 * e.weight
+    st = oracle.State(oracle.Grid(n, n, n, dt),
+                      [oracle.Species(e.x, e.w, weight, q=-1.0, m=1.0),
+                       oracle.Species(e.x, np.zeros_like(e.w), weight, q=1.0, m=100.0, mobile=False)])
+    en = [st.energies()]
+    for _ in range(wl.steps):
+        st.step(1)
+        en.append(st.energies())
+    en = np.array(en)
+    K, H, W = en[:, 0], en[:, 1], en[:, 2] + en[:, 3]
+    half_work = 0.5 * (K[1:] - K[:-1])
+    assert np.max(W) > 0.2 * K[0]   # the oscillation moves a good part of K into the field
+    mismatch = np.sum(np.abs(H[:-1] - half_work)) / np.sum(np.abs(half_work))
+    assert mismatch < 0.05, mismatch
+    with_term = np.max(np.abs(K + H + W - (K + H + W)[0])) / K[0]
+    without = np.max(np.abs(K + W - (K + W)[0])) / K[0]
+    assert with_term < 0.05 * without, (with_term, without)
+
+
 # --------------------------------------------------------------------------
 # Q7  closed-form gyration of a test particle (Section 5, gyration test)
 # --------------------------------------------------------------------------
@@ -427,8 +475,11 @@ def test_gyration_closed_form():
     uy = ((a @ a) * (c[0] - b[0]) + (b @ b) * (a[0] - c[0]) + (c @ c) * (b[0] - a[0])) / d
     r = np.hypot(pts[:, 0] - ux, pts[:, 1] - uy)
     assert np.max(np.abs(r - R)) < 1e-11
+    # Eq. (1): dw/dt = (q/m)(u/c x B).  The electron (q < 0) starts along +x in
+    # B along +z: u x B points along -y, so the force points along +y and the
+    # orbit turns counter-clockwise seen from +z, by +theta per step
     ang = np.unwrap(np.arctan2(pts[:, 1] - uy, pts[:, 0] - ux))
-    assert np.allclose(np.abs(np.diff(ang)), theta, atol=1e-11)
+    assert np.allclose(np.diff(ang), theta, atol=1e-11)
     assert np.all(pts[:, 2] == n / 2)
     assert np.sum(sp.w[:, 0] ** 2) == pytest.approx(gy["w_over_c"] ** 2, rel=1e-14)
 
