@@ -203,6 +203,20 @@ int pic_field_solve(pic_ctx* ctx, int what, void* stream);
 /* Compute pic_diag in FP64 on the GPU.  Synchronizes the stream. */
 int pic_diagnostics(pic_ctx* ctx, pic_diag* out, void* stream);
 
+/* pic_diagnostics for callers that cannot allocate device memory or take a
+ * workspace of their own: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same results and errors as
+ * pic_diagnostics, but its scratch (the mobile charge density, N FP64, and
+ * the reduction partials) lives in a fixed static device array of the
+ * library (20 MiB per GPU, held until the process ends) instead of the
+ * context's workspace; no allocation is made.  Grids of more than about
+ * 2.57 million cells are rejected with PIC_ESIZE.  Every call on one GPU
+ * uses that GPU's array, so calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialized by the caller.  Like
+ * pic_diagnostics it may capture the Gauss reference R^0 into the context
+ * first.  Synchronizes the stream. */
+int pic_diagnostics_static(pic_ctx* ctx, pic_diag* out, void* stream);
+
 /* Adjoint (reverse-mode derivative) of the time step, for gradients of a
  * loss with respect to the initial momenta and the external field (FP64 mode,
  * no plane-wave source; PIC_EINVAL otherwise).  An adjoint field buffer holds

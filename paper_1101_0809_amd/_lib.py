@@ -20,7 +20,8 @@ PIC_AUX = 8192  # source line length (include/pic.h)
 # Every symbol include/pic.h declares (checked by the CPU tests).
 EXPORTS = (
     "pic_query_sizes", "pic_init_grid", "pic_add_species", "pic_load_particles", "pic_step",
-    "pic_deposit_J", "pic_field_solve", "pic_diagnostics", "pic_particle_count",
+    "pic_deposit_J", "pic_field_solve", "pic_diagnostics", "pic_diagnostics_static",
+    "pic_particle_count",
     "pic_get_particles", "pic_sort", "pic_last_fallback_fraction", "pic_last_migrant_fraction",
     "pic_timing_start",
     "pic_timing_stop", "pic_get_host_state", "pic_set_host_state", "pic_destroy",
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
         "pic_deposit_J": (I, [P, P, P, P, I64, P, P]),
         "pic_field_solve": (I, [P, I, P]),
         "pic_diagnostics": (I, [P, ctypes.POINTER(Diag), P]),
+        "pic_diagnostics_static": (I, [P, ctypes.POINTER(Diag), P]),
         "pic_particle_count": (I64, [P, I]),
         "pic_get_particles": (I, [P, I, P, P, P, P, P]),
         "pic_sort": (I, [P, P]),

@@ -15,8 +15,6 @@
 
 namespace pic {
 
-size_t diag_partials_doubles(int nsp);
-
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 namespace {
@@ -648,6 +646,35 @@ int pic_diagnostics(pic_ctx* ctx, pic_diag* out, void* stream)
     hipError_t e = ensure_r0(c, s);
     if (e == hipSuccess) e = launch_diag(c, out, s);
     if (e != hipSuccess) return hip_fail(&c, e, "diagnostics");
+    return PIC_OK;
+}
+
+int pic_diagnostics_static(pic_ctx* ctx, pic_diag* out, void* stream)
+{
+    if (!ctx || !out) return fail(ctx ? &ctx->c : nullptr, PIC_EINVAL, "null argument");
+    Ctx& c = ctx->c;
+    const size_t need = static_scratch_doubles(c) * sizeof(double);
+    if (need > kStaticScratchBytes) {
+        char msg[200];
+        snprintf(msg, sizeof msg,
+                 "pic_diagnostics_static: %lld cells need %zu bytes of static scratch, the maximum is %zu "
+                 "(about %zu cells); use pic_diagnostics",
+                 (long long)c.k.ncell, need, kStaticScratchBytes,
+                 (size_t)(kStaticScratchBytes / sizeof(double)) - diag_partials_doubles(c.nsp) - 32);
+        return fail(&c, PIC_ESIZE, msg);
+    }
+    double* sc = nullptr;
+    hipError_t e = static_scratch_address(&sc);
+    if (e != hipSuccess) return hip_fail(&c, e, "diagnostics_static: scratch address");
+    hipStream_t s = (hipStream_t)stream;
+    double* rho_m = sc;
+    double* part = sc + align_up((size_t)c.k.ncell, 32);
+    if (!c.r0_valid) {
+        e = launch_capture_r0(c, s, rho_m);
+        if (e == hipSuccess) c.r0_valid = true;
+    }
+    if (e == hipSuccess) e = launch_diag(c, out, s, rho_m, part);
+    if (e != hipSuccess) return hip_fail(&c, e, "diagnostics_static");
     return PIC_OK;
 }
 

@@ -6,6 +6,8 @@
 // E(x^n) with E gathered by the run's own interpolation.  Reductions run over
 // a fixed grid of workgroups followed by one reducing workgroup, so the
 // result does not depend on scheduling.
+#include <mutex>
+
 #include "pic_math.h"
 
 namespace pic {
@@ -199,12 +201,13 @@ __global__ void k_zero_f64(double* p, int64_t n)
         p[i] = 0.0;
 }
 
-hipError_t mobile_rho(Ctx& c, hipStream_t s)
+// rho of the mobile species into rho_m (N doubles, cleared first by a kernel).
+hipError_t mobile_rho(Ctx& c, double* rho_m, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_f64, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.rho_m, c.k.ncell);
+    hipLaunchKernelGGL(k_zero_f64, dim3(kRedBlocks), dim3(kRedThreads), 0, s, rho_m, c.k.ncell);
     for (int i = 0; i < c.nsp; ++i)
         if (c.sp[i].d.mobile) {
-            hipError_t e = launch_rho(c, c.sp[i], c.rho_m, s);
+            hipError_t e = launch_rho(c, c.sp[i], rho_m, s);
             if (e != hipSuccess) return e;
         }
     return hipGetLastError();
@@ -221,29 +224,31 @@ __global__ __launch_bounds__(kRedThreads) void k_sum2(const double* __restrict__
 
 hipError_t launch_total_rho(Ctx& c, double* out, hipStream_t s)
 {
-    hipError_t e = mobile_rho(c, s);
+    hipError_t e = mobile_rho(c, c.rho_m, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum2, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.rho_m, c.rho_bg, out, c.k.ncell);
     return hipGetLastError();
 }
 
-hipError_t launch_capture_r0(Ctx& c, hipStream_t s)
+hipError_t launch_capture_r0(Ctx& c, hipStream_t s, double* rho_m)
 {
-    hipError_t e = mobile_rho(c, s);
+    if (!rho_m) rho_m = c.rho_m;
+    hipError_t e = mobile_rho(c, rho_m, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_capture_r0, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k, c.fields,
-                       c.rho_m, c.rho_bg, c.r0);
+                       rho_m, c.rho_bg, c.r0);
     return hipGetLastError();
 }
 
-hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s)
+hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s, double* rho_m, double* part)
 {
-    hipError_t e = mobile_rho(c, s);
+    if (!rho_m) rho_m = c.rho_m;
+    if (!part) part = c.red;
+    hipError_t e = mobile_rho(c, rho_m, s);
     if (e != hipSuccess) return e;
     // partial layout: cells kRedBlocks x kSlots, then one block per species
-    double* part = c.red;
     hipLaunchKernelGGL(k_diag_cells, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k, c.fields,
-                       c.rho_m, c.rho_bg, c.r0, part);
+                       rho_m, c.rho_bg, c.r0, part);
     int nb = kRedBlocks;
     int64_t nmob = 0;
     for (int i = 0; i < c.nsp; ++i) {
@@ -296,5 +301,49 @@ hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s)
 }
 
 size_t diag_partials_doubles(int nsp) { return (size_t)(kRedBlocks * (1 + nsp) + 1) * kSlots; }
+
+}  // namespace pic
+
+// ---------------------------------------------------------------------------
+// Diagnostics without a workspace (pic_diagnostics_static): the mobile charge
+// density and the reduction partials live in this file-scope device array,
+// one per GPU, held until the process ends.  In host code the array's name
+// stands for a host-side shadow, not the device memory: the device address
+// comes from hipGetSymbolAddress, once per device, and only that address is
+// handed to kernels.  Calls on one GPU share the array; calls that overlap on
+// one GPU race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[pic::kStaticScratchBytes / sizeof(double)];
+
+namespace pic {
+namespace {
+
+constexpr int kMaxDevices = 64;
+double* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+
+}  // namespace
+
+size_t static_scratch_doubles(const Ctx& c)
+{
+    return align_up((size_t)c.k.ncell, 32) + diag_partials_doubles(c.nsp);
+}
+
+hipError_t static_scratch_address(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
 
 }  // namespace pic

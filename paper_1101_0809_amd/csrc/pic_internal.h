@@ -160,8 +160,15 @@ hipError_t launch_rho_o2(const Ctx& c, const double* const x[3], const double* w
                          double* rho, hipStream_t s);
 // The conventional interpolation of Eq. wrong1 (grid interp 1, order 1, FP64).
 hipError_t launch_particle_step_conv(Ctx& c, Species& sp, hipStream_t s);
-hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s);
-hipError_t launch_capture_r0(Ctx& c, hipStream_t s);
+// rho_m (N doubles) and part (diag_partials_doubles) are scratch; null: the workspace's.
+hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s, double* rho_m = nullptr, double* part = nullptr);
+hipError_t launch_capture_r0(Ctx& c, hipStream_t s, double* rho_m = nullptr);
+size_t diag_partials_doubles(int nsp);
+// The static scratch of pic_diagnostics_static: its size, the doubles a
+// context needs of it, and its device address on the current device.
+constexpr size_t kStaticScratchBytes = (size_t)20 << 20;
+size_t static_scratch_doubles(const Ctx& c);
+hipError_t static_scratch_address(double** out);
 // rho of the mobile species (into the workspace's rho_m) plus the background, into out.
 hipError_t launch_total_rho(Ctx& c, double* out, hipStream_t s);
 // Electrostatic field of the charge density rho (Eqs. poiphi, egradphidis)

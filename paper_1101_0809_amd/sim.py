@@ -211,6 +211,13 @@ class Sim:
         self._check(self.lib.pic_diagnostics(self.ctx, ctypes.byref(d), _stream()))
         return d.as_dict()
 
+    def diagnostics_static(self) -> dict:
+        """pic_diagnostics_static: the same diagnostics with the library's
+        static scratch instead of the context's workspace."""
+        d = L.Diag()
+        self._check(self.lib.pic_diagnostics_static(self.ctx, ctypes.byref(d), _stream()))
+        return d.as_dict()
+
     def timing_start(self, max_steps: int):
         self._check(self.lib.pic_timing_start(self.ctx, max_steps))
 

@@ -1,0 +1,83 @@
+"""pic_diagnostics_static -- the diagnostics entry point that allocates
+nothing and takes no workspace (its scratch is a static device array of the
+library) -- against pic_diagnostics, through the C ABI, on two calls in a
+row, the second on a smaller grid and particle count than the first, so
+that it reuses the array the first call left filled."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import picgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(**kw):
+    from paper_1101_0809_amd import Sim
+    return Sim(**kw)
+
+
+def _loaded(nx, ny, nz, n, seed, precision):
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz, w_th=(0.3, 0.3, 0.3))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.stack([rng.uniform(0, m, n) for m in (nx, ny, nz)])
+    w = rng.normal(0.0, 0.3, (3, n))
+    weight = np.full(n, wl.weight)
+    sim = _sim(nx=nx, ny=ny, nz=nz, dt=wl.dt, dims=3, precision=precision, sort_every=4)
+    s = sim.add_species(-1.0, 1.0, n)
+    sim.load(s, x, w, weight)
+    si = sim.add_species(1.0, 100.0, 0, mobile=False)
+    sim.load(si, x, np.zeros_like(w), weight)
+    return sim
+
+
+def _same(a, b):
+    for key in ("step", "n_particles", "nonfinite"):
+        assert a[key] == b[key], key
+    for key in ("kinetic", "kinetic_half_step", "field_e", "field_b", "rho_mobile_max", "divb_max"):
+        assert a[key] == pytest.approx(b[key], rel=1e-12, abs=1e-300), key
+    # sums and drifts built from the charge density, whose atomics add in any order
+    scale = max(a["rho_mobile_max"], 1e-300)
+    assert abs(a["charge"] - b["charge"]) <= 1e-12 * scale
+    assert abs(a["gauss_abs"] - b["gauss_abs"]) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_static_diagnostics_match_workspace_diagnostics(precision):
+    """Two contexts in turn: 40x32x24 cells with 30,000 electrons, then
+    12x10x9 with 1,500.  Each call of the static entry point equals
+    pic_diagnostics on the same state; in the second context the static call
+    comes first, so it also captures the Gauss reference R^0."""
+    big = _loaded(40, 32, 24, 30000, 1, precision)
+    big.step(5)
+    ref = big.diagnostics()
+    got = big.diagnostics_static()
+    _same(got, ref)
+    assert got["field_e"] > 0.0
+    big.close()
+    small = _loaded(12, 10, 9, 1500, 2, precision)
+    small.step(3)
+    got = small.diagnostics_static()      # R^0 captured through the static scratch
+    ref = small.diagnostics()
+    _same(got, ref)
+    assert got["n_particles"] == 1500
+    small.step(2)
+    _same(small.diagnostics_static(), small.diagnostics())
+    small.close()
+
+
+def test_static_diagnostics_reject_grids_beyond_the_scratch():
+    """A grid of 2,621,440 cells does not fit the 20 MiB static scratch: the
+    call fails with PIC_ESIZE and a message that names the limit."""
+    import torch
+    from paper_1101_0809_amd import _lib as L
+    sim = _sim(nx=160, ny=128, nz=128, dt=0.45, dims=3)
+    d = L.Diag()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = sim.lib.pic_diagnostics_static(sim.ctx, ctypes.byref(d), stream)
+    assert rc == L.PIC_ESIZE
+    msg = sim.lib.pic_last_error(sim.ctx).decode()
+    assert "static scratch" in msg and "pic_diagnostics" in msg
+    assert sim.diagnostics()["nonfinite"] == 0   # the workspace entry point still works
+    sim.close()
