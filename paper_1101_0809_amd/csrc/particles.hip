@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
         push<R>(qmdt2, c2, E, B, w);
         for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
 
-        const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
+        const R inv = over_sqrt<R>(R(1), w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
         R disp[3];
         for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * cfl[ax];
         R d1[3];
@@ -431,7 +431,7 @@ __device__ __forceinline__ void advance_lds3(const GridK& g, const StepArgs& a, 
     const R c2 = (R)g.c * (R)g.c;
     push<R>((R)(0.5 * a.qm * g.dt), c2, E, B, w);
     for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
-    const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
+    const R inv = over_sqrt<R>(R(1), w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
     R disp[3];
     for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * (R)g.cfl[ax];
     for (int ax = 0; ax < 3; ++ax) delta[ax] = 0;
@@ -475,7 +475,7 @@ __device__ __forceinline__ void advance_global3(const GridK& g, const StepArgs& 
     const R c2 = (R)g.c * (R)g.c;
     push<R>((R)(0.5 * a.qm * g.dt), c2, E, B, w);
     for (int ax = 0; ax < 3; ++ax) ((R*)a.mom[ax])[p] = w[ax];
-    const R inv = R(1) / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
+    const R inv = over_sqrt<R>(R(1), w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + c2);
     R disp[3];
     for (int ax = 0; ax < 3; ++ax) disp[ax] = w[ax] * inv * (R)g.cfl[ax];
     R d1[3];
@@ -502,10 +502,11 @@ __device__ __forceinline__ void advance_global3(const GridK& g, const StepArgs& 
     deposit3<R>(dm, dp, jfac, S);
 }
 
-template <class R, int NT>
+template <class R, int NT, int KC>
 __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, const double* __restrict__ fields,
                                                       const double* __restrict__ bfield, double* __restrict__ Jg)
 {
+    constexpr int CH = KC * NT;  // slots per chunk
     constexpr int T = kTile3, M = kMargin3;
     constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
     constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
@@ -513,11 +514,11 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     constexpr int NJ = LJ * SJZ;  // per current component
     constexpr int C = lane_classes<R>();
     constexpr int CJ = 16;  // classes of the FP64 current tile
-    static_assert(NT % 256 == 0 && NT <= 65536 && kRowMax == 128, "chunk layout");
+    static_assert(NT % 256 == 0 && CH <= 65536 && kRowMax == 128, "chunk layout");
     static_assert(LF == 12 && LJ == 14 && fplane0(5) + 12 == kFieldPlanes3, "layout of the 3D tile");
     __shared__ R sf[kFieldPlanes3 * kFieldPlane3];
     __shared__ LdsJ<R, 3 * NJ> sj;
-    __shared__ uint16_t cperm[NT];         // chunk order: lane -> slot offset in the chunk
+    __shared__ uint16_t cperm[CH];         // chunk order: position -> slot offset in the chunk
     __shared__ uint16_t rstart[kRowMax];   // first chunk position of each class row
     __shared__ uint32_t rmask[kRowMax];    // classes present in each row
     __shared__ unsigned int ccnt[C];       // particles of each class in the chunk
@@ -558,36 +559,44 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     uint32_t* qother = (uint32_t*)a.qother + begin;
     unsigned my_migrant = 0;
 
-    // 3. the chunks
-    int ci[3] = {0, 0, 0};
-    if ((int)threadIdx.x < nt) PosIO<R, 3>::cell(a, begin + threadIdx.x, ci);
-    for (int cb = 0; cb < nt; cb += NT) {
-        const int sl = cb + (int)threadIdx.x;
+    // 3. the chunks of CH = KC * NT slots; thread t takes slots t + u NT
+    int ci[KC][3];
+#pragma unroll
+    for (int u = 0; u < KC; ++u)
+        if ((int)threadIdx.x + u * NT < nt) PosIO<R, 3>::cell(a, begin + threadIdx.x + u * NT, ci[u]);
+    for (int cb = 0; cb < nt; cb += CH) {
         // (a) classify
-        int cls = 0, mcode = -1;
-        unsigned rk = 0;
-        bool in = false;
-        if (sl < nt) {
+        int cls[KC], mcode[KC];
+        unsigned rk[KC];
+        bool in[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int sl = cb + (int)threadIdx.x + u * NT;
+            cls[u] = 0;
+            mcode[u] = -1;
+            rk[u] = 0;
+            in[u] = false;
+            if (sl >= nt) continue;
             int rel[3];
-            in = relative3(g, T0, ci, rel);
-            if (in) {
-                cls = cell_class3(rel[0], rel[1], rel[2], C);
-                rk = atomicAdd(&ccnt[cls], 1u);
+            in[u] = relative3(g, T0, ci[u], rel);
+            if (in[u]) {
+                cls[u] = cell_class3(rel[0], rel[1], rel[2], C);
+                rk[u] = atomicAdd(&ccnt[cls[u]], 1u);
+                continue;
+            }
+            // a neighbour tile takes a rank in the chunk's count for it; a
+            // tile further away reserves its bucket slot at once
+            mcode[u] = neighbour_code3(g, tx, ty, tz, ci[u]);
+            if (mcode[u] >= 0) {
+                rk[u] = atomicAdd(&mg_n[mcode[u]], 1u);
             } else {
-                // a neighbour tile takes a rank in the chunk's count for it;
-                // a tile further away reserves its bucket slot at once
-                mcode = neighbour_code3(g, tx, ty, tz, ci);
-                if (mcode >= 0) {
-                    rk = atomicAdd(&mg_n[mcode], 1u);
+                const int dt = tile_of3(g, ci[u]);
+                const unsigned r = atomicAdd(&a.mig_n[dt], 1u);
+                if (r < a.mig_cap) {
+                    a.mig[(int64_t)dt * a.mig_cap + r] = (uint32_t)(begin + sl);
+                    ++my_migrant;
                 } else {
-                    const int dt = tile_of3(g, ci);
-                    const unsigned r = atomicAdd(&a.mig_n[dt], 1u);
-                    if (r < a.mig_cap) {
-                        a.mig[(int64_t)dt * a.mig_cap + r] = (uint32_t)(begin + sl);
-                        ++my_migrant;
-                    } else {
-                        qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
-                    }
+                    qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
                 }
             }
         }
@@ -632,85 +641,95 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         }
         __syncthreads();
         // (c) chunk order; migrants take their bucket slots
-        if (mcode >= 0) {
-            const unsigned r = mg_base[mcode] + rk;
-            if (r < a.mig_cap) {
-                a.mig[(int64_t)neighbour_tile3(g, tx, ty, tz, mcode) * a.mig_cap + r] = (uint32_t)(begin + sl);
-                ++my_migrant;
-            } else {
-                qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int sl = cb + (int)threadIdx.x + u * NT;
+            if (mcode[u] >= 0) {
+                const unsigned r = mg_base[mcode[u]] + rk[u];
+                if (r < a.mig_cap) {
+                    a.mig[(int64_t)neighbour_tile3(g, tx, ty, tz, mcode[u]) * a.mig_cap + r] = (uint32_t)(begin + sl);
+                    ++my_migrant;
+                } else {
+                    qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
+                }
             }
-        }
-        if (in) {
-            const unsigned pos = rk < (unsigned)kRowMax
-                                     ? (unsigned)rstart[rk] + (unsigned)__popc(rmask[rk] & ((1u << cls) - 1u))
-                                     : c_rows + atomicAdd(&c_tail, 1u);
-            cperm[pos] = (uint16_t)threadIdx.x;
+            if (in[u]) {
+                const unsigned pos = rk[u] < (unsigned)kRowMax
+                                         ? (unsigned)rstart[rk[u]] +
+                                               (unsigned)__popc(rmask[rk[u]] & ((1u << cls[u]) - 1u))
+                                         : c_rows + atomicAdd(&c_tail, 1u);
+                cperm[pos] = (uint16_t)(threadIdx.x + u * NT);
+            }
         }
         if (threadIdx.x < C) ccnt[threadIdx.x] = 0;
         __syncthreads();
         const int ninside = (int)(c_rows + c_tail);
         // the next chunk's cells load while this chunk is advanced
-        if (sl + NT < nt) PosIO<R, 3>::cell(a, begin + sl + NT, ci);
-        if ((int)threadIdx.x >= ninside) continue;
-        // (d) advance
-        const int64_t p = begin + cb + cperm[threadIdx.x];
-        int i0[3];
-        R d0[3];
-        PosIO<R, 3>::load(a, p, i0, d0);
-        int rel[3];
-        relative3(g, T0, i0, rel);
-        Axis<R> ax0[3];
-        R d1[3], qp;
-        int delta[3];
-        advance_lds3<R>(g, a, sf, p, i0, d0, rel, ax0, d1, delta, qp);
-        R jfac[3];
-        for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
-        const bool still = (delta[0] | delta[1] | delta[2]) == 0;
-        if (still) {
-            R s1[3][3], s0[3][3];
-            for (int ax = 0; ax < 3; ++ax) {
-                cell_weights<R>(d1[ax], s1[ax]);
-                for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
-            }
-            const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
-            auto S = [&](int comp, int ix, int iy, int iz, R v) {
-                sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
-            };
-            deposit3_still<R>(s0, s1, jfac, S);
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int nsl = cb + CH + (int)threadIdx.x + u * NT;
+            if (nsl < nt) PosIO<R, 3>::cell(a, begin + nsl, ci[u]);
         }
-        // a crossing particle is queued: its entry densely, in arrival order,
-        // and its place in the class map
-        const unsigned long long mask = __ballot(!still);
-        if (mask) {
-            const int lane = threadIdx.x & 63;
-            const int leader = __ffsll((long long)mask) - 1;
-            unsigned int qbase = 0;
-            if (lane == leader) qbase = atomicAdd(&qc_total, (unsigned int)__popcll(mask));
-            qbase = __shfl(qbase, leader, 64);
-            if (!still) {
-                const unsigned e = qbase + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-                for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
-                int64_t word = p - begin;
+        // (d) advance: lane t takes chunk positions t, t + NT, ...
+        for (int q = (int)threadIdx.x; q < ninside; q += NT) {
+            const int64_t p = begin + cb + cperm[q];
+            int i0[3];
+            R d0[3];
+            PosIO<R, 3>::load(a, p, i0, d0);
+            int rel[3];
+            relative3(g, T0, i0, rel);
+            Axis<R> ax0[3];
+            R d1[3], qp;
+            int delta[3];
+            advance_lds3<R>(g, a, sf, p, i0, d0, rel, ax0, d1, delta, qp);
+            R jfac[3];
+            for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
+            const bool still = (delta[0] | delta[1] | delta[2]) == 0;
+            if (still) {
+                R s1[3][3], s0[3][3];
                 for (int ax = 0; ax < 3; ++ax) {
-                    word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
-                    word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
+                    cell_weights<R>(d1[ax], s1[ax]);
+                    for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
                 }
-                // map section: the crossing axis if there is one, 3 if several
-                const int nax = (delta[0] != 0) + (delta[1] != 0) + (delta[2] != 0);
-                const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
-                int s[3];
-                for (int ax = 0; ax < 3; ++ax) s[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
-                const int jw = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
-                const int col = sec * CJ + (jw & (CJ - 1));
-                const unsigned r = atomicAdd(&qc_n[col], 1u);
-                if (r < capc) {
-                    qmap[col + 4 * CJ * r] = e;
-                } else {
-                    word |= kUnmapped;
-                    atomicAdd(&qc_unmapped, 1u);
+                const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
+                auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                    sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
+                };
+                deposit3_still<R>(s0, s1, jfac, S);
+            }
+            // a crossing particle is queued: its entry densely, in arrival
+            // order, and its place in the class map
+            const unsigned long long mask = __ballot(!still);
+            if (mask) {
+                const int lane = threadIdx.x & 63;
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned int qbase = 0;
+                if (lane == leader) qbase = atomicAdd(&qc_total, (unsigned int)__popcll(mask));
+                qbase = __shfl(qbase, leader, 64);
+                if (!still) {
+                    const unsigned e = qbase + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+                    for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
+                    int64_t word = p - begin;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
+                        word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
+                    }
+                    // map section: the crossing axis if there is one, 3 if several
+                    const int nax = (delta[0] != 0) + (delta[1] != 0) + (delta[2] != 0);
+                    const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
+                    int sw[3];
+                    for (int ax = 0; ax < 3; ++ax) sw[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
+                    const int jw = (sw[0] + 2 + M) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
+                    const int col = sec * CJ + (jw & (CJ - 1));
+                    const unsigned r = atomicAdd(&qc_n[col], 1u);
+                    if (r < capc) {
+                        qmap[col + 4 * CJ * r] = e;
+                    } else {
+                        word |= kUnmapped;
+                        atomicAdd(&qc_unmapped, 1u);
+                    }
+                    a.qword[begin + e] = word;
                 }
-                a.qword[begin + e] = word;
             }
         }
     }
@@ -1178,6 +1197,8 @@ StepArgs step_args(const Ctx& c, const Species& sp, unsigned long long* counters
 // Threads per workgroup of each instantiation.
 constexpr int kThreads3 = 768;    // FP64: 3 waves per SIMD, <= 170 VGPRs
 constexpr int kThreads3f = 1024;  // FP32: 4 waves per SIMD
+constexpr int kChunk3 = 1;        // FP64: slots per thread and chunk (the LDS holds one chunk order of NT)
+constexpr int kChunk3f = 2;       // FP32: two slots per thread and chunk (half the barriers per particle)
 constexpr int kThreadsMig = 768;   // migrant pass, FP64 (as many waves as the step kernel)
 constexpr int kThreadsMigf = 1024; // migrant pass, FP32
 constexpr int kThreads2 = 256;
@@ -1197,7 +1218,7 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
     if (c.g.precision == PIC_FP64) {
         StepArgs a = step_args<double>(c, sp, c.counters);
         if (c.k.dims == 3) {
-            hipLaunchKernelGGL((k_particle_step3<double, kThreads3>), grid, dim3(kThreads3), 0, s, c.k, a,
+            hipLaunchKernelGGL((k_particle_step3<double, kThreads3, kChunk3>), grid, dim3(kThreads3), 0, s, c.k, a,
                                c.fields, c.bn, J);
             hipLaunchKernelGGL((k_migrants3<double, kThreadsMig>), grid, dim3(kThreadsMig), 0, s, c.k, a,
                                c.fields, c.bn, J);
@@ -1208,7 +1229,7 @@ hipError_t launch_particle_step(Ctx& c, Species& sp, hipStream_t s)
     } else {
         StepArgs a = step_args<float>(c, sp, c.counters);
         if (c.k.dims == 3) {
-            hipLaunchKernelGGL((k_particle_step3<float, kThreads3f>), grid, dim3(kThreads3f), 0, s, c.k, a,
+            hipLaunchKernelGGL((k_particle_step3<float, kThreads3f, kChunk3f>), grid, dim3(kThreads3f), 0, s, c.k, a,
                                c.fields, c.bn, J);
             hipLaunchKernelGGL((k_migrants3<float, kThreadsMigf>), grid, dim3(kThreadsMigf), 0, s, c.k, a,
                                c.fields, c.bn, J);

@@ -175,6 +175,21 @@ __device__ __forceinline__ void gather2(const Axis<R> (&w)[3], Acc F, R E[3], R 
 }
 
 // ---------------------------------------------------------------------------
+// a / sqrt(x) and a / x: correctly rounded in FP64 (the parity mode); in FP32
+// through the hardware reciprocal square root and reciprocal (about 1 ulp),
+// whose error stays far below what the FP32 representation of the particle
+// already carries.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R over_sqrt(R a, R x) { return a / sqrt(x); }
+template <>
+__device__ __forceinline__ float over_sqrt<float>(float a, float x) { return a * __builtin_amdgcn_rsqf(x); }
+template <class R>
+__device__ __forceinline__ R over(R a, R x) { return a / x; }
+template <>
+__device__ __forceinline__ float over<float>(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
+
+// ---------------------------------------------------------------------------
 // Momentum advance (Appendix): e = q dt E/(2m); w~ = w + e;
 // b = q dt B / (2 m sqrt(w~^2 + c^2)); w' = w~ + w~ x b;
 // w_new = w~ + e + 2 (w' x b)/(1 + b^2).
@@ -185,13 +200,12 @@ __device__ __forceinline__ void push(R qmdt2, R c2, const R E[3], const R B[3], 
     R e[3], wt[3], b[3];
     for (int a = 0; a < 3; ++a) e[a] = qmdt2 * E[a];
     for (int a = 0; a < 3; ++a) wt[a] = w[a] + e[a];
-    const R g = sqrt(wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2] + c2);
-    const R k = qmdt2 / g;
+    const R k = over_sqrt<R>(qmdt2, wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2] + c2);
     for (int a = 0; a < 3; ++a) b[a] = k * B[a];
     const R wp0 = wt[0] + (wt[1] * b[2] - wt[2] * b[1]);
     const R wp1 = wt[1] + (wt[2] * b[0] - wt[0] * b[2]);
     const R wp2 = wt[2] + (wt[0] * b[1] - wt[1] * b[0]);
-    const R s = R(2) / (R(1) + b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    const R s = over<R>(R(2), R(1) + b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
     w[0] = wt[0] + e[0] + s * (wp1 * b[2] - wp2 * b[1]);
     w[1] = wt[1] + e[1] + s * (wp2 * b[0] - wp0 * b[2]);
     w[2] = wt[2] + e[2] + s * (wp0 * b[1] - wp1 * b[0]);
