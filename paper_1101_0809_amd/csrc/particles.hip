@@ -270,7 +270,6 @@ __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a 
 __host__ __device__ constexpr int fnodez(int comp) { return comp >= 2 && comp <= 4 ? 1 : 0; }
 constexpr int kFieldPlanes3 = 69;  // 12 + 12 + 11 + 11 + 11 + 12
 constexpr int64_t kUnmapped = (int64_t)1 << 62;  // crossing entry not in the class map
-constexpr int kRowMax = 128;  // class rows ordered per chunk; higher ranks follow in arrival order
 constexpr unsigned kMigLds = 64;  // a migrant bucket this full is advanced with LDS tiles
 
 // Stage E^n and B^n of the 3D tile region into LDS, with SK loads of a thread
@@ -506,7 +505,9 @@ template <class R, int NT, int KC>
 __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, const double* __restrict__ fields,
                                                       const double* __restrict__ bfield, double* __restrict__ Jg)
 {
-    constexpr int CH = KC * NT;  // slots per chunk
+    constexpr int NW = NT / 64;  // waves
+    constexpr int WCH = 64 * KC;  // slots per wave chunk
+    constexpr int RW = 16;        // class rows ordered per wave chunk; higher ranks follow in arrival order
     constexpr int T = kTile3, M = kMargin3;
     constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
     constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
@@ -514,17 +515,17 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     constexpr int NJ = LJ * SJZ;  // per current component
     constexpr int C = lane_classes<R>();
     constexpr int CJ = 16;  // classes of the FP64 current tile
-    static_assert(NT % 256 == 0 && CH <= 65536 && kRowMax == 128, "chunk layout");
+    constexpr unsigned kRankBits = 27;  // migrant list entry: rank | neighbour code << 27
+    static_assert(NT % 256 == 0 && WCH <= 256 && C <= 32, "wave chunk layout");
     static_assert(LF == 12 && LJ == 14 && fplane0(5) + 12 == kFieldPlanes3, "layout of the 3D tile");
     __shared__ R sf[kFieldPlanes3 * kFieldPlane3];
     __shared__ LdsJ<R, 3 * NJ> sj;
-    __shared__ uint16_t cperm[CH];         // chunk order: position -> slot offset in the chunk
-    __shared__ uint16_t rstart[kRowMax];   // first chunk position of each class row
-    __shared__ uint32_t rmask[kRowMax];    // classes present in each row
-    __shared__ unsigned int ccnt[C];       // particles of each class in the chunk
-    __shared__ unsigned int c_rows, c_tail;
-    __shared__ unsigned int mg_n[27];      // migrants of the chunk per neighbour tile
+    __shared__ unsigned int wcnt[NW][C];   // per wave: particles of each class in its chunk
+    __shared__ uint8_t wperm[NW][WCH];     // per wave: chunk position -> slot offset in the chunk
+    __shared__ unsigned int wtail[NW];     // per wave: ranks beyond the ordered rows
+    __shared__ unsigned int mg_n[27];      // migrants of the tile per neighbour tile
     __shared__ unsigned int mg_base[27];   // their first bucket slot
+    __shared__ unsigned int ml_n;          // migrant list length
     __shared__ unsigned int qc_n[4 * CJ];  // crossing map: 4 sections (axis 0, 1, 2, several) x CJ classes
     __shared__ unsigned int qc_total, qc_unmapped;
     __shared__ unsigned int qo_n;  // migrants whose bucket was full
@@ -536,12 +537,13 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     const int tz = tile / (g.nt[0] * g.nt[1]);
     const int T0[3] = {tx * T, ty * T, tz * T};
     const bool small = g.n[0] < LJ || g.n[1] < LJ || g.n[2] < LJ;
+    const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
 
     // 1. stage E^n and B^n (B^n from bfield) into LDS
     stage_fields3<R, NT>(g, T0, fields, bfield, sf, small);
     // 2. clear the LDS current tile, the class counts and the queue counters
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
-    if (threadIdx.x < C) ccnt[threadIdx.x] = 0;
+    if (lane < C) wcnt[wv][lane] = 0;
     if (threadIdx.x < 27) mg_n[threadIdx.x] = 0;
     if (threadIdx.x < 4 * CJ) qc_n[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
@@ -549,6 +551,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         qc_unmapped = 0;
         qo_n = 0;
         n_migrant = 0;
+        ml_n = 0;
     }
     __syncthreads();
 
@@ -557,135 +560,60 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     const unsigned capc = (unsigned)(nt / (4 * CJ));
     uint32_t* qmap = (uint32_t*)a.qmap + begin;
     uint32_t* qother = (uint32_t*)a.qother + begin;
+    uint32_t* mslot = (uint32_t*)a.mlist + begin;   // migrant list: slot offsets
+    uint32_t* mword = (uint32_t*)a.mlist2 + begin;  // migrant list: rank | code << 27
     unsigned my_migrant = 0;
 
-    // 3. the chunks of CH = KC * NT slots; thread t takes slots t + u NT
-    int ci[KC][3];
-#pragma unroll
-    for (int u = 0; u < KC; ++u)
-        if ((int)threadIdx.x + u * NT < nt) PosIO<R, 3>::cell(a, begin + threadIdx.x + u * NT, ci[u]);
-    for (int cb = 0; cb < nt; cb += CH) {
-        // (a) classify
-        int cls[KC], mcode[KC];
-        unsigned rk[KC];
-        bool in[KC];
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            const int sl = cb + (int)threadIdx.x + u * NT;
-            cls[u] = 0;
-            mcode[u] = -1;
-            rk[u] = 0;
-            in[u] = false;
-            if (sl >= nt) continue;
-            int rel[3];
-            in[u] = relative3(g, T0, ci[u], rel);
-            if (in[u]) {
-                cls[u] = cell_class3(rel[0], rel[1], rel[2], C);
-                rk[u] = atomicAdd(&ccnt[cls[u]], 1u);
-                continue;
-            }
-            // a neighbour tile takes a rank in the chunk's count for it; a
-            // tile further away reserves its bucket slot at once
-            mcode[u] = neighbour_code3(g, tx, ty, tz, ci[u]);
-            if (mcode[u] >= 0) {
-                rk[u] = atomicAdd(&mg_n[mcode[u]], 1u);
-            } else {
-                const int dt = tile_of3(g, ci[u]);
-                const unsigned r = atomicAdd(&a.mig_n[dt], 1u);
-                if (r < a.mig_cap) {
-                    a.mig[(int64_t)dt * a.mig_cap + r] = (uint32_t)(begin + sl);
-                    ++my_migrant;
-                } else {
-                    qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
-                }
-            }
+    // Classify slot sl (cell ci): true if its cell lies in the tile region,
+    // with its lane class; otherwise the particle joins the tile's migrant
+    // list with its rank among the migrants to its new tile (a tile further
+    // away than a neighbour takes its bucket slot at once).
+    auto classify = [&](int sl, const int ci[3], int& cls) -> bool {
+        int rel[3];
+        if (relative3(g, T0, ci, rel)) {
+            cls = cell_class3(rel[0], rel[1], rel[2], C);
+            return true;
         }
-        __syncthreads();
-        // (b') one bucket reservation per neighbour tile that receives migrants
-        if (threadIdx.x >= 64 && threadIdx.x < 64 + 27) {
-            const int code = (int)threadIdx.x - 64;
-            const unsigned m = mg_n[code];
-            if (m) {
-                mg_n[code] = 0;
-                mg_base[code] = atomicAdd(&a.mig_n[neighbour_tile3(g, tx, ty, tz, code)], m);
-            }
+        const int code = neighbour_code3(g, tx, ty, tz, ci);
+        const unsigned r = code >= 0 ? atomicAdd(&mg_n[code], 1u) : 0u;
+        if (code >= 0 && r < (1u << kRankBits)) {
+            const unsigned e = atomicAdd(&ml_n, 1u);
+            mslot[e] = (uint32_t)sl;
+            mword[e] = r | ((uint32_t)code << kRankBits);
+            return false;
         }
-        // (b) class rows: row r holds the rank-r particle of each class that has one
-        if (threadIdx.x < 64) {
-            const int lane = (int)threadIdx.x;
-            uint32_t m0 = 0, m1 = 0;
-            for (int k = 0; k < C; ++k) {
-                const unsigned n = ccnt[k];
-                m0 |= (n > (unsigned)lane ? 1u : 0u) << k;
-                m1 |= (n > (unsigned)(lane + 64) ? 1u : 0u) << k;
-            }
-            const unsigned c0 = (unsigned)__popc(m0), c1 = (unsigned)__popc(m1);
-            unsigned s0 = c0, s1 = c1;
-            for (int o = 1; o < 64; o <<= 1) {
-                const unsigned t0 = __shfl_up(s0, o, 64);
-                const unsigned t1 = __shfl_up(s1, o, 64);
-                if (lane >= o) {
-                    s0 += t0;
-                    s1 += t1;
-                }
-            }
-            const unsigned tot0 = __shfl(s0, 63, 64);
-            rstart[lane] = (uint16_t)(s0 - c0);
-            rstart[lane + 64] = (uint16_t)(tot0 + s1 - c1);
-            rmask[lane] = m0;
-            rmask[lane + 64] = m1;
-            if (lane == 63) {
-                c_rows = tot0 + s1;
-                c_tail = 0;
-            }
+        const int dt = tile_of3(g, ci);
+        const unsigned rr = atomicAdd(&a.mig_n[dt], 1u);
+        if (rr < a.mig_cap) {
+            a.mig[(int64_t)dt * a.mig_cap + rr] = (uint32_t)(begin + sl);
+            ++my_migrant;
+        } else {
+            qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
         }
-        __syncthreads();
-        // (c) chunk order; migrants take their bucket slots
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            const int sl = cb + (int)threadIdx.x + u * NT;
-            if (mcode[u] >= 0) {
-                const unsigned r = mg_base[mcode[u]] + rk[u];
-                if (r < a.mig_cap) {
-                    a.mig[(int64_t)neighbour_tile3(g, tx, ty, tz, mcode[u]) * a.mig_cap + r] = (uint32_t)(begin + sl);
-                    ++my_migrant;
-                } else {
-                    qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
-                }
-            }
-            if (in[u]) {
-                const unsigned pos = rk[u] < (unsigned)kRowMax
-                                         ? (unsigned)rstart[rk[u]] +
-                                               (unsigned)__popc(rmask[rk[u]] & ((1u << cls[u]) - 1u))
-                                         : c_rows + atomicAdd(&c_tail, 1u);
-                cperm[pos] = (uint16_t)(threadIdx.x + u * NT);
-            }
-        }
-        if (threadIdx.x < C) ccnt[threadIdx.x] = 0;
-        __syncthreads();
-        const int ninside = (int)(c_rows + c_tail);
-        // the next chunk's cells load while this chunk is advanced
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            const int nsl = cb + CH + (int)threadIdx.x + u * NT;
-            if (nsl < nt) PosIO<R, 3>::cell(a, begin + nsl, ci[u]);
-        }
-        // (d) advance: lane t takes chunk positions t, t + NT, ...
-        for (int q = (int)threadIdx.x; q < ninside; q += NT) {
-            const int64_t p = begin + cb + cperm[q];
+        return false;
+    };
+
+    // Advance particle p, whose cell lies in the tile region: gather (LDS),
+    // push, move (state stored); a particle that stays in its cell deposits
+    // its 54 non-zero contributions, one that crosses a cell face is queued:
+    // its entry densely, in arrival order, and its place in the class map.
+    // Every lane of the wave that calls it must call it (the queue uses the
+    // wave's ballot); `active` false makes a lane a no-op.
+    auto advance = [&](int64_t p, bool active) {
+        bool still = true;
+        int rel[3] = {0, 0, 0}, delta[3] = {0, 0, 0};
+        R d0[3] = {0, 0, 0};
+        if (active) {
             int i0[3];
-            R d0[3];
             PosIO<R, 3>::load(a, p, i0, d0);
-            int rel[3];
             relative3(g, T0, i0, rel);
             Axis<R> ax0[3];
             R d1[3], qp;
-            int delta[3];
             advance_lds3<R>(g, a, sf, p, i0, d0, rel, ax0, d1, delta, qp);
-            R jfac[3];
-            for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
-            const bool still = (delta[0] | delta[1] | delta[2]) == 0;
+            still = (delta[0] | delta[1] | delta[2]) == 0;
             if (still) {
+                R jfac[3];
+                for (int ax = 0; ax < 3; ++ax) jfac[ax] = (R)g.jscale[ax] * qp;
                 R s1[3][3], s0[3][3];
                 for (int ax = 0; ax < 3; ++ax) {
                     cell_weights<R>(d1[ax], s1[ax]);
@@ -697,40 +625,118 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
                 };
                 deposit3_still<R>(s0, s1, jfac, S);
             }
-            // a crossing particle is queued: its entry densely, in arrival
-            // order, and its place in the class map
-            const unsigned long long mask = __ballot(!still);
-            if (mask) {
-                const int lane = threadIdx.x & 63;
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned int qbase = 0;
-                if (lane == leader) qbase = atomicAdd(&qc_total, (unsigned int)__popcll(mask));
-                qbase = __shfl(qbase, leader, 64);
-                if (!still) {
-                    const unsigned e = qbase + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-                    for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
-                    int64_t word = p - begin;
-                    for (int ax = 0; ax < 3; ++ax) {
-                        word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
-                        word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
-                    }
-                    // map section: the crossing axis if there is one, 3 if several
-                    const int nax = (delta[0] != 0) + (delta[1] != 0) + (delta[2] != 0);
-                    const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
-                    int sw[3];
-                    for (int ax = 0; ax < 3; ++ax) sw[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
-                    const int jw = (sw[0] + 2 + M) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
-                    const int col = sec * CJ + (jw & (CJ - 1));
-                    const unsigned r = atomicAdd(&qc_n[col], 1u);
-                    if (r < capc) {
-                        qmap[col + 4 * CJ * r] = e;
-                    } else {
-                        word |= kUnmapped;
-                        atomicAdd(&qc_unmapped, 1u);
-                    }
-                    a.qword[begin + e] = word;
-                }
+        }
+        const unsigned long long mask = __ballot(!still);
+        if (!mask) return;
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned int qbase = 0;
+        if (lane == leader) qbase = atomicAdd(&qc_total, (unsigned int)__popcll(mask));
+        qbase = __shfl(qbase, leader, 64);
+        if (still) return;
+        const unsigned e = qbase + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+        for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
+        int64_t word = p - begin;
+        for (int ax = 0; ax < 3; ++ax) {
+            word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
+            word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
+        }
+        // map section: the crossing axis if there is one, 3 if several
+        const int nax = (delta[0] != 0) + (delta[1] != 0) + (delta[2] != 0);
+        const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
+        int sw[3];
+        for (int ax = 0; ax < 3; ++ax) sw[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
+        const int jw = (sw[0] + 2 + M) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
+        const int col = sec * CJ + (jw & (CJ - 1));
+        const unsigned r = atomicAdd(&qc_n[col], 1u);
+        if (r < capc) {
+            qmap[col + 4 * CJ * r] = e;
+        } else {
+            word |= kUnmapped;
+            atomicAdd(&qc_unmapped, 1u);
+        }
+        a.qword[begin + e] = word;
+    };
+
+    // 3. wave chunks: wave w takes chunks w, w + NW, ... of WCH slots;
+    //    lane l the slots l + 64 u.  No workgroup barrier inside the loop:
+    //    the class order of a chunk is the wave's own, in its own rows.
+    int ci[KC][3];
+#pragma unroll
+    for (int u = 0; u < KC; ++u)
+        if (wv * WCH + lane + 64 * u < nt) PosIO<R, 3>::cell(a, begin + wv * WCH + lane + 64 * u, ci[u]);
+    for (int cb = wv * WCH; cb < nt; cb += NW * WCH) {
+        // (a) classify
+        int cls[KC];
+        unsigned rk[KC];
+        bool in[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int sl = cb + lane + 64 * u;
+            cls[u] = 0;
+            rk[u] = 0;
+            in[u] = sl < nt && classify(sl, ci[u], cls[u]);
+            if (in[u]) rk[u] = atomicAdd(&wcnt[wv][cls[u]], 1u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // (b) class rows: row r holds the rank-r particle of each class
+        //     that has one; lane r keeps row r's class mask and first position
+        const unsigned mycnt = lane < C ? wcnt[wv][lane] : 0u;
+        uint32_t rmask = 0;
+        unsigned rstart = 0, rows = 0;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const uint32_t m = (uint32_t)__ballot(mycnt > (unsigned)r);
+            rmask = lane == r ? m : rmask;
+            rstart = lane == r ? rows : rstart;
+            rows += (unsigned)__popc(m);
+        }
+        if (lane < C) wcnt[wv][lane] = 0;
+        if (lane == 0) wtail[wv] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // (c) chunk order
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int rsel = in[u] && rk[u] < (unsigned)RW ? (int)rk[u] : 0;
+            const uint32_t m = (uint32_t)__shfl((int)rmask, rsel, 64);
+            const unsigned st = (unsigned)__shfl((int)rstart, rsel, 64);
+            if (in[u]) {
+                const unsigned pos = rk[u] < (unsigned)RW ? st + (unsigned)__popc(m & ((1u << cls[u]) - 1u))
+                                                          : rows + atomicAdd(&wtail[wv], 1u);
+                wperm[wv][pos] = (uint8_t)(lane + 64 * u);
             }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int ninside = (int)(rows + wtail[wv]);
+        // the next chunk's cells load while this chunk is advanced
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int nsl = cb + NW * WCH + lane + 64 * u;
+            if (nsl < nt) PosIO<R, 3>::cell(a, begin + nsl, ci[u]);
+        }
+        // (d) advance: lane t takes chunk positions t, t + 64, ...
+        for (int q0 = 0; q0 < ninside; q0 += 64) {
+            const int q = q0 + lane;
+            advance(begin + cb + (q < ninside ? wperm[wv][q] : 0), q < ninside);
+        }
+    }
+    __syncthreads();
+    // the tile's migrants into the buckets of their new tiles: one reservation
+    // per neighbour tile, then the list
+    if (threadIdx.x < 27 && mg_n[threadIdx.x])
+        mg_base[threadIdx.x] = atomicAdd(&a.mig_n[neighbour_tile3(g, tx, ty, tz, threadIdx.x)], mg_n[threadIdx.x]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < (int)ml_n; e += NT) {
+        const uint32_t word = mword[e];
+        const int code = (int)(word >> kRankBits);
+        const unsigned r = mg_base[code] + (word & ((1u << kRankBits) - 1u));
+        if (r < a.mig_cap) {
+            a.mig[(int64_t)neighbour_tile3(g, tx, ty, tz, code) * a.mig_cap + r] = (uint32_t)(begin + mslot[e]);
+            ++my_migrant;
+        } else {
+            qother[atomicAdd(&qo_n, 1u)] = mslot[e];
         }
     }
     if (my_migrant) atomicAdd(&n_migrant, my_migrant);
@@ -1191,14 +1197,16 @@ StepArgs step_args(const Ctx& c, const Species& sp, unsigned long long* counters
     a.qword = sp.alt.id;
     a.qmap = (void*)sp.alt.weight;
     a.qother = sp.alt.mom[2];
+    a.mlist = sp.alt.mom[0];
+    a.mlist2 = sp.alt.mom[1];
     return a;
 }
 
 // Threads per workgroup of each instantiation.
 constexpr int kThreads3 = 768;    // FP64: 3 waves per SIMD, <= 170 VGPRs
 constexpr int kThreads3f = 1024;  // FP32: 4 waves per SIMD
-constexpr int kChunk3 = 1;        // FP64: slots per thread and chunk (the LDS holds one chunk order of NT)
-constexpr int kChunk3f = 2;       // FP32: two slots per thread and chunk (half the barriers per particle)
+constexpr int kChunk3 = 1;        // FP64: slots per lane and wave chunk
+constexpr int kChunk3f = 2;       // FP32: slots per lane and wave chunk
 constexpr int kThreadsMig = 768;   // migrant pass, FP64 (as many waves as the step kernel)
 constexpr int kThreadsMigf = 1024; // migrant pass, FP32
 constexpr int kThreads2 = 256;

@@ -783,6 +783,10 @@ struct StepArgs {
     // (32-bit slot offsets), in its third momentum array
     void* qmap;
     void* qother;
+    // 3D: the tile's migrant list (slot offsets; rank and neighbour code), in
+    // the spare copy's first two momentum arrays
+    void* mlist;
+    void* mlist2;
     // 3D migrant buckets: mig_cap particle indices per tile at mig + tile *
     // mig_cap, filled through the per-tile counters mig_n (zero between
     // launches: the migrant kernel clears the counter it reads)
