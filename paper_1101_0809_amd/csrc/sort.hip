@@ -93,10 +93,15 @@ __global__ __launch_bounds__(kSortThreads) void k_histogram(GridK g, PartArrays 
 
 // Histogram of a species that is still grouped by the tiles of its previous
 // sort (particles move at most one cell per step): one workgroup per old tile
-// range counts the particles that are still in that tile in LDS (the local
-// rank comes from the LDS atomic) and then reserves each cell's rank range in
-// the global histogram with one atomic; a particle now in another tile takes
-// its rank from a global atomic directly.  Ranks stay unique per cell.
+// range.  Each of its waves takes a contiguous block of the range and counts
+// the particles still in that tile per cell in its own LDS counters (a
+// wave's atomics rank its lanes in lane order, so the ranks follow the
+// storage order), a prefix over the waves orders the blocks, and each cell's
+// rank range in the global histogram is reserved with one atomic.  The ranks
+// of a cell's particles therefore keep their old order: a particle that did
+// not move keeps its place, and the final gather stays a near copy.  A
+// particle now in another tile takes its rank from a global atomic directly.
+// Ranks stay unique per cell.
 constexpr uint32_t kLocalRank = 1u << 31;
 
 template <class R, int D, int T>
@@ -105,38 +110,50 @@ __global__ __launch_bounds__(1024) void k_histogram_tiled(GridK g, PartArrays a,
                                                           uint32_t* __restrict__ hist)
 {
     constexpr int TPD = D == 3 ? T * T * T : T * T;
-    constexpr int NTH = 1024, U = 4;  // threads, particles of a thread in flight
-    __shared__ uint32_t cnt[TPD];
-    __shared__ uint32_t lut[D == 3 ? TPD : 1];  // class-major local keys, computed once per tile
+    constexpr int NTH = 1024, NW = NTH / 64, U = 4;  // threads, waves, slots of a lane in flight
+    __shared__ uint32_t cnt[NW][TPD];                // per wave, then per wave's first rank
+    __shared__ uint32_t lut[D == 3 ? TPD : 1];       // class-major local keys, computed once per tile
     const int t = blockIdx.x;
+    const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int64_t b = ts[t], e = ts[t + 1];
     const uint32_t k0 = (uint32_t)t * TPD;
-    for (int c = threadIdx.x; c < TPD; c += NTH) {
-        cnt[c] = 0;
+    for (int c = threadIdx.x; c < NW * TPD; c += NTH) (&cnt[0][0])[c] = 0;
+    for (int c = threadIdx.x; c < TPD; c += NTH)
         if (D == 3) lut[c] = class_major_local<lane_classes<R>()>(c % T, (c / T) % T, c / (T * T));
-    }
     __syncthreads();
-    for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += U * NTH) {
+    // wave w: slots [b + w L, b + (w + 1) L)
+    const int64_t L = (e - b + NW - 1) / NW;
+    const int64_t wb = b + wv * L, we = min(e, wb + L);
+    for (int64_t p0 = wb + lane; p0 < we; p0 += U * 64) {
         uint32_t k[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (p0 + u * NTH < e) k[u] = key_of<R, D, T>(g, a, p0 + u * NTH, D == 3 ? lut : nullptr);
+            if (p0 + u * 64 < we) k[u] = key_of<R, D, T>(g, a, p0 + u * 64, D == 3 ? lut : nullptr);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t p = p0 + u * NTH;
-            if (p >= e) continue;
+            const int64_t p = p0 + u * 64;
+            if (p >= we) continue;
             key[p] = k[u];
-            rank[p] = k[u] - k0 < (uint32_t)TPD ? (kLocalRank | atomicAdd(&cnt[k[u] - k0], 1u))
+            rank[p] = k[u] - k0 < (uint32_t)TPD ? (kLocalRank | atomicAdd(&cnt[wv][k[u] - k0], 1u))
                                                 : atomicAdd(&hist[k[u]], 1u);
         }
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < TPD; c += NTH)
-        if (cnt[c]) cnt[c] = atomicAdd(&hist[k0 + c], cnt[c]);
+    // per cell: the waves' first ranks, then the reservation of the whole range
+    for (int c = threadIdx.x; c < TPD; c += NTH) {
+        uint32_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t m = cnt[w][c];
+            cnt[w][c] = run;
+            run += m;
+        }
+        const uint32_t base = run ? atomicAdd(&hist[k0 + c], run) : 0u;
+        for (int w = 0; w < NW; ++w) cnt[w][c] += base;
+    }
     __syncthreads();
-    for (int64_t p = b + threadIdx.x; p < e; p += NTH) {
+    for (int64_t p = wb + lane; p < we; p += 64) {
         const uint32_t r = rank[p];
-        if (r & kLocalRank) rank[p] = cnt[key[p] - k0] + (r & ~kLocalRank);
+        if (r & kLocalRank) rank[p] = cnt[wv][key[p] - k0] + (r & ~kLocalRank);
     }
 }
 
@@ -337,7 +354,11 @@ __global__ __launch_bounds__(kSortThreads) void k_final_src(int64_t n, const uin
 // Move the particle arrays: slot q of the spare copy takes particle src[q].
 // Writes are coalesced; reads are local, since a particle's new slot is
 // mostly in or near the tile range it came from.  Each XCD takes a
-// contiguous run of slots, so a tile's reads gather in one XCD's L2.
+// contiguous run of slots, so a tile's reads gather in one XCD's L2.  A
+// thread moves kGatherU particles, all their loads in flight before the
+// stores.
+constexpr int kGatherU = 4;
+
 template <class R>
 __global__ __launch_bounds__(kSortThreads) void k_gather_final(PartArrays from, PartArrays to, int64_t n,
                                                                const uint32_t* __restrict__ src)
@@ -346,16 +367,39 @@ __global__ __launch_bounds__(kSortThreads) void k_gather_final(PartArrays from, 
     const int per = nb / kXcds, rem = nb % kXcds;
     const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
     const int blk = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
-    const int64_t q = (int64_t)blk * kSortThreads + threadIdx.x;
-    if (q >= n) return;
-    const int64_t p = src[q];
-    for (int ax = 0; ax < 3; ++ax) {
-        ((R*)to.pos[ax])[q] = ((const R*)from.pos[ax])[p];
-        ((R*)to.mom[ax])[q] = ((const R*)from.mom[ax])[p];
+    const int64_t q0 = (int64_t)blk * kSortThreads * kGatherU + threadIdx.x;
+    int64_t p[kGatherU];
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u) {
+        const int64_t q = q0 + u * kSortThreads;
+        p[u] = q < n ? (int64_t)src[q] : -1;
     }
-    ((R*)to.weight)[q] = ((const R*)from.weight)[p];
-    if (sizeof(R) == 4) to.cell[q] = from.cell[p];
-    to.id[q] = from.id[p];
+    R v[kGatherU][7];
+    uint32_t cl[kGatherU];
+    int64_t id[kGatherU];
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u) {
+        if (p[u] < 0) continue;
+        for (int ax = 0; ax < 3; ++ax) {
+            v[u][ax] = ((const R*)from.pos[ax])[p[u]];
+            v[u][3 + ax] = ((const R*)from.mom[ax])[p[u]];
+        }
+        v[u][6] = ((const R*)from.weight)[p[u]];
+        cl[u] = sizeof(R) == 4 ? from.cell[p[u]] : 0u;
+        id[u] = from.id[p[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u) {
+        if (p[u] < 0) continue;
+        const int64_t q = q0 + u * kSortThreads;
+        for (int ax = 0; ax < 3; ++ax) {
+            ((R*)to.pos[ax])[q] = v[u][ax];
+            ((R*)to.mom[ax])[q] = v[u][3 + ax];
+        }
+        ((R*)to.weight)[q] = v[u][6];
+        if (sizeof(R) == 4) to.cell[q] = cl[u];
+        to.id[q] = id[u];
+    }
 }
 
 template <int TPD>
@@ -399,8 +443,8 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
                                sp.tile_start);
         hipLaunchKernelGGL(k_final_src, dim3(nblk(n)), dim3(kSortThreads), 0, s, n, sp.key, sp.rank, c.hist,
                            sp.dest, sp.src);
-        hipLaunchKernelGGL((k_gather_final<R>), dim3(nblk(n)), dim3(kSortThreads), 0, s, sp.cur, sp.alt, n,
-                           sp.src);
+        hipLaunchKernelGGL((k_gather_final<R>), dim3(nblk((n + kGatherU - 1) / kGatherU)), dim3(kSortThreads), 0,
+                           s, sp.cur, sp.alt, n, sp.src);
         const PartArrays t = sp.cur;
         sp.cur = sp.alt;
         sp.alt = t;
