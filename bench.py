@@ -367,7 +367,8 @@ def _oracle_state(wl, e, ion, order=1, interp="alternating"):
 
 
 def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int = 1,
-                 interp: str = "alternating", full_limit: int = 1 << 22, sample_n: int = 1 << 20):
+                 interp: str = "alternating", full_limit: int = 1 << 22, sample_n: int = 1 << 20,
+                 all_cores: bool = True):
     """The FP64 oracle as it stands, serial, on the host.  A workload of at
     most full_limit mobile particles runs whole steps (all particles, full
     grid), as many as take min_seconds (at most max_steps).  A larger one is
@@ -375,7 +376,8 @@ def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int 
     and one step of the full grid with sample_n electrons (and as many ions
     when they move) drawn from the workload's distributions; the per-particle
     time of the second, with the grid time of the first, gives the rate of a
-    step of the whole workload."""
+    step of the whole workload; with all_cores, the sampled form also runs on
+    every host core at once (cpu_all_cores)."""
     import picgen
 
     host = (f"host {platform.processor() or platform.machine()} "
@@ -400,6 +402,27 @@ def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int 
     grid_only.step(1)
     t_grid = time.perf_counter() - t0
     del grid_only
+    t_step, ns = _oracle_sample_step(wl, sample_n, order, interp)
+    t_pp = max(t_step - t_grid, 1e-12) / ns
+    t_full = t_grid + wl.n_particles * t_pp
+    out = {"value": round(wl.n_particles / t_full, 1), "unit": "particle-steps/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"full {wl.nx}x{wl.ny}x{wl.nz} grid: one oracle step without particles "
+                     f"({t_grid:.2f} s, the field updates) and one with {ns} particles drawn from the "
+                     f"workload's distributions ({t_step:.2f} s); rate of the whole workload "
+                     f"({wl.n_particles} particles) = N / (grid time + N x per-particle time), "
+                     f"serial C oracle, order {order} 1/2, {interp} interpolation, {host}"}
+    if all_cores:
+        out["all_cores"] = cpu_all_cores(wl, t_grid, sample_n, order, interp)
+    return out
+
+
+def _oracle_sample_step(wl, sample_n, order, interp):
+    """One oracle step of the full grid with sample_n electrons (and as many
+    ions when they move) drawn from the workload's distributions: (seconds,
+    particles stepped)."""
+    import picgen
+
     small = wl.scaled(ppc=1)
     e = picgen.electrons(small, n=sample_n)
     e.weight[:] = wl.weight
@@ -408,16 +431,44 @@ def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int 
     ns = sample_n * (2 if wl.ions_mobile else 1)
     t0 = time.perf_counter()
     st.step(1)
-    t_step = time.perf_counter() - t0
-    t_pp = max(t_step - t_grid, 1e-12) / ns
+    return time.perf_counter() - t0, ns
+
+
+def cpu_all_cores(wl, t_grid, sample_n, order, interp, procs=None):
+    """The serial oracle on every host core at once: one child process per
+    core (at most 16), each stepping its own sample as the serial leg does.
+    The particles of a step are independent, so P copies stepping P samples
+    side by side give the host's rate for the particle work; the field
+    update (t_grid, serial) is added once.  Children are separate programs
+    started after the parent has used the GPU, not forks of it."""
+    import subprocess
+
+    procs = procs or max(1, min(16, os.cpu_count() or 1))
+    code = (f"import json, sys; sys.path.insert(0, {ROOT!r}); import bench, picgen; "
+            f"wl = picgen.WORKLOADS[{wl.name!r}]; "
+            f"t, ns = bench._oracle_sample_step(wl, {sample_n}, {order}, {interp!r}); "
+            f"print(json.dumps({{'t': t, 'ns': ns}}))")
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
+    t0 = time.perf_counter()
+    ch = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                           env=env, text=True) for _ in range(procs)]
+    res = []
+    for c in ch:
+        out, _ = c.communicate()
+        if c.returncode != 0:
+            raise RuntimeError(f"oracle child failed with status {c.returncode}")
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    wall = time.perf_counter() - t0
+    t_slow = max(r["t"] for r in res)   # every child's particle step overlaps the others'
+    ns_all = sum(r["ns"] for r in res)
+    t_pp = max(t_slow - t_grid, 1e-12) / ns_all
     t_full = t_grid + wl.n_particles * t_pp
-    return {"value": round(wl.n_particles / t_full, 1), "unit": "particle-steps/s", "cores": 1,
+    return {"value": round(wl.n_particles / t_full, 1), "unit": "particle-steps/s", "cores": procs,
             "kind": "oracle",
-            "sample": f"full {wl.nx}x{wl.ny}x{wl.nz} grid: one oracle step without particles "
-                      f"({t_grid:.2f} s, the field updates) and one with {ns} particles drawn from the "
-                      f"workload's distributions ({t_step:.2f} s); rate of the whole workload "
-                      f"({wl.n_particles} particles) = N / (grid time + N x per-particle time), "
-                      f"serial C oracle, order {order} 1/2, {interp} interpolation, {host}"}
+            "sample": f"{procs} copies of the serial C oracle side by side, one per core, each stepping "
+                      f"its own {res[0]['ns']} particles on the full grid (slowest step {t_slow:.2f} s, "
+                      f"{wall:.1f} s wall with set-up); per-particle time = slowest step / all particles, "
+                      f"plus one serial field update"}
 
 
 def main(argv=None):

@@ -197,11 +197,11 @@ def test_3d_migrants_and_full_buckets_parity(precision, tols):
                                              ("fp32c", (1e-3, 1e-5, 1e-6))])
 def test_3d_crowded_cell_parity(precision, tols):
     """600 electrons packed in one cell, beamed along +x, among a uniform
-    background: one lane class holds far more particles than its column of
-    the tile, and the crowd's crossers share one window class, so both class
-    queues of the 3D kernel overflow (displaced particles processed in place,
-    crossing entries outside the class map) -- against the oracle, with
-    re-sorts inside the run."""
+    background: a wave chunk holds far more particles of one lane class
+    than its 16 class rows, so the rest run in the unordered tail, and the
+    crowd's crossers share one window class, so their column of the crossing
+    map overflows and the entries outside it deposit in arrival order --
+    against the oracle, with re-sorts inside the run."""
     rng = np.random.Generator(np.random.PCG64(20260))
     n = 16
     crowd = 600
