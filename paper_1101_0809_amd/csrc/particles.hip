@@ -270,7 +270,10 @@ __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a 
 __host__ __device__ constexpr int fnodez(int comp) { return comp >= 2 && comp <= 4 ? 1 : 0; }
 constexpr int kFieldPlanes3 = 69;  // 12 + 12 + 11 + 11 + 11 + 12
 constexpr int64_t kUnmapped = (int64_t)1 << 62;  // crossing entry not in the class map
-constexpr unsigned kMigLds = 64;  // a migrant bucket this full is advanced with LDS tiles
+// A migrant bucket this full is advanced with LDS tiles.  Staging the tile and
+// flushing its current cost about as much as 8 particles on the global path
+// (144 global atomics each).
+constexpr unsigned kMigLds = 8;
 
 // Stage E^n and B^n of the 3D tile region into LDS, with SK loads of a thread
 // in flight before their stores (one load at a time would wait out the

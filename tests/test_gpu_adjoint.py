@@ -195,6 +195,55 @@ def test_step_vjp_particles_off_their_tile():
     sim.close()
 
 
+def test_step_vjp_off_tile_queue_overflow():
+    """3D reverse step of a tile whose off-tile queue overflows: 12,000
+    electrons loaded into one 8^3 tile of a 64^3 grid (512 tiles, so one
+    workgroup per tile) near its +x face, beamed along +x at w_x = 3 (0.43
+    cells per step), sorted, then stepped 6 times without a re-sort.  About
+    four in five end more than one cell outside the tile, more than the
+    7168 entries of the workgroup's queue, so the rest run their global form
+    inline in phase 1.  Against the oracle's one-step vector-Jacobian
+    product of that state."""
+    from paper_1101_0809_amd import Sim
+    box, dt, n = (64, 64, 64), 0.45, 12000
+    rng = np.random.Generator(np.random.PCG64(97))
+    x = np.stack([6.0 + 2.0 * rng.random(n), 8.0 * rng.random(n), 8.0 * rng.random(n)])
+    w = rng.normal(0.0, 0.05, (3, n))
+    w[0] += 3.0
+    weight = np.full(n, 1e-6)  # a light beam: its own field barely deflects it
+    shape = (box[2], box[1], box[0])
+    f = _fields(shape, 98, 0.05)
+    bext = (0.01, -0.02, 0.03)
+    sim = Sim(nx=box[0], ny=box[1], nz=box[2], dt=dt, dims=3, bext=bext, fields=f, sort_every=0)
+    sim.add_species(-1.0, 1.0, capacity=n)
+    sim.load(0, x, w, weight)
+    sim.sort()
+    sim.step(6)
+    F = sim.fields_numpy()
+    xs, ws, wts, ids = sim.particles(0)
+    assert np.array_equal(ids, np.arange(n))
+    # every particle was sorted into tile 0; count those beyond its region
+    # (cells -1 .. 8 on each axis)
+    off = int(((np.floor(xs) < -1) | (np.floor(xs) > 8)).any(axis=0).sum())
+    assert off > 7168 + 1000, off
+    lam = [rng.normal(size=(3,) + shape), rng.normal(size=(3,) + shape),
+           rng.normal(size=(3, n)), rng.normal(size=(3, n))]
+    ref = ad.step_vjp(ad.Grid(*box, dt), F[:3], F[3:6], xs, ws, wts, -1.0, 1.0, bext, *lam)
+    dev = torch.device("cuda:0")
+    lf = torch.tensor(np.concatenate([lam[0], lam[1]]).reshape(-1), device=dev)
+    lx = torch.tensor(lam[2], device=dev)
+    lw = torch.tensor(lam[3], device=dev)
+    lb = torch.zeros(3, dtype=torch.float64, device=dev)
+    sim.adjoint_step(lf, [lx], [lw], lb)
+    got = lf.cpu().numpy().reshape((6,) + shape)
+    _close(got[:3], ref[0], 1e-12)
+    _close(got[3:], ref[1], 1e-12)
+    _close(lx.cpu().numpy(), ref[2], 1e-12)
+    _close(lw.cpu().numpy(), ref[3], 1e-12)
+    _close(lb.cpu().numpy(), ref[4], 1e-12)
+    sim.close()
+
+
 CASES = {
     # 2D3V beams in B_z, several sorts and checkpoint segments
     "2d_8x8": dict(box=(8, 8, 1), dims=2, dt=0.5, n=64, seed=17, w_th=0.05, drift=0.2,
