@@ -225,43 +225,48 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 }
 
 // ---------------------------------------------------------------------------
-// The 3D particle-step kernel (tile kTile3^3, margin kMargin3).
+// The 3D particle-step kernel (tile kTile3^3; layout Tile3<R>).
 //
-// LDS: the field tile holds E^n and B^n on the cells T0-2 .. T0+9 of each axis
-// (12 values), rows padded to kFieldRow3 values and planes to kFieldPlane3;
-// the components that are node-centred in z (E^z, B^x, B^y) never read the
-// first plane and store planes 1..11 only.  The FP64 current tile covers
-// T0-3 .. T0+10 (14 cells per axis) with plane stride kJPlane3.  A cell's
-// field and current base indices then share their residue modulo 32, and that
-// residue modulo C (16 in FP64, 32 in FP32) is the cell's lane class.  Lanes
-// of one LDS pass that hold cells of distinct classes read and add in
+// LDS: the field tile holds E^n and B^n on the tile plus its margin and the
+// stencil: cells T0-1-MX .. T0+T+MX along x and T0-1-M .. T0+T+M along y and
+// z, in rows of FROW values and planes of FPLANE; the components that are
+// node-centred in z (E^z, B^x, B^y) never read the first plane and store
+// planes 1..11 only.  The FP64 current tile covers T0-2-MX .. T0+T+1+MX along
+// x and T0-2-M .. T0+T+1+M along y and z, rows of JROW, planes of JPLANE.  A
+// cell's field and current base indices share their residue modulo 32, and
+// that residue modulo C (16 in FP64, 32 in FP32) is the cell's lane class.
+// Lanes of one LDS pass that hold cells of distinct classes read and add in
 // distinct banks.
 //
-// The tile's particles are taken in chunks of NT consecutive storage slots,
-// so that every load and store of a chunk stays within a few cache lines per
-// array however far the particles have drifted since the last sort.  For each
-// chunk:
-//   (a) every slot's cell is classified (the load was issued during the
-//       previous chunk).  A particle within M cells of the tile takes a rank
-//       in its class (LDS atomic); any other particle has left the tile's
-//       region and is appended to the migrant bucket of the tile that now
-//       holds its cell, for k_migrants3;
-//   (b) one wave turns the class counts into rows: row r holds the rank-r
-//       particle of every class that has one, in class order;
-//   (c) each particle writes its slot into the chunk's permutation at its
-//       row position, so consecutive lanes hold distinct classes;
-//   (d) lane t advances the particle at permutation entry t: gather (LDS),
+// Each wave takes chunks of 64 KC consecutive storage slots (chunks w, w + NW,
+// ... of the tile), so every load and store of a chunk stays within a few
+// cache lines per array however far the particles have drifted since the last
+// sort, and orders its own chunk without a workgroup barrier:
+//   (a) every slot's cell is classified (its load was issued during the
+//       previous chunk).  A particle inside the tile region takes a rank among
+//       the chunk's particles of its class (LDS counter per wave and class);
+//       any other particle has left the region: it joins the tile's migrant
+//       list with its rank among the migrants to its neighbour tile (one
+//       further away takes a bucket slot at once);
+//   (b) one ballot per rank r < 16 gives row r, the classes with more than r
+//       particles in the chunk, so a row holds distinct classes;
+//   (c) each particle's place is its row's start plus the number of smaller
+//       classes in the row (ranks from 16 on follow the rows), written into
+//       the wave's permutation of the chunk;
+//   (d) lane t advances the particle at place t, t + 64, ...: gather (LDS),
 //       push, move (state stored), and, if it stays in its cell, its 54
 //       non-zero current contributions; a particle that crosses a cell face
 //       is appended to the crossing queue, with its place in a class map
 //       (column = class of its window's first cell).
-// After the chunks, pass 3 deposits the crossing particles' windows in
-// class-map order, in sections by crossing axis (75 contributions for one
-// axis, 144 for several); the entries a full map column could not take
-// follow in arrival order.  Migrants whose bucket was full are advanced with
-// global memory (gather from the grid, global atomics).  Last, the non-zero
-// current entries are flushed with global FP64 atomics.  The spare particle
-// copy holds the crossing queue and the overflow list (idle between sorts).
+// After the chunks, the migrants go into the buckets of their new tiles (one
+// global reservation per neighbour tile), those whose bucket was full are
+// advanced with global memory (gather from the grid, global atomics), and the
+// crossing pass deposits the queued windows in class-map order, in sections by
+// crossing axis (74 contributions for one axis, 144 for several); the entries
+// a full map column could not take follow in arrival order.  Last, the
+// non-zero current entries are flushed with global FP64 atomics.  The spare
+// particle copy holds the crossing queue and the migrant lists (idle between
+// sorts); the sort scratch holds the buckets.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a field component
 {
@@ -282,10 +287,10 @@ template <class R, int NT>
 __device__ __forceinline__ void stage_fields3(const GridK& g, const int T0[3], const double* __restrict__ fields,
                                               const double* __restrict__ bfield, R* sf, bool small)
 {
-    constexpr int T = kTile3, M = kMargin3;
-    constexpr int LF = T + 2 + 2 * M;
-    constexpr int SFY = kFieldRow3, SFZ = kFieldPlane3;
-    constexpr int NV = kFieldPlanes3 * LF * LF;
+    using TL = Tile3Dims<R>;
+    constexpr int MX = TL::MX, M = TL::M, LFX = TL::LFX, LFY = TL::LFY;
+    constexpr int SFY = TL::FROW, SFZ = TL::FPLANE;
+    constexpr int NV = kFieldPlanes3 * LFX * LFY;
     constexpr int SK = 7;
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -298,13 +303,13 @@ __device__ __forceinline__ void stage_fields3(const GridK& g, const int T0[3], c
             const int e = e0 + u * NT;
             li[u] = -1;
             if (e < NV) {
-                const int pl = e / (LF * LF);
-                const int rr = e - pl * (LF * LF);
-                const int ly = rr / LF;
-                const int lx = rr - ly * LF;
+                const int pl = e / (LFX * LFY);
+                const int rr = e - pl * (LFX * LFY);
+                const int ly = rr / LFX;
+                const int lx = rr - ly * LFX;
                 const int comp = pl < 12 ? 0 : (pl < 24 ? 1 : (pl < 35 ? 2 : (pl < 46 ? 3 : (pl < 57 ? 4 : 5))));
                 const int lz = pl - fplane0(comp) + fnodez(comp);
-                const int gx = wr(T0[0] - 1 - M + lx, nx);
+                const int gx = wr(T0[0] - 1 - MX + lx, nx);
                 const int gy = wr(T0[1] - 1 - M + ly, ny);
                 const int gz = wr(T0[2] - 1 - M + lz, nz);
                 v[u] = (comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[((int64_t)gz * ny + gy) * nx + gx];
@@ -323,10 +328,10 @@ template <class R, int NT, class LJT>
 __device__ __forceinline__ void flush_current3(const GridK& g, const int T0[3], const LJT& sj,
                                                double* __restrict__ Jg, bool small)
 {
-    constexpr int M = kMargin3;
-    constexpr int LJ = kTile3 + 4 + 2 * M;
-    constexpr int SJZ = kJPlane3;
-    constexpr int NJ = LJ * SJZ;
+    using TL = Tile3Dims<R>;
+    constexpr int MX = TL::MX, M = TL::M;
+    constexpr int SJY = TL::JROW, SJZ = TL::JPLANE;
+    constexpr int NJ = TL::NJ;
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
@@ -337,9 +342,9 @@ __device__ __forceinline__ void flush_current3(const GridK& g, const int T0[3], 
         const int r = e - comp * NJ;
         const int lz = r / SJZ;
         const int rr = r - lz * SJZ;
-        const int ly = rr / LJ;
-        const int lx = rr - ly * LJ;
-        const int gx = wr(T0[0] - 2 - M + lx, nx);
+        const int ly = rr / SJY;
+        const int lx = rr - ly * SJY;
+        const int gx = wr(T0[0] - 2 - MX + lx, nx);
         const int gy = wr(T0[1] - 2 - M + ly, ny);
         const int gz = wr(T0[2] - 2 - M + lz, nz);
         global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
@@ -347,18 +352,21 @@ __device__ __forceinline__ void flush_current3(const GridK& g, const int T0[3], 
 }
 
 // Position of cell i0 relative to the tile at T0, periodic-corrected; true if
-// within M cells of the tile (inside its LDS regions).
+// within the tile's margins (MX along x, M along y and z: inside its LDS
+// regions).
+template <class R>
 __device__ __forceinline__ bool relative3(const GridK& g, const int T0[3], const int i0[3], int rel[3])
 {
-    constexpr int T = kTile3, M = kMargin3;
+    constexpr int T = kTile3;
     bool in = true;
     for (int ax = 0; ax < 3; ++ax) {
+        const int m = ax == 0 ? Tile3<R>::MX : Tile3<R>::M;
         int r = i0[ax] - T0[ax];
         const int n = g.n[ax];
         if (r > n / 2) r -= n;
         if (r < -(n / 2)) r += n;
         rel[ax] = r;
-        in = in && (r >= -M) && (r <= T - 1 + M);
+        in = in && (r >= -m) && (r <= T - 1 + m);
     }
     return in;
 }
@@ -417,14 +425,15 @@ __device__ __forceinline__ void advance_lds3(const GridK& g, const StepArgs& a, 
                                              const int i0[3], const R d0[3], const int rel[3], Axis<R> (&ax0)[3],
                                              R d1[3], int delta[3], R& qp)
 {
-    constexpr int M = kMargin3;
-    constexpr int SFY = kFieldRow3, SFZ = kFieldPlane3;
+    using TL = Tile3<R>;
+    constexpr int MX = TL::MX, M = TL::M;
+    constexpr int SFY = TL::FROW, SFZ = TL::FPLANE;
     R w[3];
     for (int ax = 0; ax < 3; ++ax) w[ax] = ((const R*)a.mom[ax])[p];
     qp = (R)a.q * ((const R*)a.weight)[p];
     for (int ax = 0; ax < 3; ++ax) ax0[ax] = form_factor<R>(d0[ax]);
     R E[3], B[3];
-    const int base = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SFY + (rel[2] + 1 + M) * SFZ;
+    const int base = (rel[0] + 1 + MX) + (rel[1] + 1 + M) * SFY + (rel[2] + 1 + M) * SFZ;
     auto F = [&](int comp, int da, int db, int dc) -> R {
         return sf[(fplane0(comp) - fnodez(comp)) * SFZ + base + da + db * SFY + dc * SFZ];
     };
@@ -511,17 +520,17 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     constexpr int NW = NT / 64;  // waves
     constexpr int WCH = 64 * KC;  // slots per wave chunk
     constexpr int RW = 16;        // class rows ordered per wave chunk; higher ranks follow in arrival order
-    constexpr int T = kTile3, M = kMargin3;
-    constexpr int LF = T + 2 + 2 * M;  // field region: cells T0-1-M .. T0+T+M
-    constexpr int LJ = T + 4 + 2 * M;  // current region: T0-2-M .. T0+T+1+M
-    constexpr int SJY = LJ, SJZ = kJPlane3;
-    constexpr int NJ = LJ * SJZ;  // per current component
+    using TL = Tile3Dims<R>;
+    constexpr int T = kTile3, MX = TL::MX, M = TL::M;  // margins along x; along y and z
+    constexpr int LJX = TL::LJX, LJY = TL::LJY;  // current region: T0-2-M .. T0+T+1+M per axis
+    constexpr int SJY = TL::JROW, SJZ = TL::JPLANE;
+    constexpr int NJ = TL::NJ;  // per current component
     constexpr int C = lane_classes<R>();
     constexpr int CJ = 16;  // classes of the FP64 current tile
     constexpr unsigned kRankBits = 27;  // migrant list entry: rank | neighbour code << 27
     static_assert(NT % 256 == 0 && WCH <= 256 && C <= 32, "wave chunk layout");
-    static_assert(LF == 12 && LJ == 14 && fplane0(5) + 12 == kFieldPlanes3, "layout of the 3D tile");
-    __shared__ R sf[kFieldPlanes3 * kFieldPlane3];
+    static_assert(TL::LFY == 12 && fplane0(5) + 12 == kFieldPlanes3, "z planes of the 3D field tile");
+    __shared__ R sf[kFieldPlanes3 * TL::FPLANE];
     __shared__ LdsJ<R, 3 * NJ> sj;
     __shared__ unsigned int wcnt[NW][C];   // per wave: particles of each class in its chunk
     __shared__ uint8_t wperm[NW][WCH];     // per wave: chunk position -> slot offset in the chunk
@@ -539,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     const int ty = (tile / g.nt[0]) % g.nt[1];
     const int tz = tile / (g.nt[0] * g.nt[1]);
     const int T0[3] = {tx * T, ty * T, tz * T};
-    const bool small = g.n[0] < LJ || g.n[1] < LJ || g.n[2] < LJ;
+    const bool small = g.n[0] < LJX || g.n[1] < LJY || g.n[2] < LJY;
     const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
 
     // 1. stage E^n and B^n (B^n from bfield) into LDS
@@ -573,8 +582,8 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     // away than a neighbour takes its bucket slot at once).
     auto classify = [&](int sl, const int ci[3], int& cls) -> bool {
         int rel[3];
-        if (relative3(g, T0, ci, rel)) {
-            cls = cell_class3(rel[0], rel[1], rel[2], C);
+        if (relative3<R>(g, T0, ci, rel)) {
+            cls = cell_class3<R>(rel[0], rel[1], rel[2]);
             return true;
         }
         const int code = neighbour_code3(g, tx, ty, tz, ci);
@@ -609,7 +618,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         if (active) {
             int i0[3];
             PosIO<R, 3>::load(a, p, i0, d0);
-            relative3(g, T0, i0, rel);
+            relative3<R>(g, T0, i0, rel);
             Axis<R> ax0[3];
             R d1[3], qp;
             advance_lds3<R>(g, a, sf, p, i0, d0, rel, ax0, d1, delta, qp);
@@ -622,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
                     cell_weights<R>(d1[ax], s1[ax]);
                     for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
                 }
-                const int jb = (rel[0] + 1 + M) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
+                const int jb = (rel[0] + 1 + MX) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
                 auto S = [&](int comp, int ix, int iy, int iz, R v) {
                     sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
                 };
@@ -640,7 +649,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         for (int ax = 0; ax < 3; ++ax) ((R*)a.qd0[ax])[begin + e] = d0[ax];
         int64_t word = p - begin;
         for (int ax = 0; ax < 3; ++ax) {
-            word |= (int64_t)(rel[ax] + M) << (32 + 4 * ax);
+            word |= (int64_t)(rel[ax] + (ax == 0 ? MX : M)) << (32 + 4 * ax);
             word |= (int64_t)(delta[ax] + 1) << (44 + 2 * ax);
         }
         // map section: the crossing axis if there is one, 3 if several
@@ -648,7 +657,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         const int sec = nax == 1 ? (delta[0] != 0 ? 0 : (delta[1] != 0 ? 1 : 2)) : 3;
         int sw[3];
         for (int ax = 0; ax < 3; ++ax) sw[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
-        const int jw = (sw[0] + 2 + M) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
+        const int jw = (sw[0] + 2 + MX) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
         const int col = sec * CJ + (jw & (CJ - 1));
         const unsigned r = atomicAdd(&qc_n[col], 1u);
         if (r < capc) {
@@ -758,7 +767,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
             int rel[3], delta[3];
             R d0[3], d1[3];
             for (int ax = 0; ax < 3; ++ax) {
-                rel[ax] = (int)((word >> (32 + 4 * ax)) & 15) - M;
+                rel[ax] = (int)((word >> (32 + 4 * ax)) & 15) - (ax == 0 ? MX : M);
                 delta[ax] = (int)((word >> (44 + 2 * ax)) & 3) - 1;
                 d0[ax] = ((const R*)a.qd0[ax])[e];
                 if (sizeof(R) == 8) {  // the stored end position, as in PosIO::move
@@ -780,7 +789,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
             }
             int sw[3];
             for (int ax = 0; ax < 3; ++ax) sw[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
-            const int jb = (sw[0] + 2 + M) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
+            const int jb = (sw[0] + 2 + MX) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
             auto S = [&](int comp, int ix, int iy, int iz, R v) {
                 sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
             };
@@ -836,11 +845,11 @@ template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_migrants3(GridK g, StepArgs a, const double* __restrict__ fields,
                                                  const double* __restrict__ bfield, double* __restrict__ Jg)
 {
-    constexpr int T = kTile3, M = kMargin3;
-    constexpr int LJ = T + 4 + 2 * M;
-    constexpr int SJY = LJ, SJZ = kJPlane3;
-    constexpr int NJ = LJ * SJZ;
-    __shared__ R sf[kFieldPlanes3 * kFieldPlane3];
+    using TL = Tile3Dims<R>;
+    constexpr int T = kTile3, MX = TL::MX, M = TL::M;
+    constexpr int SJY = TL::JROW, SJZ = TL::JPLANE;
+    constexpr int NJ = TL::NJ;
+    __shared__ R sf[kFieldPlanes3 * TL::FPLANE];
     __shared__ LdsJ<R, 3 * NJ> sj;
     __shared__ unsigned int n_global;
 
@@ -861,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_migrants3(GridK g, StepArgs a, const dou
     const int ty = (tile / g.nt[0]) % g.nt[1];
     const int tz = tile / (g.nt[0] * g.nt[1]);
     const int T0[3] = {tx * T, ty * T, tz * T};
-    const bool small = g.n[0] < LJ || g.n[1] < LJ || g.n[2] < LJ;
+    const bool small = g.n[0] < TL::LJX || g.n[1] < TL::LJY || g.n[2] < TL::LJY;
     stage_fields3<R, NT>(g, T0, fields, bfield, sf, small);
     for (int e = threadIdx.x; e < 3 * NJ; e += NT) sj.zero(e);
     if (threadIdx.x == 0) n_global = 0;
@@ -873,7 +882,7 @@ __global__ __launch_bounds__(NT) void k_migrants3(GridK g, StepArgs a, const dou
         R d0[3];
         PosIO<R, 3>::load(a, p, i0, d0);
         int rel[3];
-        if (!relative3(g, T0, i0, rel)) {  // not a cell of this tile (non-finite input): global memory
+        if (!relative3<R>(g, T0, i0, rel)) {  // not a cell of this tile (non-finite input): global memory
             advance_global3<R>(g, a, p, fields, bfield, Jg);
             ++my_global;
             continue;
@@ -892,7 +901,7 @@ __global__ __launch_bounds__(NT) void k_migrants3(GridK g, StepArgs a, const dou
         }
         int s[3];
         for (int ax = 0; ax < 3; ++ax) s[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
-        const int jb = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
+        const int jb = (s[0] + 2 + MX) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
         auto S = [&](int comp, int ix, int iy, int iz, R v) {
             sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
         };

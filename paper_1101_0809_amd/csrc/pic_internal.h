@@ -20,33 +20,53 @@ constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its o
 constexpr int kTile3 = 8;
 constexpr int kTile2 = 16;
 
-// 3D particle kernel LDS layout.  A particle inside a tile's region may sit up
-// to kMargin3 cells outside the tile.  The field tile (E^n, B^n on 12 cells
-// per axis) has rows of kFieldRow3 values and planes of kFieldPlane3; the FP64
-// current tile (14 cells per axis) has rows of 14 and planes of kJPlane3
-// doubles.  The strides agree modulo 32, so the field base index and the
-// current base index of a cell have the same residue: the cell's lane class,
-// shared by the sort (which places particles by class) and the kernel.
-constexpr int kMargin3 = 1;
-constexpr int kFieldRow3 = 14;
-constexpr int kFieldPlane3 = 168;
-constexpr int kJPlane3 = 200;
-static_assert(kFieldRow3 >= kTile3 + 2 + 2 * kMargin3 && kFieldRow3 == kTile3 + 4 + 2 * kMargin3,
-              "field rows are padded to the current tile's row stride");
-static_assert(kFieldPlane3 >= 11 * kFieldRow3 + 12 && kJPlane3 >= 14 * 14, "planes hold their rows");
-static_assert((kJPlane3 - kFieldPlane3) % 32 == 0, "field and current plane strides agree mod 32");
+// 3D particle kernel LDS layout, per precision.  A particle inside a tile's
+// region may sit up to MX cells outside the tile along x and M cells along y
+// and z.  The field tile (E^n, B^n) covers LFX x LFY x LFY cells, with rows of
+// FROW values and planes of FPLANE; the FP64 current tile covers LJX x LJY x
+// LJY cells, with rows of JROW and planes of JPLANE doubles.  The strides agree
+// modulo 32, so the field base index and the current base index of a cell have
+// the same residue: the cell's lane class, shared by the sort (which places
+// particles by class) and the kernel.  FP32 mode stores its field tile in
+// FP32, which leaves room for a margin of 2 along x: fewer particles leave
+// their tile's region between sorts when they drift along x.
+template <class R>
+struct Tile3;
+template <>
+struct Tile3<double> {
+    static constexpr int MX = 1, M = 1;
+    static constexpr int FROW = 14, FPLANE = 168, JROW = 14, JPLANE = 200;
+};
+template <>
+struct Tile3<float> {
+    static constexpr int MX = 2, M = 1;
+    static constexpr int FROW = 16, FPLANE = 200, JROW = 16, JPLANE = 232;
+};
+template <class R>
+struct Tile3Dims : Tile3<R> {
+    using L = Tile3<R>;
+    static constexpr int LFX = kTile3 + 2 + 2 * L::MX, LFY = kTile3 + 2 + 2 * L::M;
+    static constexpr int LJX = kTile3 + 4 + 2 * L::MX, LJY = kTile3 + 4 + 2 * L::M;
+    static constexpr int NJ = LJY * L::JPLANE;  // doubles per current component
+    static_assert(L::FROW >= LFX && L::FPLANE >= LFY * L::FROW, "field rows and planes hold the region");
+    static_assert(L::JROW >= LJX && L::JPLANE >= LJY * L::JROW, "current rows and planes hold the region");
+    static_assert((L::JROW - L::FROW) % 32 == 0 && (L::JPLANE - L::FPLANE) % 32 == 0,
+                  "field and current strides agree mod 32");
+    static_assert(kTile3 - 1 + 2 * L::MX < 16 && kTile3 - 1 + 2 * L::M < 16, "region offsets fit 4 bits");
+};
 
 // Lane classes: LDS serves 128 bytes per clock, 16 lanes of 8-byte values (FP64
 // fields and the current tile) or 32 lanes of 4-byte values (FP32 fields).
 template <class R>
 constexpr int lane_classes() { return sizeof(R) == 8 ? 16 : 32; }
 
-// Class of a cell at offset rel (each in [-kMargin3, kTile3 - 1 + kMargin3])
-// from its tile's first cell: its field-tile base index modulo C.
-__host__ __device__ inline int cell_class3(int rx, int ry, int rz, int C)
+// Class of a cell at offset rel from its tile's first cell (rel inside the
+// tile region): its field-tile base index modulo the lane classes.
+template <class R>
+__host__ __device__ inline int cell_class3(int rx, int ry, int rz)
 {
-    return ((rx + 1 + kMargin3) + (ry + 1 + kMargin3) * kFieldRow3 + (rz + 1 + kMargin3) * kFieldPlane3) &
-           (C - 1);
+    using L = Tile3<R>;
+    return ((rx + 1 + L::MX) + (ry + 1 + L::M) * L::FROW + (rz + 1 + L::M) * L::FPLANE) & (lane_classes<R>() - 1);
 }
 
 // Particle arrays of one copy (the library keeps two for out-of-place sorts).

@@ -35,15 +35,15 @@ __device__ __forceinline__ void unpack(uint32_t c, int i[3])
 // most one cell of a class (T < C consecutive x offsets), so the cell's index
 // inside its class is the number of earlier rows, in (lz, ly) order, that
 // hold a cell of that class.
-template <int C>
+template <class R>
 __device__ __forceinline__ uint32_t class_major_local(int lx, int ly, int lz)
 {
-    constexpr int T = kTile3;
+    constexpr int T = kTile3, C = lane_classes<R>();
     static_assert(T < C && (T * T * T) % C == 0, "one cell of a class per row, equal classes");
-    const int cls = cell_class3(lx, ly, lz, C);
+    const int cls = cell_class3<R>(lx, ly, lz);
     uint32_t idx = 0;
     for (int row = 0; row < ly + lz * T; ++row) {
-        const int b = cell_class3(0, row % T, row / T, C);
+        const int b = cell_class3<R>(0, row % T, row / T);
         idx += ((cls - b) & (C - 1)) < T ? 1u : 0u;
     }
     return (uint32_t)cls * (T * T * T / C) + idx;
@@ -68,7 +68,7 @@ __device__ __forceinline__ uint32_t key_of(const GridK& g, const PartArrays& a, 
     const uint32_t lx = i[0] - tx * T, ly = i[1] - ty * T, lz = D == 3 ? i[2] - tz * T : 0;
     uint32_t local = ly * T + lx;
     if (D == 3)
-        local = lut ? lut[(lz * T + ly) * T + lx] : class_major_local<lane_classes<R>()>((int)lx, (int)ly, (int)lz);
+        local = lut ? lut[(lz * T + ly) * T + lx] : class_major_local<R>((int)lx, (int)ly, (int)lz);
     return tile * (uint32_t)(D == 3 ? T * T * T : T * T) + local;
 }
 
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(1024) void k_histogram_tiled(GridK g, PartArrays a,
     const uint32_t k0 = (uint32_t)t * TPD;
     for (int c = threadIdx.x; c < NW * TPD; c += NTH) (&cnt[0][0])[c] = 0;
     for (int c = threadIdx.x; c < TPD; c += NTH)
-        if (D == 3) lut[c] = class_major_local<lane_classes<R>()>(c % T, (c / T) % T, c / (T * T));
+        if (D == 3) lut[c] = class_major_local<R>(c % T, (c / T) % T, c / (T * T));
     __syncthreads();
     // wave w: slots [b + w L, b + (w + 1) L)
     const int64_t L = (e - b + NW - 1) / NW;

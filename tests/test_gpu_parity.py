@@ -163,8 +163,9 @@ def test_3d_ragged_tiles_fp64_parity():
                                              ("fp32c", (1e-3, 1e-5, 1e-6))])
 def test_3d_migrants_and_full_buckets_parity(precision, tols):
     """A beam at w_x = 1 (0.32 cells per step) that is sorted only when loaded:
-    every electron leaves its sorted tile's region and is advanced by the
-    migrant pass of the tile it moved into.  The species' capacity equals its
+    most electrons leave their sorted tile's region (the immobile ions left
+    behind pull the beam back) and are advanced by the migrant pass of the
+    tile they moved into.  The species' capacity equals its
     count, so each of the 16 tiles' buckets holds a quarter of the particles,
     and the two tiles the beam (y < 8) enters overflow: their extra migrants
     take the global-memory path.  Against the oracle."""
@@ -185,10 +186,10 @@ def test_3d_migrants_and_full_buckets_parity(precision, tols):
                        oracle.Species(x, np.zeros_like(w), weight, q=1.0, m=100.0, mobile=False)])
     sim.step(14)
     st.step(14)
-    sim.step(4)   # statistics of the last call: the beam is beyond its tiles' regions
+    sim.step(4)   # statistics of the last call: most of the beam is beyond its tiles' regions
     st.step(4)
-    assert sim.migrant_fraction() > 0.5
-    assert sim.fallback_fraction() > 0.0
+    mig, fb = sim.migrant_fraction(), sim.fallback_fraction()
+    assert mig > 0.3 and fb > 0.0, (mig, fb)
     wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz)
     _compare(sim, st, wl, *tols)
 
@@ -358,7 +359,8 @@ def test_sort_order(dims, precision):
     """After a sort, storage order is tile-major and the ids are a permutation
     of the loaded ones.  Inside a 3D tile of n_t particles, slot s holds a
     particle of lane class s mod C (C = 16 FP64, 32 FP32; the class of tile
-    cell l is ((lx+2) + 14 (ly+2) + 168 (lz+2)) mod C) in as many slots as the
+    cell l is its field-tile base index mod C: ((lx+2) + 14 (ly+2) + 168 (lz+2))
+    in FP64, ((lx+3) + 16 (ly+2) + 200 (lz+2)) in FP32) in as many slots as the
     class counts allow -- sum over classes of min(count, rows of the column) --
     those slots form the first rows of each column, and down a column the
     cells follow their (lz, ly) row order.  Inside a 2D tile: rank levels in
@@ -384,8 +386,10 @@ def test_sort_order(dims, precision):
     lz = cell[2] % T if dims == 3 else np.zeros_like(cell[0])
     lx, ly = cell[0] % T, cell[1] % T
     if dims == 3:
-        C = 16 if precision == "fp64" else 32
-        cls = ((lx + 2) + 14 * (ly + 2) + 168 * (lz + 2)) % C
+        if precision == "fp64":
+            C, cls = 16, ((lx + 2) + 14 * (ly + 2) + 168 * (lz + 2)) % 16
+        else:
+            C, cls = 32, ((lx + 3) + 16 * (ly + 2) + 200 * (lz + 2)) % 32
         row_order = lz * T + ly
         for t in np.unique(tile):
             sel = np.flatnonzero(tile == t)
