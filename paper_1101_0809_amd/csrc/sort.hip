@@ -354,12 +354,20 @@ __global__ __launch_bounds__(kSortThreads) void k_final_src(int64_t n, const uin
 // Move the particle arrays: slot q of the spare copy takes particle src[q].
 // Writes are coalesced; reads are local, since a particle's new slot is
 // mostly in or near the tile range it came from.  Each XCD takes a
-// contiguous run of slots, so a tile's reads gather in one XCD's L2.  A
-// thread moves kGatherU particles, all their loads in flight before the
-// stores.
+// contiguous run of slots, so a tile's reads gather in one XCD's L2.  One
+// launch moves one array (A = 0..2 positions, 3..5 momenta, 6 weight, 7 id,
+// 8 the FP32 cell): the source lines that the tiles in flight on an XCD
+// touch then fit its L2, where all arrays at once would not.  A thread moves
+// kGatherU particles, all their loads in flight before the stores.
 constexpr int kGatherU = 4;
 
-template <class R>
+template <class V, int A>
+__device__ __forceinline__ V* gather_array(const PartArrays& P)
+{
+    return (V*)(A < 3 ? P.pos[A] : (A < 6 ? P.mom[A - 3] : (A == 6 ? P.weight : (A == 7 ? (void*)P.id : (void*)P.cell))));
+}
+
+template <class V, int A>
 __global__ __launch_bounds__(kSortThreads) void k_gather_final(PartArrays from, PartArrays to, int64_t n,
                                                                const uint32_t* __restrict__ src)
 {
@@ -368,38 +376,37 @@ __global__ __launch_bounds__(kSortThreads) void k_gather_final(PartArrays from, 
     const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
     const int blk = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
     const int64_t q0 = (int64_t)blk * kSortThreads * kGatherU + threadIdx.x;
+    const V* __restrict__ in = gather_array<V, A>(from);
+    V* __restrict__ out = gather_array<V, A>(to);
     int64_t p[kGatherU];
 #pragma unroll
     for (int u = 0; u < kGatherU; ++u) {
         const int64_t q = q0 + u * kSortThreads;
         p[u] = q < n ? (int64_t)src[q] : -1;
     }
-    R v[kGatherU][7];
-    uint32_t cl[kGatherU];
-    int64_t id[kGatherU];
+    V v[kGatherU];
 #pragma unroll
-    for (int u = 0; u < kGatherU; ++u) {
-        if (p[u] < 0) continue;
-        for (int ax = 0; ax < 3; ++ax) {
-            v[u][ax] = ((const R*)from.pos[ax])[p[u]];
-            v[u][3 + ax] = ((const R*)from.mom[ax])[p[u]];
-        }
-        v[u][6] = ((const R*)from.weight)[p[u]];
-        cl[u] = sizeof(R) == 4 ? from.cell[p[u]] : 0u;
-        id[u] = from.id[p[u]];
-    }
+    for (int u = 0; u < kGatherU; ++u)
+        if (p[u] >= 0) v[u] = in[p[u]];
 #pragma unroll
-    for (int u = 0; u < kGatherU; ++u) {
-        if (p[u] < 0) continue;
-        const int64_t q = q0 + u * kSortThreads;
-        for (int ax = 0; ax < 3; ++ax) {
-            ((R*)to.pos[ax])[q] = v[u][ax];
-            ((R*)to.mom[ax])[q] = v[u][3 + ax];
-        }
-        ((R*)to.weight)[q] = v[u][6];
-        if (sizeof(R) == 4) to.cell[q] = cl[u];
-        to.id[q] = id[u];
-    }
+    for (int u = 0; u < kGatherU; ++u)
+        if (p[u] >= 0) out[q0 + u * kSortThreads] = v[u];
+}
+
+template <class R>
+void launch_gather_final(const PartArrays& from, const PartArrays& to, int64_t n, const uint32_t* src,
+                         hipStream_t s, dim3 grid)
+{
+    hipLaunchKernelGGL((k_gather_final<R, 0>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    hipLaunchKernelGGL((k_gather_final<R, 1>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    hipLaunchKernelGGL((k_gather_final<R, 2>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    hipLaunchKernelGGL((k_gather_final<R, 3>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    hipLaunchKernelGGL((k_gather_final<R, 4>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    hipLaunchKernelGGL((k_gather_final<R, 5>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    hipLaunchKernelGGL((k_gather_final<R, 6>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    hipLaunchKernelGGL((k_gather_final<int64_t, 7>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
+    if (sizeof(R) == 4)
+        hipLaunchKernelGGL((k_gather_final<uint32_t, 8>), grid, dim3(kSortThreads), 0, s, from, to, n, src);
 }
 
 template <int TPD>
@@ -443,8 +450,7 @@ hipError_t sort_impl(Ctx& c, Species& sp, hipStream_t s)
                                sp.tile_start);
         hipLaunchKernelGGL(k_final_src, dim3(nblk(n)), dim3(kSortThreads), 0, s, n, sp.key, sp.rank, c.hist,
                            sp.dest, sp.src);
-        hipLaunchKernelGGL((k_gather_final<R>), dim3(nblk((n + kGatherU - 1) / kGatherU)), dim3(kSortThreads), 0,
-                           s, sp.cur, sp.alt, n, sp.src);
+        launch_gather_final<R>(sp.cur, sp.alt, n, sp.src, s, dim3(nblk((n + kGatherU - 1) / kGatherU)));
         const PartArrays t = sp.cur;
         sp.cur = sp.alt;
         sp.alt = t;
