@@ -519,7 +519,10 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
 {
     constexpr int NW = NT / 64;  // waves
     constexpr int WCH = 64 * KC;  // slots per wave chunk
-    constexpr int RW = 16;        // class rows ordered per wave chunk; higher ranks follow in arrival order
+    // class rows ordered per wave chunk; higher ranks follow in arrival order.
+    // A chunk averages 4 particles per class, so a class fills more than 10
+    // rows in about 0.3% of chunks.
+    constexpr int RW = 10;
     using TL = Tile3Dims<R>;
     constexpr int T = kTile3, MX = TL::MX, M = TL::M;  // margins along x; along y and z
     constexpr int LJX = TL::LJX, LJY = TL::LJY;  // current region: T0-2-M .. T0+T+1+M per axis
