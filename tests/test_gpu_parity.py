@@ -196,6 +196,46 @@ def test_3d_migrants_and_full_buckets_parity(precision, tols):
 
 @pytest.mark.parametrize("precision,tols", [("fp64", (1e-12, 1e-12, 1e-12)),
                                              ("fp32c", (1e-3, 1e-5, 1e-6))])
+def test_3d_tile_margin_along_x(precision, tols):
+    """The tile region's margin along x: 2 cells in FP32 mode, 1 in FP64.  A
+    light beam (its own field negligible) starts in the last x cell of its
+    tile (x in [7.15, 7.25)) at w_x = 1 (0.318 cells per step; a transverse
+    spread of 0.01 makes every field component physical) and is sorted
+    only when loaded.  Steps 7 and 8 start with every particle in cell 9, two
+    cells past its tile: inside the FP32 region, so no particle is a migrant;
+    outside the FP64 one, so every particle is (the capacity leaves room in
+    the one bucket they all enter).  Against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(4343))
+    nx, ny, nz, n = 32, 16, 16, 2000
+    x = np.stack([7.15 + 0.1 * rng.random(n), 8.0 * rng.random(n), 8.0 * rng.random(n)])
+    w = rng.normal(0.0, 0.01, (3, n))
+    w[0] += 1.0
+    weight = np.full(n, 1e-6)
+    sim = _sim(nx=nx, ny=ny, nz=nz, dt=0.45, dims=3, precision=precision, sort_every=0)
+    se = sim.add_species(-1.0, 1.0, 16 * n)
+    sim.load(se, x, w, weight)
+    si = sim.add_species(1.0, 100.0, 0, mobile=False)
+    sim.load(si, x, np.zeros_like(w), weight)
+    st = oracle.State(oracle.Grid(nx, ny, nz, 0.45),
+                      [oracle.Species(x, w, weight, q=-1.0, m=1.0),
+                       oracle.Species(x, np.zeros_like(w), weight, q=1.0, m=100.0, mobile=False)])
+    sim.step(6)
+    st.step(6)
+    xs = sim.particles(0)[0]
+    assert np.all((xs[0] >= 9.0) & (xs[0] < 9.25)), (xs[0].min(), xs[0].max())
+    sim.step(2)   # statistics of this call: the steps that start in cell 9
+    st.step(2)
+    mig = sim.migrant_fraction()
+    if precision == "fp32c":
+        assert mig == 0.0, mig
+    else:
+        assert mig > 0.99, mig
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz)
+    _compare(sim, st, wl, *tols)
+
+
+@pytest.mark.parametrize("precision,tols", [("fp64", (1e-12, 1e-12, 1e-12)),
+                                             ("fp32c", (1e-3, 1e-5, 1e-6))])
 def test_3d_crowded_cell_parity(precision, tols):
     """600 electrons packed in one cell, beamed along +x, among a uniform
     background: a wave chunk holds far more particles of one lane class
