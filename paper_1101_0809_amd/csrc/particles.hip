@@ -531,6 +531,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     constexpr int C = lane_classes<R>();
     constexpr int CJ = 16;  // classes of the FP64 current tile
     constexpr unsigned kRankBits = 27;  // migrant list entry: rank | neighbour code << 27
+    constexpr uint32_t kPlaced = 0xffffffffu;  // migrant list entry already in its bucket (code 31)
     static_assert(NT % 256 == 0 && WCH <= 256 && C <= 32, "wave chunk layout");
     static_assert(TL::LFY == 12 && fplane0(5) + 12 == kFieldPlanes3, "z planes of the 3D field tile");
     __shared__ R sf[kFieldPlanes3 * TL::FPLANE];
@@ -581,30 +582,16 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
 
     // Classify slot sl (cell ci): true if its cell lies in the tile region,
     // with its lane class; otherwise the particle joins the tile's migrant
-    // list with its rank among the migrants to its new tile (a tile further
-    // away than a neighbour takes its bucket slot at once).
+    // list, whose entries are placed after the particle loop (a wave with one
+    // migrant would otherwise run the whole placement with its other lanes
+    // idle).
     auto classify = [&](int sl, const int ci[3], int& cls) -> bool {
         int rel[3];
         if (relative3<R>(g, T0, ci, rel)) {
             cls = cell_class3<R>(rel[0], rel[1], rel[2]);
             return true;
         }
-        const int code = neighbour_code3(g, tx, ty, tz, ci);
-        const unsigned r = code >= 0 ? atomicAdd(&mg_n[code], 1u) : 0u;
-        if (code >= 0 && r < (1u << kRankBits)) {
-            const unsigned e = atomicAdd(&ml_n, 1u);
-            mslot[e] = (uint32_t)sl;
-            mword[e] = r | ((uint32_t)code << kRankBits);
-            return false;
-        }
-        const int dt = tile_of3(g, ci);
-        const unsigned rr = atomicAdd(&a.mig_n[dt], 1u);
-        if (rr < a.mig_cap) {
-            a.mig[(int64_t)dt * a.mig_cap + rr] = (uint32_t)(begin + sl);
-            ++my_migrant;
-        } else {
-            qother[atomicAdd(&qo_n, 1u)] = (uint32_t)sl;
-        }
+        mslot[atomicAdd(&ml_n, 1u)] = (uint32_t)sl;
         return false;
     };
 
@@ -738,13 +725,37 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
         }
     }
     __syncthreads();
-    // the tile's migrants into the buckets of their new tiles: one reservation
-    // per neighbour tile, then the list
+    // The tile's migrants into the buckets of their new tiles.  First each
+    // migrant's rank among those to its neighbour tile (a tile further away
+    // takes its bucket slot at once); then one reservation per neighbour
+    // tile; then the bucket entries.
+    for (int e = threadIdx.x; e < (int)ml_n; e += NT) {
+        const uint32_t sl = mslot[e];
+        int ci[3];
+        PosIO<R, 3>::cell(a, begin + sl, ci);
+        const int code = neighbour_code3(g, tx, ty, tz, ci);
+        const unsigned r = code >= 0 ? atomicAdd(&mg_n[code], 1u) : 0u;
+        if (code >= 0 && r < (1u << kRankBits)) {
+            mword[e] = r | ((uint32_t)code << kRankBits);
+            continue;
+        }
+        mword[e] = kPlaced;
+        const int dt = tile_of3(g, ci);
+        const unsigned rr = atomicAdd(&a.mig_n[dt], 1u);
+        if (rr < a.mig_cap) {
+            a.mig[(int64_t)dt * a.mig_cap + rr] = (uint32_t)(begin + sl);
+            ++my_migrant;
+        } else {
+            qother[atomicAdd(&qo_n, 1u)] = sl;
+        }
+    }
+    __syncthreads();
     if (threadIdx.x < 27 && mg_n[threadIdx.x])
         mg_base[threadIdx.x] = atomicAdd(&a.mig_n[neighbour_tile3(g, tx, ty, tz, threadIdx.x)], mg_n[threadIdx.x]);
     __syncthreads();
     for (int e = threadIdx.x; e < (int)ml_n; e += NT) {
         const uint32_t word = mword[e];
+        if (word == kPlaced) continue;
         const int code = (int)(word >> kRankBits);
         const unsigned r = mg_base[code] + (word & ((1u << kRankBits) - 1u));
         if (r < a.mig_cap) {
