@@ -520,9 +520,9 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     constexpr int NW = NT / 64;  // waves
     constexpr int WCH = 64 * KC;  // slots per wave chunk
     // class rows ordered per wave chunk; higher ranks follow in arrival order.
-    // A chunk averages 4 particles per class, so a class fills more than 10
-    // rows in about 0.3% of chunks.
-    constexpr int RW = 10;
+    // A chunk averages 4 (FP64) or 6 (FP32) particles per class; a class
+    // fills more than 10, or 12, rows in under 1% of chunks.
+    constexpr int RW = 64 * KC / lane_classes<R>() >= 6 ? 12 : 10;
     using TL = Tile3Dims<R>;
     constexpr int T = kTile3, MX = TL::MX, M = TL::M;  // margins along x; along y and z
     constexpr int LJX = TL::LJX, LJY = TL::LJY;  // current region: T0-2-M .. T0+T+1+M per axis
@@ -1232,7 +1232,7 @@ StepArgs step_args(const Ctx& c, const Species& sp, unsigned long long* counters
 constexpr int kThreads3 = 768;    // FP64: 3 waves per SIMD, <= 170 VGPRs
 constexpr int kThreads3f = 1024;  // FP32: 4 waves per SIMD
 constexpr int kChunk3 = 1;        // FP64: slots per lane and wave chunk
-constexpr int kChunk3f = 2;       // FP32: slots per lane and wave chunk
+constexpr int kChunk3f = 3;       // FP32: slots per lane and wave chunk
 constexpr int kThreadsMig = 768;   // migrant pass, FP64 (as many waves as the step kernel)
 constexpr int kThreadsMigf = 1024; // migrant pass, FP32
 constexpr int kThreads2 = 256;
