@@ -280,9 +280,12 @@ constexpr int64_t kUnmapped = (int64_t)1 << 62;  // crossing entry not in the cl
 // (144 global atomics each).
 constexpr unsigned kMigLds = 8;
 
-// Stage E^n and B^n of the 3D tile region into LDS, with SK loads of a thread
-// in flight before their stores (one load at a time would wait out the
-// memory latency once per value).
+// Stage E^n and B^n of the 3D tile region into LDS.  The region is a set of
+// rows of at most 16 x values (69 stored planes x LFY rows): 16 lanes take a
+// row, each lane one x column, so a lane wraps its x coordinate once and
+// each row is decoded once.  SK rows' loads of a thread are in flight before
+// their stores (one load at a time would wait out the memory latency once per
+// value).
 template <class R, int NT>
 __device__ __forceinline__ void stage_fields3(const GridK& g, const int T0[3], const double* __restrict__ fields,
                                               const double* __restrict__ bfield, R* sf, bool small)
@@ -290,26 +293,27 @@ __device__ __forceinline__ void stage_fields3(const GridK& g, const int T0[3], c
     using TL = Tile3Dims<R>;
     constexpr int MX = TL::MX, M = TL::M, LFX = TL::LFX, LFY = TL::LFY;
     constexpr int SFY = TL::FROW, SFZ = TL::FPLANE;
-    constexpr int NV = kFieldPlanes3 * LFX * LFY;
+    constexpr int RPP = NT / 16;                 // rows per pass of the workgroup
+    constexpr int NROWS = kFieldPlanes3 * LFY;  // (stored plane, row) pairs
     constexpr int SK = 7;
+    static_assert(LFX <= 16 && NT % 64 == 0, "a field-tile row fits 16 lanes");
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
-    for (int e0 = threadIdx.x; e0 < NV; e0 += SK * NT) {
+    const int lx = (int)threadIdx.x & 15;
+    const int gx = wr(T0[0] - 1 - MX + (lx < LFX ? lx : 0), nx);
+    for (int r0 = lx < LFX ? (int)threadIdx.x >> 4 : NROWS; r0 < NROWS; r0 += SK * RPP) {
         double v[SK];
         int li[SK];
 #pragma unroll
         for (int u = 0; u < SK; ++u) {
-            const int e = e0 + u * NT;
+            const int r = r0 + u * RPP;
             li[u] = -1;
-            if (e < NV) {
-                const int pl = e / (LFX * LFY);
-                const int rr = e - pl * (LFX * LFY);
-                const int ly = rr / LFX;
-                const int lx = rr - ly * LFX;
+            if (r < NROWS) {
+                const int pl = r / LFY;
+                const int ly = r - pl * LFY;
                 const int comp = pl < 12 ? 0 : (pl < 24 ? 1 : (pl < 35 ? 2 : (pl < 46 ? 3 : (pl < 57 ? 4 : 5))));
                 const int lz = pl - fplane0(comp) + fnodez(comp);
-                const int gx = wr(T0[0] - 1 - MX + lx, nx);
                 const int gy = wr(T0[1] - 1 - M + ly, ny);
                 const int gz = wr(T0[2] - 1 - M + lz, nz);
                 v[u] = (comp < 3 ? fields + comp * N : bfield + (comp - 3) * N)[((int64_t)gz * ny + gy) * nx + gx];
@@ -322,29 +326,32 @@ __device__ __forceinline__ void stage_fields3(const GridK& g, const int T0[3], c
     }
 }
 
-// Flush the LDS current tile of a 3D tile into the grid's J (the plane
-// padding is never written).
+// Flush the LDS current tile of a 3D tile into the grid's J: 16 lanes per
+// row of the tile, one x column each (the padding is never written); only
+// the non-zero entries take a global atomic.
 template <class R, int NT, class LJT>
 __device__ __forceinline__ void flush_current3(const GridK& g, const int T0[3], const LJT& sj,
                                                double* __restrict__ Jg, bool small)
 {
     using TL = Tile3Dims<R>;
-    constexpr int MX = TL::MX, M = TL::M;
+    constexpr int MX = TL::MX, M = TL::M, LJX = TL::LJX, LJY = TL::LJY;
     constexpr int SJY = TL::JROW, SJZ = TL::JPLANE;
     constexpr int NJ = TL::NJ;
+    constexpr int RPP = NT / 16;
+    constexpr int NROWS = 3 * LJY * LJY;  // (component, plane, row)
+    static_assert(LJX <= 16 && NT % 64 == 0, "a current-tile row fits 16 lanes");
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
-    for (int e = threadIdx.x; e < 3 * NJ; e += NT) {
-        const double v = sj.get(e);
+    const int lx = (int)threadIdx.x & 15;
+    const int gx = wr(T0[0] - 2 - MX + (lx < LJX ? lx : 0), nx);
+    for (int r = lx < LJX ? (int)threadIdx.x >> 4 : NROWS; r < NROWS; r += RPP) {
+        const int comp = r / (LJY * LJY);
+        const int rr = r - comp * (LJY * LJY);
+        const int lz = rr / LJY;
+        const int ly = rr - lz * LJY;
+        const double v = sj.get(comp * NJ + lz * SJZ + ly * SJY + lx);
         if (v == 0.0) continue;
-        const int comp = e / NJ;
-        const int r = e - comp * NJ;
-        const int lz = r / SJZ;
-        const int rr = r - lz * SJZ;
-        const int ly = rr / SJY;
-        const int lx = rr - ly * SJY;
-        const int gx = wr(T0[0] - 2 - MX + lx, nx);
         const int gy = wr(T0[1] - 2 - M + ly, ny);
         const int gz = wr(T0[2] - 2 - M + lz, nz);
         global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
