@@ -331,8 +331,9 @@ int pic_sort(pic_ctx* ctx, void* stream);
 double pic_last_fallback_fraction(pic_ctx* ctx, void* stream);
 
 /* Tuning of the 3D particle step: fraction of particle updates during the
- * last pic_step call that were made by the migrant pass (particles found more
- * than one cell outside their sorted tile, advanced with the LDS tiles of
+ * last pic_step call that were made by the migrant pass (particles found
+ * outside their sorted tile's region -- more than one cell off the tile, or
+ * in FP32 mode more than two along x -- and advanced with the LDS tiles of
  * the tile that holds them now), or -1 if not recorded.  Synchronizes the
  * stream. */
 double pic_last_migrant_fraction(pic_ctx* ctx, void* stream);
