@@ -25,9 +25,10 @@ namespace pic {
 namespace {
 
 // ---------------------------------------------------------------------------
-// LDS current storage.  Both precisions accumulate in FP64: an FP32
-// contribution is exact in FP64, so the tile sums carry only FP64 rounding
-// (relative 2^-53 per add).  This is the compensated accumulation of the FP32
+// LDS current storage.  Both precisions accumulate in FP64.  In FP32 mode a
+// contribution is the product of two FP32 factors, formed in FP64, where it
+// is exact, so the tile sums carry only FP64 rounding (relative 2^-53 per
+// add).  This is the compensated accumulation of the FP32
 // mode: a hi/lo pair of FP32 arrays updated by two-sum from the atomic's
 // returned old value moves the same LDS bytes per contribution but needs the
 // round trip of a returning atomic, and measured about ten times slower.
@@ -36,7 +37,7 @@ template <class R, int NJ>
 struct LdsJ {
     double v[NJ];
     __device__ __forceinline__ void zero(int i) { v[i] = 0.0; }
-    __device__ __forceinline__ void add(int i, R x) { atomicAdd(&v[i], (double)x); }
+    __device__ __forceinline__ void add(int i, double x) { atomicAdd(&v[i], x); }
     __device__ __forceinline__ double get(int i) const { return v[i]; }
 };
 
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
 
         if (inside) {
             const int jb = (s[0] + 2 + M) + (s[1] + 2 + M) * SJY + (D == 3 ? (s[2] + 2 + M) * SJZ : 0);
-            auto S = [&](int comp, int ix, int iy, int iz, R v) {
+            auto S = [&](int comp, int ix, int iy, int iz, double v) {
                 sj.add(comp * NJ + jb + ix + iy * SJY + (D == 3 ? iz * SJZ : 0), v);
             };
             if (D == 3) deposit3<R>(dm, dp, jfac, S);
@@ -194,8 +195,8 @@ __global__ __launch_bounds__(NT) void k_particle_step(GridK g, StepArgs a, const
                 yj[o] = wrapi(T0[1] + s[1] + o, ny) * nx;
                 zk[o] = D == 3 ? (int64_t)wrapi(T0[2] + s[2] + o, nz) * nx * ny : 0;
             }
-            auto S = [&](int comp, int ix, int iy, int iz, R v) {
-                global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
+            auto S = [&](int comp, int ix, int iy, int iz, double v) {
+                global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], v);
             };
             if (D == 3) deposit3<R>(dm, dp, jfac, S);
             else deposit2<R>(dm, dp, jfac, jz2, S);
@@ -273,6 +274,15 @@ __host__ __device__ constexpr int fplane0(int comp)  // first stored plane of a 
     return comp < 2 ? 12 * comp : (comp < 5 ? 24 + 11 * (comp - 2) : 57);
 }
 __host__ __device__ constexpr int fnodez(int comp) { return comp >= 2 && comp <= 4 ? 1 : 0; }
+// Lowest offset of the gather stencil of a component along an axis: 0 where
+// the component takes node factors along it (two points), -1 where it takes
+// cell factors (three points).
+__host__ __device__ constexpr int lo_offset(int comp, int ax)
+{
+    // bit ax set: node factors along ax (E^x, E^y, E^z, B^x, B^y, B^z)
+    const int node = comp == 0 ? 1 : comp == 1 ? 2 : comp == 2 ? 4 : comp == 3 ? 6 : comp == 4 ? 5 : 3;
+    return (node >> ax) & 1 ? 0 : -1;
+}
 constexpr int kFieldPlanes3 = 69;  // 12 + 12 + 11 + 11 + 11 + 12
 constexpr int64_t kUnmapped = (int64_t)1 << 62;  // crossing entry not in the class map
 // A migrant bucket this full is advanced with LDS tiles.  Staging the tile and
@@ -441,8 +451,28 @@ __device__ __forceinline__ void advance_lds3(const GridK& g, const StepArgs& a, 
     for (int ax = 0; ax < 3; ++ax) ax0[ax] = form_factor<R>(d0[ax]);
     R E[3], B[3];
     const int base = (rel[0] + 1 + MX) + (rel[1] + 1 + M) * SFY + (rel[2] + 1 + M) * SFZ;
+    // One base register per component at the lowest point of its stencil,
+    // and a second two planes up where the stencil spans three z planes:
+    // every point is then a small immediate offset of a base (a paired LDS
+    // read reaches 255 elements), where the compiler would otherwise derive
+    // a new base for most rows.
+    using LP = __attribute__((address_space(3))) const R*;
+    LP lo[6], hi[6];
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp) {
+        const int c0 = (fplane0(comp) - fnodez(comp)) * SFZ + base + lo_offset(comp, 0) +
+                       lo_offset(comp, 1) * SFY + lo_offset(comp, 2) * SFZ;
+        lo[comp] = (LP)(sf + c0);
+        asm("" : "+v"(lo[comp]));
+        if (!fnodez(comp)) {
+            hi[comp] = (LP)(sf + c0 + 2 * SFZ);
+            asm("" : "+v"(hi[comp]));
+        }
+    }
+    static_assert(2 + 2 * SFY + SFZ <= 255, "a stencil's two lower z planes in reach of one base");
     auto F = [&](int comp, int da, int db, int dc) -> R {
-        return sf[(fplane0(comp) - fnodez(comp)) * SFZ + base + da + db * SFY + dc * SFZ];
+        const int a = da - lo_offset(comp, 0), b = db - lo_offset(comp, 1), c = dc - lo_offset(comp, 2);
+        return c == 2 ? hi[comp][a + b * SFY] : lo[comp][a + b * SFY + c * SFZ];
     };
     gather3<R>(ax0, F, E, B);
     for (int ax = 0; ax < 3; ++ax) B[ax] += (R)g.bext[ax];
@@ -514,8 +544,8 @@ __device__ __forceinline__ void advance_global3(const GridK& g, const StepArgs& 
         yj[o] = wrapi(i0[1] + (delta[1] < 0 ? -1 : 0) - 1 + o, ny) * nx;
         zk[o] = (int64_t)wrapi(i0[2] + (delta[2] < 0 ? -1 : 0) - 1 + o, nz) * nx * ny;
     }
-    auto S = [&](int comp, int ix, int iy, int iz, R v) {
-        global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
+    auto S = [&](int comp, int ix, int iy, int iz, double v) {
+        global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], v);
     };
     deposit3<R>(dm, dp, jfac, S);
 }
@@ -629,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
                     for (int k = 0; k < 3; ++k) s0[ax][k] = ax0[ax].s[k];
                 }
                 const int jb = (rel[0] + 1 + MX) + (rel[1] + 1 + M) * SJY + (rel[2] + 1 + M) * SJZ;
-                auto S = [&](int comp, int ix, int iy, int iz, R v) {
+                auto S = [&](int comp, int ix, int iy, int iz, double v) {
                     sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
                 };
                 deposit3_still<R>(s0, s1, jfac, S);
@@ -811,7 +841,7 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
             int sw[3];
             for (int ax = 0; ax < 3; ++ax) sw[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
             const int jb = (sw[0] + 2 + MX) + (sw[1] + 2 + M) * SJY + (sw[2] + 2 + M) * SJZ;
-            auto S = [&](int comp, int ix, int iy, int iz, R v) {
+            auto S = [&](int comp, int ix, int iy, int iz, double v) {
                 sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
             };
             if (sec == 0) deposit3_axis<0, R>(dm, dp, jfac, S);
@@ -923,7 +953,7 @@ __global__ __launch_bounds__(NT) void k_migrants3(GridK g, StepArgs a, const dou
         int s[3];
         for (int ax = 0; ax < 3; ++ax) s[ax] = rel[ax] + (delta[ax] < 0 ? -1 : 0) - 1;
         const int jb = (s[0] + 2 + MX) + (s[1] + 2 + M) * SJY + (s[2] + 2 + M) * SJZ;
-        auto S = [&](int comp, int ix, int iy, int iz, R v) {
+        auto S = [&](int comp, int ix, int iy, int iz, double v) {
             sj.add(comp * NJ + jb + ix + iy * SJY + iz * SJZ, v);
         };
         deposit3<R>(dm, dp, jfac, S);
@@ -991,8 +1021,8 @@ __global__ __launch_bounds__(256) void k_deposit_pairs(GridK g, const double* __
         yj[o] = wrapi(s[1] + o, ny) * nx;
         zk[o] = D == 3 ? (int64_t)wrapi(s[2] + o, nz) * nx * ny : 0;
     }
-    auto S = [&](int comp, int ix, int iy, int iz, R v) {
-        global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], (double)v);
+    auto S = [&](int comp, int ix, int iy, int iz, double v) {
+        global_add(&Jg[comp * N + zk[iz] + yj[iy] + xi[ix]], v);
     };
     if (D == 3) deposit3<R>(dm, dp, jfac, S);
     else deposit2<R>(dm, dp, jfac, jz2, S);

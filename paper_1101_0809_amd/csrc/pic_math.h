@@ -218,7 +218,9 @@ __device__ __forceinline__ void push(R qmdt2, R c2, const R E[3], const R B[3], 
 // the cumulative difference at face s+t+1 is P_t = sum_{t' <= t} dm_t'
 // (t = 0..2; the face s+4 gets sum of all dm = 0).  The last prefix is taken
 // as -dm_3, which is the same value and exactly zero whenever the window's
-// last cell is empty.
+// last cell is empty.  A contribution is the face factor P_t times the
+// transverse factor; both are converted to FP64 once and the product is
+// formed there (exact for FP32 factors), and handed to the sink as FP64.
 // ---------------------------------------------------------------------------
 template <class R>
 __device__ __forceinline__ void window(const R s0[3], const R s1[3], int delta, R dm[4], R dp[4])
@@ -252,14 +254,13 @@ __device__ __forceinline__ void deposit3(const R (&dm)[3][4], const R (&dp)[3][4
         for (int t = 0; t < 4; ++t) m3[a][t] = dm[a][t] * third;
     for (int comp = 0; comp < 3; ++comp) {
         const int u = (comp + 1) % 3, v = (comp + 2) % 3;
-        R P[3];
-        P[0] = dm[comp][0];
-        P[1] = dm[comp][0] + dm[comp][1];
-        P[2] = -dm[comp][3];
-        for (int t = 0; t < 3; ++t) P[t] *= jfac[comp];
+        double P[3];
+        P[0] = dm[comp][0] * jfac[comp];
+        P[1] = (dm[comp][0] + dm[comp][1]) * jfac[comp];
+        P[2] = -dm[comp][3] * jfac[comp];
         for (int b = 0; b < 4; ++b)
             for (int c = 0; c < 4; ++c) {
-                const R tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
+                const double tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
                 for (int t = 0; t < 3; ++t) {
                     int ijk[3];
                     ijk[comp] = t + 1;
@@ -290,11 +291,11 @@ __device__ __forceinline__ void deposit3_still(const R (&s0)[3][3], const R (&s1
         }
     for (int comp = 0; comp < 3; ++comp) {
         const int u = (comp + 1) % 3, v = (comp + 2) % 3;
-        const R P0 = dm[comp][0] * jfac[comp];
-        const R P1 = (dm[comp][0] + dm[comp][1]) * jfac[comp];
+        const double P0 = dm[comp][0] * jfac[comp];
+        const double P1 = (dm[comp][0] + dm[comp][1]) * jfac[comp];
         for (int b = 0; b < 3; ++b)
             for (int c = 0; c < 3; ++c) {
-                const R tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
+                const double tr = dp[u][b] * dp[v][c] + m3[u][b] * dm[v][c];
                 int ijk[3];
                 ijk[u] = b;
                 ijk[v] = c;
@@ -320,14 +321,13 @@ __device__ __forceinline__ void deposit3_axis(const R (&dm)[3][4], const R (&dp)
         const int u = (comp + 1) % 3, v = (comp + 2) % 3;
         const int nt = comp == A ? 3 : 2;
         const int nb = u == A ? 4 : 3, nc = v == A ? 4 : 3;
-        R P[3];
-        P[0] = dm[comp][0];
-        P[1] = dm[comp][0] + dm[comp][1];
-        P[2] = -dm[comp][3];
-        for (int t = 0; t < 3; ++t) P[t] *= jfac[comp];
+        double P[3];
+        P[0] = dm[comp][0] * jfac[comp];
+        P[1] = (dm[comp][0] + dm[comp][1]) * jfac[comp];
+        P[2] = -dm[comp][3] * jfac[comp];
         for (int b = 0; b < nb; ++b)
             for (int c = 0; c < nc; ++c) {
-                const R tr = dp[u][b] * dp[v][c] + (dm[u][b] * third) * dm[v][c];
+                const double tr = dp[u][b] * dp[v][c] + (dm[u][b] * third) * dm[v][c];
                 for (int t = 0; t < nt; ++t) {
                     int ijk[3];
                     ijk[comp] = t + 1;
@@ -359,12 +359,12 @@ __device__ __forceinline__ void deposit2(const R (&dm)[3][4], const R (&dp)[3][4
                 int ij[2];
                 ij[comp] = t + 1;
                 ij[u] = b;
-                S(comp, ij[0], ij[1], 0, P[t] * dp[u][b]);
+                S(comp, ij[0], ij[1], 0, (double)(P[t] * dp[u][b]));
             }
     }
     for (int a = 0; a < 4; ++a) {
         const R mx = dm[0][a] * third;
-        for (int b = 0; b < 4; ++b) S(2, a, b, 0, jz * (dp[0][a] * dp[1][b] + mx * dm[1][b]));
+        for (int b = 0; b < 4; ++b) S(2, a, b, 0, (double)(jz * (dp[0][a] * dp[1][b] + mx * dm[1][b])));
     }
 }
 
