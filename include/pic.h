@@ -58,9 +58,10 @@ enum pic_status {
 
 enum pic_precision {
     PIC_FP64 = 0,  /* particles as FP64 absolute positions; all arithmetic FP64 */
-    PIC_FP32C = 1  /* particles as int cell + FP32 offset; gather, push and current
-                      contributions in FP32; contributions summed in FP64 (exact for
-                      FP32 terms) in the LDS tile; grid and reductions FP64 */
+    PIC_FP32C = 1  /* particles as int cell + FP32 offset; gather, push and the
+                      current's factors in FP32; each contribution the FP64 product
+                      of two FP32 factors (exact), summed in FP64 in the LDS tile;
+                      grid and reductions FP64 */
 };
 
 enum pic_field_op {
