@@ -294,14 +294,17 @@ def measured_traffic(precision: str, workload: str):
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"k_particle_step_{workload}.md")
-    src = os.path.join(ROOT, "paper_1101_0809_amd", "csrc", "particles.hip")
     if not os.path.exists(path):
         return None
     m = re.search(r"<!-- traffic-json (\{.*\}) -->", open(path).read())
     if not m:
         return None
     info = json.loads(m.group(1))
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    # the step kernels' sources: the kernel file and the two headers it builds on
+    h = hashlib.sha256()
+    for name in ("particles.hip", "pic_math.h", "pic_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1101_0809_amd", "csrc", name), "rb").read())
+    digest = h.hexdigest()[:16]
     if info.get("source_sha256_16") != digest:
         return None
     return info["traffic"].get(precision)

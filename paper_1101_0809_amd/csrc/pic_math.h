@@ -903,7 +903,8 @@ struct PosIO<float, D> {
             i1[ax] = c;
             if (store) ((float*)a.pos[ax])[p] = o;
         }
-        if (store) a.cell[p] = pack_cell(i1[0], i1[1], i1[2]);
+        // a particle that stays in its cell keeps its stored cell word
+        if (store && (delta[0] | delta[1] | delta[2])) a.cell[p] = pack_cell(i1[0], i1[1], i1[2]);
     }
 };
 
