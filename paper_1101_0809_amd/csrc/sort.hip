@@ -340,13 +340,20 @@ __global__ __launch_bounds__(kTile3 * kTile3 * kTile3) void k_dest3(const uint32
 
 // Which particle fills each final slot: the inverse of the final-slot map, by
 // one 4-byte scatter, so that the move writes every slot once, in order.
+// Each XCD takes a contiguous run of particles: a tile's particles scatter
+// into the same few tile ranges of src, whose lines are then written whole
+// in one XCD's L2 rather than in pieces by all of them.
 __global__ __launch_bounds__(kSortThreads) void k_final_src(int64_t n, const uint32_t* __restrict__ key,
                                                             const uint32_t* __restrict__ rank,
                                                             const uint32_t* __restrict__ offs,
                                                             const uint32_t* __restrict__ dest,
                                                             uint32_t* __restrict__ src)
 {
-    const int64_t p = (int64_t)blockIdx.x * kSortThreads + threadIdx.x;
+    const int nb = gridDim.x;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+    const int blk = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    const int64_t p = (int64_t)blk * kSortThreads + threadIdx.x;
     if (p >= n) return;
     src[dest[(int64_t)offs[key[p]] + rank[p]]] = (uint32_t)p;
 }
