@@ -123,3 +123,41 @@ def test_python_binding_imports_without_gpu():
     assert hasattr(mod, "Sim")
     import bench  # noqa: F401  (the benchmark module must import cleanly too)
     import __graft_entry__  # noqa: F401
+
+
+def test_committed_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
+    """bench.py reports the committed HBM traffic only while the recorded hash
+    matches the step kernels' sources: a change to any of the three files,
+    the kernel file or either header, turns it off."""
+    import hashlib
+    import json
+    import shutil
+
+    import bench
+
+    src = os.path.join(ROOT, "paper_1101_0809_amd", "csrc")
+    dst = tmp_path / "paper_1101_0809_amd" / "csrc"
+    dst.mkdir(parents=True)
+    names = ("particles.hip", "pic_math.h", "pic_internal.h")
+    for n in names:
+        shutil.copy(os.path.join(src, n), dst / n)
+
+    def digest():
+        h = hashlib.sha256()
+        for n in names:
+            h.update((dst / n).read_bytes())
+        return h.hexdigest()[:16]
+
+    (tmp_path / "profiles").mkdir()
+    info = {"source_sha256_16": digest(), "traffic": {"fp32c": 123, "fp64": 456}}
+    (tmp_path / "profiles" / "k_particle_step_w.md").write_text(f"x\n<!-- traffic-json {json.dumps(info)} -->\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("fp32c", "w") == 123
+    assert bench.measured_traffic("fp64", "w") == 456
+    assert bench.measured_traffic("fp32c", "other") is None
+    for n in names:
+        before = (dst / n).read_bytes()
+        (dst / n).write_bytes(before + b"\n")
+        assert bench.measured_traffic("fp32c", "w") is None, n
+        (dst / n).write_bytes(before)
+    assert bench.measured_traffic("fp32c", "w") == 123
