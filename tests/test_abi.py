@@ -75,6 +75,9 @@ def test_query_sizes():
     (dict(interp=1, order=2), -1),          # conventional: order 1 only
     (dict(interp=1, precision=1), -1),      # conventional: FP64 only
     (dict(precision=1, nx=4096), -1),        # FP32 cell packing limit
+    (dict(precision=1, nx=2049), -1),        # 11 bits for the x cell
+    (dict(precision=1, ny=2049), -1),        # 11 bits for the y cell
+    (dict(precision=1, nz=1025), -1),        # 10 bits for the z cell
     (dict(dx=-1.0), -1),
 ])
 def test_invalid_descriptions_rejected(kw, code):
@@ -88,6 +91,14 @@ def test_invalid_descriptions_rejected(kw, code):
     rc2 = lib.pic_init_grid(ctypes.byref(_desc(L, **kw)), ctypes.cast(buf, ctypes.c_void_p), 16,
                             ctypes.cast(buf, ctypes.c_void_p), 16, ctypes.byref(ctx))
     assert rc2 == code and not ctx.value
+
+
+@pytest.mark.parametrize("kw", [dict(nx=2048), dict(ny=2048), dict(nz=1024)])
+def test_fp32_mode_accepts_its_largest_axes(kw):
+    """The packed FP32 cell word's limits themselves are accepted."""
+    L, lib = _lib()
+    sz = L.Sizes()
+    assert lib.pic_query_sizes(ctypes.byref(_desc(L, precision=L.PIC_FP32C, **kw)), 10, ctypes.byref(sz)) == 0
 
 
 def test_two_dimensional_courant_ignores_z():

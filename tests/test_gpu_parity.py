@@ -239,6 +239,41 @@ def test_3d_tile_margin_along_x(precision, tols):
     _compare(sim, st, wl, *tols)
 
 
+@pytest.mark.parametrize("axis,dims3", [(0, (2048, 16, 16)), (1, (16, 2048, 16)), (2, (16, 16, 1024))])
+@pytest.mark.parametrize("precision,tols", [("fp64", (1e-12, 1e-12, 1e-12)),
+                                             ("fp32c", (1e-3, 1e-5, 1e-6))])
+def test_3d_largest_axis_wrap(precision, tols, axis, dims3):
+    """The largest axes the FP32 cell word holds (11 + 11 + 10 bits: 2048
+    cells along x and y, 1024 along z).  A light beam starts in the last two
+    cells of the long axis at 1 c (0.32 cells per step) and crosses its
+    periodic boundary, so the highest packed cell index and its wrap to
+    cell 0 are stored, sorted (every 3 steps) and advanced.  Against the
+    oracle."""
+    rng = np.random.Generator(np.random.PCG64(4545 + axis))
+    n = 2000
+    L = dims3[axis]
+    x = np.stack([dims3[a] * rng.random(n) for a in range(3)])
+    x[axis] = (L - 1.6) + 1.5 * rng.random(n)
+    w = rng.normal(0.0, 0.01, (3, n))
+    w[axis] += 1.0
+    weight = np.full(n, 1e-4)
+    nx, ny, nz = dims3
+    sim = _sim(nx=nx, ny=ny, nz=nz, dt=0.45, dims=3, precision=precision, sort_every=3)
+    se = sim.add_species(-1.0, 1.0, n)
+    sim.load(se, x, w, weight)
+    si = sim.add_species(1.0, 100.0, 0, mobile=False)
+    sim.load(si, x, np.zeros_like(w), weight)
+    st = oracle.State(oracle.Grid(nx, ny, nz, 0.45),
+                      [oracle.Species(x, w, weight, q=-1.0, m=1.0),
+                       oracle.Species(x, np.zeros_like(w), weight, q=1.0, m=100.0, mobile=False)])
+    sim.step(9)
+    st.step(9)
+    xs = sim.particles(0)[0][axis]
+    assert np.mean(xs < 3.0) > 0.95, np.mean(xs < 3.0)   # the beam wrapped to the start of the axis
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz)
+    _compare(sim, st, wl, *tols)
+
+
 @pytest.mark.parametrize("precision,tols", [("fp64", (1e-12, 1e-12, 1e-12)),
                                              ("fp32c", (1e-3, 1e-5, 1e-6))])
 def test_3d_crowded_cell_parity(precision, tols):
