@@ -68,6 +68,65 @@ def test_deposit_matches_oracle(precision, tol, dims):
     assert np.max(np.abs(J - ref)) / scale < tol
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32c", 3e-6)])
+@pytest.mark.parametrize("dims", [3, 2])
+def test_deposit_degenerate_moves(precision, tol, dims):
+    """pic_deposit_J on the method's degenerate moves: starts and ends exactly
+    on cell faces (offset 0), moves onto a face from either side, no move,
+    single-axis moves, a move ending exactly on the periodic boundary and
+    one leaving cell 0 downwards.  Integer and half-integer positions are
+    exact in FP32 too, so both precisions take the same inputs."""
+    n, ny = 16, 12
+    nz = n if dims == 3 else 1
+    box = np.array([n, ny, nz], dtype=float)[:, None]
+    rng = np.random.Generator(np.random.PCG64(7))
+    m = 64
+    cells = np.stack([rng.integers(0, b, m) for b in (n, ny, nz)]).astype(float)
+    half = rng.integers(-1, 2, (3, m)) * 0.5            # -0.5, 0, 0.5 per axis
+    frac = np.round(rng.uniform(0.05, 0.95, (3, m)) * 64) / 64
+    moves = []
+    moves.append((cells, cells + half))                  # face to face or to a mid-point
+    moves.append((cells + frac, np.floor(cells + frac)))  # onto the face below
+    moves.append((cells + frac, np.ceil(cells + frac)))   # onto the face above
+    moves.append((cells + frac, cells + frac))            # no move
+    for a in range(3):                                    # one axis at a time
+        x1 = cells + frac
+        x1 = x1.copy()
+        x1[a] = np.floor(x1[a]) if a % 2 else np.ceil(x1[a])
+        moves.append((cells + frac, x1))
+    edge0 = cells + frac
+    edge0[0] = n - 0.25
+    edge1 = edge0.copy()
+    edge1[0] = float(n)                                   # exactly onto the periodic boundary
+    moves.append((edge0, edge1))
+    low0 = cells + frac
+    low0[0] = 0.0
+    low1 = low0.copy()
+    low1[0] = -0.375                                      # from cell 0's lower face downwards
+    moves.append((low0, low1))
+    x0 = np.concatenate([a for a, _ in moves], axis=1)
+    x1 = np.concatenate([b for _, b in moves], axis=1)
+    if dims == 2:   # as in the random-move test: the z displacement halved
+        x1[2] = x0[2] + (x1[2] - x0[2]) * 0.5
+    assert np.all(np.abs(x1 - x0) < 1.0)
+    sim = _sim(nx=n, ny=ny, nz=nz, dt=0.41, dims=dims, precision=precision)
+    g = oracle.Grid(n, ny, nz, 0.41)
+    q = rng.uniform(-1, 1, x0.shape[1])
+    J = sim.deposit(x0, x1, q).cpu().numpy()
+    ref = np.zeros((3,) + g.shape)
+    for p in range(x0.shape[1]):
+        oracle.deposit(g, x0[:, p], x1[:, p], q[p], J=ref)
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    assert np.max(np.abs(J - ref)) / scale < tol
+    # a particle that does not move carries no current
+    still = np.zeros(x0.shape[1], bool)
+    k = 3 * m
+    still[k:k + m] = True
+    Js = sim.deposit(x0[:, still], x1[:, still], q[still]).cpu().numpy()
+    assert np.max(np.abs(Js)) == 0.0
+
+
 def test_field_solve_matches_oracle():
     n = (10, 9, 8)
     rng = np.random.Generator(np.random.PCG64(3))
@@ -235,6 +294,36 @@ def test_3d_tile_margin_along_x(precision, tols):
         assert mig == 0.0, mig
     else:
         assert mig > 0.99, mig
+    wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz)
+    _compare(sim, st, wl, *tols)
+
+
+@pytest.mark.parametrize("precision,tols", [("fp64", (1e-12, 1e-12, 1e-12)),
+                                             ("fp32c", (1e-3, 1e-5, 1e-6))])
+def test_3d_face_and_centre_starts(precision, tols):
+    """Particles that start exactly on cell faces (integer coordinates, offset
+    0: node factors (1, 0), cell factors (1/2, 1/2, 0)) or at cell centres
+    (offset 1/2), half of them at rest, among a random third; the immobile
+    ions sit at the electrons' starts.  10 steps, re-sorted every 4, against
+    the oracle."""
+    rng = np.random.Generator(np.random.PCG64(4646))
+    nx, ny, nz, m = 16, 16, 16, 3000
+    cells = np.stack([rng.integers(0, b, m) for b in (nx, ny, nz)]).astype(float)
+    x = np.concatenate([cells[:, :1000], cells[:, 1000:2000] + 0.5,
+                        cells[:, 2000:] + rng.random((3, 1000))], axis=1)
+    w = rng.normal(0.0, 0.2, (3, m))
+    w[:, ::2] = 0.0   # every other particle at rest
+    weight = np.full(m, 0.01)
+    sim = _sim(nx=nx, ny=ny, nz=nz, dt=0.45, dims=3, precision=precision, sort_every=4)
+    se = sim.add_species(-1.0, 1.0, m)
+    sim.load(se, x, w, weight)
+    si = sim.add_species(1.0, 100.0, 0, mobile=False)
+    sim.load(si, x, np.zeros_like(w), weight)
+    st = oracle.State(oracle.Grid(nx, ny, nz, 0.45),
+                      [oracle.Species(x, w, weight, q=-1.0, m=1.0),
+                       oracle.Species(x, np.zeros_like(w), weight, q=1.0, m=100.0, mobile=False)])
+    sim.step(10)
+    st.step(10)
     wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz)
     _compare(sim, st, wl, *tols)
 
