@@ -390,7 +390,9 @@ void orc_update_e(const orc_grid* g, double* fields)
  * staggered operators as the grid restricted to x (E^y at faces, B^z at
  * nodes), so a plane wave uniform in y and z evolves identically on both and
  * the correction terms below inject it without leakage into x < plane.
- * Aux index a sits at grid index src_plane - 2 + a.
+ * Aux index a sits at grid index src_plane - 2 + a.  Parity unpinned: the
+ * waveform's phase (a sine from t = 0) is this source's convention; the
+ * workload fixes only its amplitude and wavelength, which the pins check.
  * ------------------------------------------------------------------------- */
 static double src_wave(const orc_grid* g, double t)
 {

@@ -237,14 +237,18 @@ def test_single_particle_continuity(form, order):
 # Q5  whole-run Gauss law and div B invariants (Section 2)
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("cell", [(1.0, 1.0, 1.0), (1.0, 0.8, 1.25)])
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("shape", [(6, 5, 4), (8, 8, 1)])
-def test_gauss_and_divb_invariant(shape, order):
+def test_gauss_and_divb_invariant(shape, order, cell):
+    """Unequal cell sizes make every curl coefficient and divergence term
+    carry its own axis's size."""
     nx, ny, nz = shape
     wl = picgen.Workload("pin", nx, ny, nz, 3 if nz > 1 else 2, 0.45, 4, (0.2,) * 3, 0.3, 20)
     e = picgen.electrons(wl)
     ions = picgen.ions_like(wl, e)
-    st = oracle.State(oracle.Grid(nx, ny, nz, wl.dt, order=order),
+    dx, dy, dz = cell
+    st = oracle.State(oracle.Grid(nx, ny, nz, wl.dt, dx=dx, dy=dy, dz=dz, order=order),
                       [oracle.Species(e.x, e.w, e.weight, q=-1.0, m=1.0),
                        oracle.Species(ions.x, ions.w, ions.weight, q=1.0, m=100.0, mobile=False)])
     # start from a non-trivial field with zero divergence of B
@@ -259,6 +263,26 @@ def test_gauss_and_divb_invariant(shape, order):
     # positions stay in the box
     for a, n in enumerate(shape):
         assert np.all((st.species[0].x[a] >= 0) & (st.species[0].x[a] < n))
+
+
+def test_free_streaming_displacement():
+    """Eq. coordscheme on unequal cells: in zero field a particle advances
+    (w_a / gamma) c dt / h_a cells per step along axis a, with
+    gamma = sqrt(1 + w^2 / c^2).  The weights are so small that the
+    particles' own fields do not move them measurably."""
+    dx, dy, dz, dt = 1.0, 0.8, 1.25, 0.45
+    nx, ny, nz = 16, 20, 12
+    w = np.array([[0.3, -1.2, 2.5], [0.0, 0.7, -0.4], [-0.9, 0.05, 1.5]])
+    x0 = np.array([[3.2, 7.5, 12.9], [4.4, 10.1, 0.3], [6.7, 2.2, 9.8]])
+    st = oracle.State(oracle.Grid(nx, ny, nz, dt, dx=dx, dy=dy, dz=dz),
+                      [oracle.Species(x0.copy(), w.copy(), np.full(3, 1e-14), q=-1.0, m=1.0)])
+    n = 10
+    st.step(n)
+    gam = np.sqrt(1.0 + np.sum(w ** 2, axis=0))
+    for a, (h, L) in enumerate(((dx, nx), (dy, ny), (dz, nz))):
+        expect = np.mod(x0[a] + n * (w[a] / gam) * dt / h, L)
+        diff = (st.species[0].x[a] - expect + L / 2) % L - L / 2
+        assert np.max(np.abs(diff)) < 1e-9, (a, diff)
 
 
 # --------------------------------------------------------------------------
@@ -405,6 +429,27 @@ def test_conventional_interpolation_conserves_charge_but_not_energy():
         defects.append(abs(st.energies().sum() - tot0) / tot0)
     assert defects[0] < 1e-4
     assert defects[1] > 30 * defects[0], defects
+
+
+@pytest.mark.parametrize("dx", [1.0, 1.25])
+def test_field_energies_of_one_mode(dx):
+    """The field energies (Section 4.1) of one Fourier mode, in closed form.
+    E^y = A sin(2 pi m i / nx), uniform in y and z, and B^{n-1/2} = 0.  The
+    magnetic energy is taken at B^n, the stored B^{n-1/2} advanced half a step
+    by Eq. updateB: B^z = -(c dt / dx) A sin(pi m / nx) cos(2 pi m (i + s) / nx)
+    for a fixed stagger s, and B^x = B^y = 0.  Over the N cells of volume V,
+    V/(8 pi) sum (E^y)^2 = V/(8 pi) A^2 N / 2, and
+    V/(8 pi) sum (B^z)^2 = V/(8 pi) (c dt / dx)^2 A^2 sin^2(pi m / nx) N / 2."""
+    nx, ny, nz, m, A, dt = 16, 4, 3, 3, 0.7, 0.45
+    dy, dz = 0.8, 1.1
+    st = oracle.State(oracle.Grid(nx, ny, nz, dt, dx=dx, dy=dy, dz=dz), [])
+    st.fields[1] = A * np.sin(2 * np.pi * m * np.arange(nx) / nx)[None, None, :]
+    kin, half, fe, fb = st.energies()
+    V, N = dx * dy * dz, nx * ny * nz
+    assert kin == 0.0 and half == 0.0
+    assert fe == pytest.approx(V / (8 * np.pi) * A ** 2 * N / 2, rel=1e-13)
+    assert fb == pytest.approx(V / (8 * np.pi) * (dt / dx) ** 2 * A ** 2 * np.sin(np.pi * m / nx) ** 2 * N / 2,
+                               rel=1e-12)
 
 
 def test_half_step_energy_term_is_half_the_work_of_a_step():
@@ -671,6 +716,32 @@ def test_plane_wave_source_is_one_sided_and_exact():
         for c in (0, 2, 3, 4):
             assert np.max(np.abs(st.fields[c])) == 0.0
     assert np.max(np.abs(st.fields[1])) > 0.5 * omega   # the wave is there (ramp done)
+
+
+def test_plane_wave_source_amplitude_and_wavelength():
+    """The laser as the slab workload's statement fixes it: amplitude a0 = 1,
+    i.e. E = a0 omega in units with c = m = |q| = 1, and wavelength 20 cells.
+    In vacuum, past the ramp, the injected E^y has amplitude omega, and its
+    zeros are half a wavelength apart.  The wavelength is the grid's own,
+    from the dispersion relation sin(omega dt / 2) / (c dt) = sin(k dx / 2) / dx
+    (19.93 cells for 20 in vacuum).  The phase, a sine from t = 0, is this
+    source's convention: the statement does not fix it."""
+    n, plane, dt = 256, 8, 0.45
+    omega = 2 * math.pi / 20
+    ramp = 2 * math.pi / omega
+    st = oracle.State(oracle.Grid(n, 2, 2, dt, source=(plane, omega, omega, ramp)), [])
+    nsteps = 160
+    st.step(nsteps)
+    ey = st.fields[1][0, 0, :]
+    hi = plane + int((nsteps * dt - ramp) * 0.95)   # launched after the ramp, with a margin
+    assert hi - plane > 45
+    seg = ey[plane + 2:hi]
+    assert np.max(np.abs(seg)) == pytest.approx(omega, rel=0.02)
+    k = 2 * np.arcsin(np.sin(omega * dt / 2) / dt)
+    i = np.nonzero(np.sign(seg[:-1]) * np.sign(seg[1:]) < 0)[0]
+    zeros = i + seg[i] / (seg[i] - seg[i + 1])
+    assert len(zeros) >= 4
+    assert np.max(np.abs(np.diff(zeros) - np.pi / k)) < 0.05, (np.diff(zeros), np.pi / k)
 
 
 def test_plane_wave_source_keeps_gauss_and_divb():
