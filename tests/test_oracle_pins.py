@@ -782,6 +782,23 @@ def test_poisson_solution_satisfies_gauss_law_and_energy_identity():
     assert lhs == pytest.approx(rhs, rel=1e-12)
 
 
+def test_poisson_field_meets_the_step_gauss_law():
+    """The reference Poisson field, placed in a particle state, has the step's
+    own Gauss residual (Eq. chargelaw, pinned by the whole-run invariants)
+    equal to -4 pi <rho> in every cell: the uniform background the solve
+    removes.  This ties the module's face convention (E^x between cells i-1
+    and i) to the one the step and its deposit use."""
+    from oracle import poisson
+    wl = picgen.Workload("es", 10, 7, 6, 3, 0.3, 2, (0.1,) * 3, 0.3, 1, seed=12)
+    e = picgen.electrons(wl)
+    g = oracle.Grid(10, 7, 6, 0.3, dx=1.1, dy=0.8, dz=1.3)
+    st = oracle.State(g, [oracle.Species(e.x, e.w, e.weight, q=-1.0, m=1.0)])
+    rho = st.rho()
+    st.fields[0:3] = poisson.e_of_phi(g, poisson.solve(g, rho))
+    R = st.gauss_residual()
+    assert np.max(np.abs(R + 4 * np.pi * rho.mean())) < 1e-12 * np.max(np.abs(4 * np.pi * rho))
+
+
 def test_poisson_single_mode_closed_form():
     """rho = cos(2 pi m x / L) along x: Phi = 4 pi rho / lambda_m with the
     discrete eigenvalue lambda_m = (2 - 2 cos(2 pi m / N)) / dx^2."""
