@@ -338,6 +338,18 @@ __global__ __launch_bounds__(kTile3 * kTile3 * kTile3) void k_dest3(const uint32
     }
 }
 
+// This workgroup's place in a run of consecutive blocks per XCD: workgroup
+// ids are dealt round-robin to the 8 XCDs, so XCD x takes blocks
+// [x * per, (x + 1) * per) (one more for the first nb % 8 XCDs), and the
+// blocks an XCD runs at a time touch neighbouring memory.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 // Which particle fills each final slot: the inverse of the final-slot map, by
 // one 4-byte scatter, so that the move writes every slot once, in order.
 // Each XCD takes a contiguous run of particles: a tile's particles scatter
@@ -349,10 +361,7 @@ __global__ __launch_bounds__(kSortThreads) void k_final_src(int64_t n, const uin
                                                             const uint32_t* __restrict__ dest,
                                                             uint32_t* __restrict__ src)
 {
-    const int nb = gridDim.x;
-    const int per = nb / kXcds, rem = nb % kXcds;
-    const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
-    const int blk = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    const int blk = xcd_block();
     const int64_t p = (int64_t)blk * kSortThreads + threadIdx.x;
     if (p >= n) return;
     src[dest[(int64_t)offs[key[p]] + rank[p]]] = (uint32_t)p;
@@ -378,10 +387,7 @@ template <class V, int A>
 __global__ __launch_bounds__(kSortThreads) void k_gather_final(PartArrays from, PartArrays to, int64_t n,
                                                                const uint32_t* __restrict__ src)
 {
-    const int nb = gridDim.x;
-    const int per = nb / kXcds, rem = nb % kXcds;
-    const int x = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
-    const int blk = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    const int blk = xcd_block();
     const int64_t q0 = (int64_t)blk * kSortThreads * kGatherU + threadIdx.x;
     const V* __restrict__ in = gather_array<V, A>(from);
     V* __restrict__ out = gather_array<V, A>(to);
