@@ -20,6 +20,24 @@ namespace {
 
 __device__ __forceinline__ void add_global(double* p, double v) { unsafeAtomicAdd(p, v); }
 
+// window5 with both weight sets in registers first: a select between two
+// entries of one array (the window shifted one cell or not) would otherwise
+// become one load at a run-time index, which keeps the array in scratch
+// memory.
+__device__ __forceinline__ void window5_reg(const double (&s0)[4], const double (&s1)[4], int shift, double dm[5],
+                                            double dp[5])
+{
+    double a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = s0[k];
+        b[k] = s1[k];
+        asm("" : "+v"(a[k]));
+        asm("" : "+v"(b[k]));
+    }
+    window5<double>(a, b, shift, dm, dp);
+}
+
 // The single pass, used in 2D3V (its two regions fit in LDS with margin 2).
 constexpr int kO2M2 = 2, kO2NT2 = 256;
 
@@ -115,7 +133,7 @@ __global__ __launch_bounds__(kO2NT2) void k_step_o2(GridK g, StepArgs a, const d
         for (int ax = 0; ax < D; ++ax) {
             const Axis2<double> e1 = form_factor2<double>(d1[ax]);
             const int shift = delta[ax] + e1.h - ax0[ax].h;
-            window5<double>(ax0[ax].s, e1.s, shift, dm[ax], dp[ax]);
+            window5_reg(ax0[ax].s, e1.s, shift, dm[ax], dp[ax]);
             s[ax] = ax0[ax].h + (shift < 0 ? shift : 0) - 2;  // window start, from the particle cell
         }
         double jfac[3];
@@ -269,7 +287,7 @@ __device__ __forceinline__ bool o2_windows(const GridK& g, const StepArgs& a, co
         const Axis2<double> e1 = form_factor2<double>(x1 - f1);
         const int shift = delta + e1.h - e0.h;
         mv.still = mv.still && shift == 0;
-        window5<double>(e0.s, e1.s, shift, dm[ax], dp[ax]);
+        window5_reg(e0.s, e1.s, shift, dm[ax], dp[ax]);
         mv.s[ax] = e0.h + (shift < 0 ? shift : 0) - 2;
         int r = mv.i0[ax] - T0[ax];
         const int n = g.n[ax];
@@ -366,7 +384,7 @@ __global__ __launch_bounds__(256) void k_deposit_pairs_o2(GridK g, const double*
         const Axis2<double> e1 = form_factor2<double>(a1 - f1);
         i0[ax] = (int)f0;
         const int shift = ((int)f1 + e1.h) - ((int)f0 + e0.h);
-        window5<double>(e0.s, e1.s, shift, dm[ax], dp[ax]);
+        window5_reg(e0.s, e1.s, shift, dm[ax], dp[ax]);
         s[ax] = e0.h + (shift < 0 ? shift : 0) - 2;
     }
     const double q = charge[p];
