@@ -37,6 +37,7 @@ _lib = None
 
 
 AUX = 8192  # auxiliary line length of the plane-wave source (ORC_AUX)
+ABSORB = 2  # particle-absorbing layer at each open x wall, in cells (ORC_ABSORB)
 
 
 class _Grid(ctypes.Structure):
@@ -47,7 +48,7 @@ class _Grid(ctypes.Structure):
                 ("src_kind", ctypes.c_int64), ("src_plane", ctypes.c_int64),
                 ("src_amp", ctypes.c_double), ("src_omega", ctypes.c_double),
                 ("src_ramp", ctypes.c_double), ("order", ctypes.c_int64),
-                ("interp", ctypes.c_int64)]
+                ("interp", ctypes.c_int64), ("xbc", ctypes.c_int64)]
 
 
 class _Species(ctypes.Structure):
@@ -114,6 +115,8 @@ class Grid:
     source: tuple = None   # (plane, amplitude, omega, ramp time): +x plane wave, E^y
     order: int = 1         # alternating order l_a = order + 1/2 (Section 4.5): 1 or 2
     interp: int = 0        # 0 alternating order; 1 the conventional uniform order (Eq. wrong1)
+    xbc: int = 0           # x boundary: 0 periodic; 1 open (Mur walls at x = 0 and nx - 1,
+                           # particles absorbed within ABSORB cells of a wall)
 
     @property
     def shape(self):
@@ -129,6 +132,7 @@ class Grid:
         g.dx, g.dy, g.dz, g.dt, g.c = self.dx, self.dy, self.dz, self.dt, self.c
         g.order = int(self.order)
         g.interp = int(self.interp)
+        g.xbc = int(self.xbc)
         for a in range(3):
             g.bext[a] = float(self.bext[a])
         if self.source is not None:

@@ -441,10 +441,80 @@ static void src_fix_e(const orc_grid* g, double* fields, const double* aux)
 }
 
 /* ---------------------------------------------------------------------------
+ * Open x boundary (xbc = 1; not part of the paper's method, whose tests are
+ * periodic boxes).  The walls are the node planes x = 0 and x = nx - 1, on
+ * which B^y and B^z lie.  Their values follow Mur's first-order absorbing
+ * condition (G. Mur, IEEE Trans. Electromagn. Compat. 23, 377 (1981)): the
+ * one-way wave equation dB/dt = +-c dB/dx of a wave leaving the box, with
+ * both derivatives taken at the midpoint between the wall and the plane one
+ * cell inside and between B^{n-1/2} and B^{n+1/2}, solved for the new wall
+ * value:
+ *   B_wall^{n+1/2} = B_in^{n-1/2} + k (B_in^{n+1/2} - B_wall^{n-1/2}),
+ *   k = (c dt - dx) / (c dt + dx).
+ * Every other value is updated by the periodic operators above; the cell
+ * layer between x = nx - 1 and the periodic image of x = 0 is outside the
+ * box and its E^y, E^z and B^x are set to zero after each update, so that
+ * nothing carries across it.
+ * save: [side][wall B^y, wall B^z, inside B^y, inside B^z][ny nz], side 0 the
+ * wall x = 0 (inside plane x = 1), side 1 the wall x = nx - 1 (inside plane
+ * x = nx - 2).
+ * ------------------------------------------------------------------------- */
+static void wall_save(const orc_grid* g, const double* fields, double* save)
+{
+    const size_t nc = ncell(g), nyz = (size_t)g->ny * g->nz;
+    const double *By = fields + 4 * nc, *Bz = fields + 5 * nc;
+    for (int side = 0; side < 2; ++side) {
+        const long iw = side == 0 ? 0 : g->nx - 1, in = side == 0 ? 1 : g->nx - 2;
+        double* sv = save + 4 * nyz * side;
+        for (long k = 0; k < g->nz; ++k)
+            for (long j = 0; j < g->ny; ++j) {
+                const size_t q = (size_t)k * g->ny + j;
+                sv[q] = By[idx(g, iw, j, k)];
+                sv[nyz + q] = Bz[idx(g, iw, j, k)];
+                sv[2 * nyz + q] = By[idx(g, in, j, k)];
+                sv[3 * nyz + q] = Bz[idx(g, in, j, k)];
+            }
+    }
+}
+
+static void wall_mur(const orc_grid* g, double* fields, const double* save)
+{
+    const size_t nc = ncell(g), nyz = (size_t)g->ny * g->nz;
+    double *Bx = fields + 3 * nc, *By = fields + 4 * nc, *Bz = fields + 5 * nc;
+    const double cdt = g->c * g->dt;
+    const double kmur = (cdt - g->dx) / (cdt + g->dx);
+    for (int side = 0; side < 2; ++side) {
+        const long iw = side == 0 ? 0 : g->nx - 1, in = side == 0 ? 1 : g->nx - 2;
+        const double* sv = save + 4 * nyz * side;
+        for (long k = 0; k < g->nz; ++k)
+            for (long j = 0; j < g->ny; ++j) {
+                const size_t q = (size_t)k * g->ny + j;
+                By[idx(g, iw, j, k)] = sv[2 * nyz + q] + kmur * (By[idx(g, in, j, k)] - sv[q]);
+                Bz[idx(g, iw, j, k)] = sv[3 * nyz + q] + kmur * (Bz[idx(g, in, j, k)] - sv[nyz + q]);
+            }
+    }
+    for (long k = 0; k < g->nz; ++k)
+        for (long j = 0; j < g->ny; ++j) Bx[idx(g, g->nx - 1, j, k)] = 0.0;
+}
+
+static void outside_zero_e(const orc_grid* g, double* fields)
+{
+    const size_t nc = ncell(g);
+    double *Ey = fields + nc, *Ez = fields + 2 * nc;
+    for (long k = 0; k < g->nz; ++k)
+        for (long j = 0; j < g->ny; ++j) {
+            Ey[idx(g, g->nx - 1, j, k)] = 0.0;
+            Ez[idx(g, g->nx - 1, j, k)] = 0.0;
+        }
+}
+
+/* ---------------------------------------------------------------------------
  * One full time step in the Appendix order: B half step; for every particle,
  * in index order, form factors at x^n, gather, push, new position, current;
  * second B half step; E update.  J is cleared before the particle loop, so
- * after the step it holds J^{n+1/2}.
+ * after the step it holds J^{n+1/2}.  With an open x boundary the walls'
+ * B^{n-1/2} is saved first and their B^{n+1/2} is replaced by Mur's value
+ * before the E update, which reads it.
  * ------------------------------------------------------------------------- */
 static void wrap_pos(double* x, long n)
 {
@@ -475,6 +545,8 @@ void orc_particle_step(const orc_grid* g, const double* fields, const orc_specie
             s->x[a * s->n + p] = x1[a];
             s->w[a * s->n + p] = w[a];
         }
+        if (g->xbc == 1 && (x1[0] < ORC_ABSORB || x1[0] >= (double)(g->nx - 1 - ORC_ABSORB)))
+            s->weight[p] = 0.0; /* absorbed: its current of this step is already on the grid */
     }
 }
 
@@ -484,7 +556,9 @@ void orc_step_src(const orc_grid* g, double* fields, int nsp, const orc_species*
     const size_t nc = ncell(g);
     double* J = fields + 6 * nc;
     const int src = g->src_kind == 1 && aux != NULL;
+    double* save = g->xbc == 1 ? (double*)malloc(8 * (size_t)g->ny * g->nz * sizeof(double)) : NULL;
     for (int it = 0; it < nsteps; ++it) {
+        if (save) wall_save(g, fields, save);
         orc_half_b(g, fields);
         if (src) {
             src_fix_b(g, fields, aux);
@@ -498,12 +572,15 @@ void orc_step_src(const orc_grid* g, double* fields, int nsp, const orc_species*
             src_fix_b(g, fields, aux);
             aux_half_b(g, aux);
         }
+        if (save) wall_mur(g, fields, save);
         orc_update_e(g, fields);
         if (src) {
             src_fix_e(g, fields, aux);
             aux_update_e(g, aux, (double)(step0 + it + 1) * g->dt);
         }
+        if (save) outside_zero_e(g, fields);
     }
+    free(save);
 }
 
 void orc_step(const orc_grid* g, double* fields, int nsp, const orc_species* sp, int nsteps)

@@ -29,7 +29,15 @@ typedef struct orc_grid {
      * component's node axes the weight is the mean of the two adjacent cell
      * factors, Delta F elsewhere */
     int64_t interp;
+    /* x boundary: 0 periodic; 1 open -- walls at the node planes x = 0 and
+     * x = nx - 1 with Mur's first-order absorbing condition on the tangential
+     * B^y, B^z, the cell layer x in [nx - 1, nx) outside the box (its E^y,
+     * E^z, B^x held at zero), and particles absorbed (weight set to zero) when
+     * a step ends within ORC_ABSORB cells of a wall */
+    int64_t xbc;
 } orc_grid;
+
+#define ORC_ABSORB 2  /* width in cells of the particle-absorbing layer at each wall */
 
 #define ORC_AUX 8192  /* auxiliary line length: E^y[ORC_AUX] then B^z[ORC_AUX] */
 
@@ -41,7 +49,7 @@ typedef struct orc_species {
     int32_t deposit;       /* 0: test particles, no current */
     double* x;             /* [3][n] positions in cell units, in [0, N) */
     double* w;             /* [3][n] momentum over mass, w^{n-1/2} */
-    const double* weight;  /* [n] macro-particle weight */
+    double* weight;        /* [n] macro-particle weight (zeroed when absorbed) */
 } orc_species;
 
 double orc_shape(int l, double r);
