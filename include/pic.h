@@ -112,8 +112,29 @@ typedef struct pic_grid_desc {
      * curl_h 0 = 0) and is set and read with pic_set_vector_potential /
      * pic_get_vector_potential.  Not with the plane-wave source or the adjoint. */
     int32_t field_form;
-    int32_t reserved2;   /* must be 0 */
+    /* x boundary.  0: periodic (every axis is periodic; the paper's tests are
+     * periodic boxes).  1: open -- an extension around the paper's field
+     * update, which specifies no boundary.  The walls are the node planes
+     * x = 0 and x = nx - 1, on which B^y and B^z lie; each step sets their
+     * B^{n+1/2} by Mur's first-order absorbing condition (G. Mur, IEEE Trans.
+     * Electromagn. Compat. 23, 377 (1981)),
+     *   B_wall^{n+1/2} = B_in^{n-1/2} + k (B_in^{n+1/2} - B_wall^{n-1/2}),
+     *   k = (c dt - dx) / (c dt + dx), B_in one cell inside the wall,
+     * before the E update reads it.  The cell layer x in [nx - 1, nx) is
+     * outside the box: the step sets its E^y, E^z and B^x to zero.  A
+     * particle whose step ends within PIC_ABSORB cells of a wall
+     * (x < PIC_ABSORB or x >= nx - 1 - PIC_ABSORB) is absorbed: its weight
+     * becomes zero once its current of that step is deposited, and it
+     * moves on as a particle without charge.  With 1 the Gauss drift of
+     * pic_diagnostics covers cells PIC_ABSORB + 1 .. nx - 3 - PIC_ABSORB along
+     * x (those no absorbed charge reaches) and div B the nodes 1 .. nx - 2.
+     * Needs nx >= 8, the alternating order 1 1/2 with B carried, and a source
+     * plane <= nx - 3; pic_field_solve, pic_solve_poisson and the adjoint
+     * reject such a context (their operators are periodic). */
+    int32_t xbc;
 } pic_grid_desc;
+
+#define PIC_ABSORB 2
 
 #define PIC_AUX 8192
 

@@ -42,7 +42,7 @@ class GridDesc(ctypes.Structure):
                 ("src_kind", ctypes.c_int32), ("src_plane", ctypes.c_int32),
                 ("src_amp", ctypes.c_double), ("src_omega", ctypes.c_double),
                 ("src_ramp", ctypes.c_double), ("field_form", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("xbc", ctypes.c_int32)]
 
 
 class SpeciesDesc(ctypes.Structure):

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 
+#include "boundary.h"
 #include "pic_internal.h"
 
 namespace pic {
@@ -143,8 +144,18 @@ int make_grid(const pic_grid_desc* g, GridK* k, std::string* msg)
     k->src_omega = g->src_omega;
     k->src_ramp = g->src_ramp;
     k->aux = nullptr;
-    if ((g->field_form != 0 && g->field_form != 1) || g->reserved2 != 0) {
-        *msg = "field_form must be 0 (B) or 1 (vector potential) and reserved2 0";
+    if (g->field_form != 0 && g->field_form != 1) {
+        *msg = "field_form must be 0 (B) or 1 (vector potential)";
+        return PIC_EINVAL;
+    }
+    if (g->xbc != 0 && g->xbc != 1) {
+        *msg = "xbc must be 0 (periodic) or 1 (open)";
+        return PIC_EINVAL;
+    }
+    if (g->xbc == 1 && (g->nx < 8 || g->order != 1 || g->interp != 0 || g->field_form != 0 ||
+                        (g->src_kind == 1 && g->src_plane > g->nx - 3))) {
+        *msg = "the open x boundary needs nx >= 8, the alternating order 1 1/2 with B carried, "
+               "and a source plane <= nx - 3";
         return PIC_EINVAL;
     }
     if (g->field_form == 1 && g->src_kind != 0) {
@@ -434,6 +445,9 @@ int pic_step(pic_ctx* ctx, int nsteps, void* stream)
         mark(1);
         for (int i = 0; i < c.nsp && e == hipSuccess; ++i)
             if (c.sp[i].d.mobile) e = launch_particle_step(c, c.sp[i], s);
+        if (c.g.xbc == 1)  // after every species' current of the step is deposited
+            for (int i = 0; i < c.nsp && e == hipSuccess; ++i)
+                if (c.sp[i].d.mobile) e = launch_absorb(c, c.sp[i], s);
         mark(2);
         if (e == hipSuccess) e = launch_field_update_e(c, s, c.step);
         mark(3);
@@ -472,6 +486,8 @@ int pic_field_solve(pic_ctx* ctx, int what, void* stream)
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (c.k.field_form != 0) return fail(&c, PIC_ESTATE, "field_solve advances B; this context carries A");
+    if (c.g.xbc != 0)
+        return fail(&c, PIC_ESTATE, "the open x walls need whole steps (pic_step); field_solve is periodic");
     if (what == PIC_B_HALF) {
         e = launch_field_half_b(c, s);
     } else if (what == PIC_E_FULL) {
@@ -489,6 +505,7 @@ static int adjoint_ready(Ctx& c)
     if (c.g.precision != PIC_FP64) return fail(&c, PIC_EINVAL, "the adjoint is FP64 only");
     if (c.k.src_kind != 0) return fail(&c, PIC_EINVAL, "the adjoint does not cover the plane-wave source");
     if (c.k.field_form != 0) return fail(&c, PIC_EINVAL, "the adjoint covers the B form only");
+    if (c.g.xbc != 0) return fail(&c, PIC_EINVAL, "the adjoint covers periodic boxes only");
     if (c.g.order != 1 || c.g.interp != 0)
         return fail(&c, PIC_EINVAL, "the adjoint covers the alternating order 1 1/2 only");
     if (c.k.ncell * (int64_t)sizeof(double) >= ((int64_t)1 << 32))
@@ -597,6 +614,7 @@ int pic_solve_poisson(pic_ctx* ctx, int neutralize, double tol, int64_t* iterati
     if (!ctx) return fail(nullptr, PIC_EINVAL, "null context");
     Ctx& c = ctx->c;
     if (neutralize != 0 && neutralize != 1) return fail(&c, PIC_EINVAL, "neutralize must be 0 or 1");
+    if (c.g.xbc != 0) return fail(&c, PIC_ESTATE, "the Poisson solve is periodic; this context has an open x boundary");
     if (!(tol > 0.0)) tol = 1e-13;
     hipStream_t s = (hipStream_t)stream;
     // the total charge density goes to the Gauss reference's buffer, which is

@@ -74,11 +74,14 @@ __global__ __launch_bounds__(kRedThreads) void k_capture_r0(GridK g, const doubl
     }
 }
 
+// The Gauss drift covers x cells gx0 .. gx1 and div B x nodes bx0 .. bx1 (all
+// of them, unless the open x boundary excludes the walls' surroundings).
 __global__ __launch_bounds__(kRedThreads) void k_diag_cells(GridK g, const double* __restrict__ f,
                                                             const double* __restrict__ rho_m,
                                                             const double* __restrict__ rho_bg,
                                                             const double* __restrict__ r0,
-                                                            double* __restrict__ part)
+                                                            double* __restrict__ part, int gx0, int gx1,
+                                                            int bx0, int bx1)
 {
     double v[kSlots] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t N = g.ncell;
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(kRedThreads) void k_diag_cells(GridK g, const doubl
         int i, j, k;
         decode(g, p, i, j, k);
         const double R = gauss_at(g, f, rho_m, rho_bg, p, i, j, k);
-        v[0] = fmax(v[0], fabs(R - r0[p]));
+        if (i >= gx0 && i <= gx1) v[0] = fmax(v[0], fabs(R - r0[p]));
         v[1] = fmax(v[1], fabs(4.0 * kPi * rho_m[p]));
         const double ex = f[p], ey = f[N + p], ez = f[2 * N + p];
         v[2] += ex * ex + ey * ey + ez * ez;
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(kRedThreads) void k_diag_cells(GridK g, const doubl
         v[3] += bx * bx + by * by + bz * bz;
         const double db = (Bx[p] - Bx[im]) * g.inv_h[0] + (By[p] - By[jm]) * g.inv_h[1] +
                           (Bz[p] - Bz[km]) * g.inv_h[2];
-        v[4] = fmax(v[4], fabs(db));
+        if (i >= bx0 && i <= bx1) v[4] = fmax(v[4], fabs(db));
         v[5] += rho_m[p] + rho_bg[p];
         for (int c = 0; c < 6; ++c)
             if (!isfinite(f[c * N + p])) v[6] += 1.0;
@@ -247,8 +250,13 @@ hipError_t launch_diag(Ctx& c, pic_diag* out, hipStream_t s, double* rho_m, doub
     hipError_t e = mobile_rho(c, rho_m, s);
     if (e != hipSuccess) return e;
     // partial layout: cells kRedBlocks x kSlots, then one block per species
+    // open x boundary: the Gauss drift away from the absorbed charge, div B
+    // where every B follows the curl of E (see pic_grid_desc.xbc)
+    const int nx = c.k.n[0];
+    const bool open = c.g.xbc == 1;
     hipLaunchKernelGGL(k_diag_cells, dim3(kRedBlocks), dim3(kRedThreads), 0, s, c.k, c.fields,
-                       rho_m, c.rho_bg, c.r0, part);
+                       rho_m, c.rho_bg, c.r0, part, open ? PIC_ABSORB + 1 : 0,
+                       open ? nx - 3 - PIC_ABSORB : nx - 1, open ? 1 : 0, open ? nx - 2 : nx - 1);
     int nb = kRedBlocks;
     int64_t nmob = 0;
     for (int i = 0; i < c.nsp; ++i) {

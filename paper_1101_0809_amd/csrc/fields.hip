@@ -64,9 +64,16 @@ __global__ __launch_bounds__(kFieldThreads) void k_half_b(GridK g, double* __res
 // Both B half steps of a time step at once (they use the same E^n): B^n =
 // B^{n-1/2} - (1/2) curl_h E^n to bn, then B^{n+1/2} = B^n - (1/2) curl_h E^n
 // in place, each half step with the same expression and rounding as k_half_b.
+// With the open x boundary (mur != null, pic_grid_desc.xbc): the planes one
+// cell inside the walls save their B^y, B^z of n - 1/2 to mur ([side][y, z]
+// [ny nz], side 0 the plane x = 1, side 1 the plane x = nx - 2), the walls
+// x = 0 and x = nx - 1 keep theirs in place for k_mur_walls, and the outside
+// layer's B^x is set to zero.  The walls' B^n in bn is the plain half step;
+// no particle within the box reads it.
 __global__ __launch_bounds__(kFieldThreads) void k_half_b_pair(GridK g, double* __restrict__ f,
                                                                double* __restrict__ bn,
-                                                               unsigned long long* __restrict__ zero, int nzero)
+                                                               unsigned long long* __restrict__ zero, int nzero,
+                                                               double* __restrict__ mur)
 {
     const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
     if (p < nzero) zero[p] = 0;  // counters of the particle kernels that follow
@@ -101,9 +108,44 @@ __global__ __launch_bounds__(kFieldThreads) void k_half_b_pair(GridK g, double* 
     by = by - cy + dy;
     bz = bz - cz + dz;
     if (src) bz += sc;
+    if (mur) {
+        const int nx = g.n[0];
+        const int64_t nyz = (int64_t)g.n[1] * g.n[2], q = (int64_t)c.k * g.n[1] + c.j;
+        if (c.i == 1 || c.i == nx - 2) {
+            double* sv = mur + (c.i == 1 ? 0 : 2 * nyz);
+            sv[q] = By[p];
+            sv[nyz + q] = Bz[p];
+        }
+        if (c.i == 0 || c.i == nx - 1) {  // walls: k_mur_walls sets B^y, B^z
+            Bx[p] = c.i == 0 ? bx : 0.0;
+            return;
+        }
+    }
     Bx[p] = bx;
     By[p] = by;
     Bz[p] = bz;
+}
+
+// Open x boundary: Mur's first-order condition on the walls' B^y, B^z,
+// B_wall^{n+1/2} = B_in^{n-1/2} + k (B_in^{n+1/2} - B_wall^{n-1/2}), with
+// B_in^{n-1/2} from mur and B_wall^{n-1/2} still in place (k_half_b_pair).
+// One thread per wall point: side = blockIdx.y.
+__global__ __launch_bounds__(kFieldThreads) void k_mur_walls(GridK g, double* __restrict__ f,
+                                                             const double* __restrict__ mur, double kmur)
+{
+    const int64_t nyz = (int64_t)g.n[1] * g.n[2];
+    const int64_t q = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
+    if (q >= nyz) return;
+    const int side = blockIdx.y;
+    const int nx = g.n[0];
+    const int64_t N = g.ncell;
+    const int64_t pw = q * nx + (side == 0 ? 0 : nx - 1);
+    const int64_t pi = q * nx + (side == 0 ? 1 : nx - 2);
+    double* By = f + 4 * N;
+    double* Bz = f + 5 * N;
+    const double* sv = mur + 2 * nyz * side;
+    By[pw] = sv[q] + kmur * (By[pi] - By[pw]);
+    Bz[pw] = sv[nyz + q] + kmur * (Bz[pi] - Bz[pw]);
 }
 
 // The source's auxiliary line, advanced by a one-workgroup kernel after each
@@ -142,8 +184,9 @@ __global__ __launch_bounds__(kFieldThreads) void k_aux_half_b_pair(GridK g)
 }
 __global__ __launch_bounds__(kFieldThreads) void k_aux_update_e(GridK g, double t) { aux_update_e(g, t); }
 
-// E <- E - 4 pi dt J + curl_h B ; J <- 0
-__global__ __launch_bounds__(kFieldThreads) void k_update_e(GridK g, double* __restrict__ f)
+// E <- E - 4 pi dt J + curl_h B ; J <- 0.  open: the open x boundary's
+// outside layer x in [nx - 1, nx) gets E^y = E^z = 0.
+__global__ __launch_bounds__(kFieldThreads) void k_update_e(GridK g, double* __restrict__ f, int open)
 {
     const int64_t p = (int64_t)blockIdx.x * kFieldThreads + threadIdx.x;
     if (p >= g.ncell) return;
@@ -168,8 +211,10 @@ __global__ __launch_bounds__(kFieldThreads) void k_update_e(GridK g, double* __r
     double ey = Ey[p] - g.fourpidt * Jy[p] + cz * (Bx[kp] - bx) - cx * (Bz[ip] - bz);
     if (g.src_kind == 1 && c.i == g.src_plane)  // E^y at face plane+1/2 is total-field:
         ey += cx * g.aux[PIC_AUX + 2];         // add the incident B^z of node plane
+    double ez = Ez[p] - g.fourpidt * Jz[p] + cx * (By[ip] - by) - cy * (Bx[jp] - bx);
+    if (open && c.i == g.n[0] - 1) ey = ez = 0.0;
     Ey[p] = ey;
-    Ez[p] = Ez[p] - g.fourpidt * Jz[p] + cx * (By[ip] - by) - cy * (Bx[jp] - bx);
+    Ez[p] = ez;
     Jx[p] = 0.0;
     Jy[p] = 0.0;
     Jz[p] = 0.0;
@@ -238,10 +283,22 @@ hipError_t launch_field_half_b(const Ctx& c, hipStream_t s)
     return hipGetLastError();
 }
 
+// The open x boundary's walls: B^{n-1/2} of the inside planes goes to the
+// adjoint scratch (4 ny nz doubles of its 3 nx ny nz), which an open-boundary
+// context never uses for the adjoint.
 hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s, unsigned long long* zero, int nzero)
 {
     const unsigned blocks = (unsigned)((std::max<int64_t>(c.k.ncell, nzero) + kFieldThreads - 1) / kFieldThreads);
-    hipLaunchKernelGGL(k_half_b_pair, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields, c.bn, zero, nzero);
+    double* mur = c.g.xbc == 1 ? c.adj : nullptr;
+    hipLaunchKernelGGL(k_half_b_pair, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields, c.bn, zero, nzero,
+                       mur);
+    if (mur) {
+        const int64_t nyz = (int64_t)c.k.n[1] * c.k.n[2];
+        const double cdt = c.g.c * c.g.dt;
+        hipLaunchKernelGGL(k_mur_walls, dim3((unsigned)((nyz + kFieldThreads - 1) / kFieldThreads), 2),
+                           dim3(kFieldThreads), 0, s, c.k, c.fields, (const double*)mur,
+                           (cdt - c.g.dx) / (cdt + c.g.dx));
+    }
     if (c.k.src_kind == 1)  // the line's two half steps, after the grid kernel read its E^y
         hipLaunchKernelGGL(k_aux_half_b_pair, dim3(1), dim3(kFieldThreads), 0, s, c.k);
     return hipGetLastError();
@@ -250,7 +307,7 @@ hipError_t launch_field_half_b_pair(const Ctx& c, hipStream_t s, unsigned long l
 hipError_t launch_field_update_e(const Ctx& c, hipStream_t s, int64_t step)
 {
     const unsigned blocks = (unsigned)((c.k.ncell + kFieldThreads - 1) / kFieldThreads);
-    hipLaunchKernelGGL(k_update_e, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields);
+    hipLaunchKernelGGL(k_update_e, dim3(blocks), dim3(kFieldThreads), 0, s, c.k, c.fields, c.g.xbc == 1 ? 1 : 0);
     if (c.k.src_kind == 1)  // the line's E^y at t = (step + 1) dt
         hipLaunchKernelGGL(k_aux_update_e, dim3(1), dim3(kFieldThreads), 0, s, c.k,
                            (double)(step + 1) * c.k.dt);

@@ -50,13 +50,15 @@ class Sim:
                  precision: str = "fp64", dx: float = 1.0, dy: float = 1.0, dz: float = 1.0,
                  c: float = 1.0, sort_every: int = 0, bext=(0.0, 0.0, 0.0),
                  device: str = "cuda:0", fields: np.ndarray = None, source=None, order: int = 1,
-                 interp: str = "alternating", field_form: str = "B"):
+                 interp: str = "alternating", field_form: str = "B", xbc: str = "periodic"):
         """source: None or (plane, amplitude, omega, ramp time) for the +x
         E^y plane-wave source of include/pic.h.  order: alternating form
         factor order l_a = order + 1/2 (1, or 2 in FP64).  interp:
         "alternating" or "conventional" (the uniform-order comparison of
         Eq. wrong1; order 1, FP64).  field_form: "B", or "A" to carry the
-        vector potential (Section 4.2, Eq. dadt) with B = curl_h A."""
+        vector potential (Section 4.2, Eq. dadt) with B = curl_h A.  xbc:
+        "periodic", or "open" for Mur walls at x = 0 and x = nx - 1 and
+        particles absorbed within PIC_ABSORB cells of them (include/pic.h)."""
         if not torch.cuda.is_available():
             raise RuntimeError("the PIC library needs a GPU (no CPU fallback)")
         self.lib = L.load()
@@ -68,6 +70,7 @@ class Sim:
         d.order, d.sort_every = int(order), sort_every
         d.interp = {"alternating": 0, "conventional": 1}[interp]
         d.field_form = {"B": 0, "A": 1}[field_form]
+        d.xbc = {"periodic": 0, "open": 1}[xbc]
         d.dx, d.dy, d.dz, d.dt, d.c = dx, dy, dz, dt, c
         for a in range(3):
             d.bext[a] = float(bext[a])
@@ -266,7 +269,8 @@ class Sim:
                   dx=d["dx"], dy=d["dy"], dz=d["dz"], c=d["c"], sort_every=d["sort_every"],
                   bext=tuple(d["bext"]), device=device, source=src, order=d["order"],
                   interp=("alternating", "conventional")[d["interp"]],
-                  field_form=("B", "A")[d["field_form"]])
+                  field_form=("B", "A")[d["field_form"]],
+                  xbc=("periodic", "open")[d.get("xbc", 0)])
         for sp in st["species"]:
             sim.add_species(sp["q"], sp["m"], sp["capacity"], mobile=sp["mobile"])
         sim.fields_t.copy_(st["fields"])

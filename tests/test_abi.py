@@ -79,6 +79,12 @@ def test_query_sizes():
     (dict(precision=1, ny=2049), -1),        # 11 bits for the y cell
     (dict(precision=1, nz=1025), -1),        # 10 bits for the z cell
     (dict(dx=-1.0), -1),
+    (dict(xbc=2), -1),                      # x boundary: 0 periodic, 1 open
+    (dict(xbc=1, nx=7), -1),                # open x needs nx >= 8
+    (dict(xbc=1, order=2), -1),             # open x: order 1 1/2 only
+    (dict(xbc=1, interp=1), -1),
+    (dict(xbc=1, field_form=1), -1),        # open x: B carried
+    (dict(xbc=1, src_kind=1, src_plane=14), -1),  # source plane <= nx - 3
 ])
 def test_invalid_descriptions_rejected(kw, code):
     L, lib = _lib()
@@ -99,6 +105,14 @@ def test_fp32_mode_accepts_its_largest_axes(kw):
     L, lib = _lib()
     sz = L.Sizes()
     assert lib.pic_query_sizes(ctypes.byref(_desc(L, precision=L.PIC_FP32C, **kw)), 10, ctypes.byref(sz)) == 0
+
+
+@pytest.mark.parametrize("kw", [dict(xbc=1, nx=8), dict(xbc=1, src_kind=1, src_plane=13),
+                                dict(xbc=1, precision=1), dict(xbc=1, dims=2, nz=1)])
+def test_open_x_descriptions_accepted(kw):
+    L, lib = _lib()
+    sz = L.Sizes()
+    assert lib.pic_query_sizes(ctypes.byref(_desc(L, **kw)), 10, ctypes.byref(sz)) == 0
 
 
 def test_two_dimensional_courant_ignores_z():
