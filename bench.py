@@ -115,13 +115,14 @@ def sampled_state(sim, species, per_species: int = 16384):
 
 
 def run_gpu(wl, precision: str, steps: int, warmup: int, order: int = 1, interp: str = "alternating",
-            sample: bool = False):
+            sample: bool = False, xbc: str = "periodic"):
     import torch
 
     from paper_1101_0809_amd import Sim
 
     sim = Sim(nx=wl.nx, ny=wl.ny, nz=wl.nz, dt=wl.dt, dims=wl.dims, precision=precision,
-              sort_every=wl.sort_every, bext=wl.bext, order=order, interp=interp, source=wl.source)
+              sort_every=wl.sort_every, bext=wl.bext, order=order, interp=interp, source=wl.source,
+              xbc=xbc)
     species = load_workload(sim, wl)
     torch.cuda.empty_cache()
     sim.step(warmup)
@@ -359,19 +360,20 @@ def roofline(res, precision, wl, copy_gbs=None, order=1, interp="alternating"):
             "frac_of_copy": None if copy_gbs is None else round(achieved / copy_gbs, 4)}
 
 
-def _oracle_state(wl, e, ion, order=1, interp="alternating"):
+def _oracle_state(wl, e, ion, order=1, interp="alternating", xbc=0):
     import oracle
 
     sp = [oracle.Species(e.x, e.w, e.weight, q=e.q, m=e.m)] if e is not None else []
     if ion is not None:
         sp.append(oracle.Species(ion.x, ion.w, ion.weight, q=ion.q, m=ion.m, mobile=wl.ions_mobile))
     return oracle.State(oracle.Grid(wl.nx, wl.ny, wl.nz, wl.dt, bext=wl.bext, order=order,
-                                    interp=1 if interp == "conventional" else 0, source=wl.source), sp)
+                                    interp=1 if interp == "conventional" else 0, source=wl.source,
+                                    xbc=xbc), sp)
 
 
 def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int = 1,
                  interp: str = "alternating", full_limit: int = 1 << 22, sample_n: int = 1 << 20,
-                 all_cores: bool = True):
+                 all_cores: bool = True, xbc: int = 0):
     """The FP64 oracle as it stands, serial, on the host.  A workload of at
     most full_limit mobile particles runs whole steps (all particles, full
     grid), as many as take min_seconds (at most max_steps).  A larger one is
@@ -388,7 +390,7 @@ def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int 
     if wl.n_particles <= full_limit:
         e = picgen.electrons(wl)
         ion = picgen.ions_like(wl, e)
-        st = _oracle_state(wl, e, ion, order, interp)
+        st = _oracle_state(wl, e, ion, order, interp, xbc)
         t0 = time.perf_counter()
         sample_steps = 0
         while sample_steps < max_steps and (sample_steps == 0 or time.perf_counter() - t0 < min_seconds):
@@ -400,7 +402,7 @@ def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int 
                 "sample": f"{sample_steps} full step(s) of the same workload ({wl.n_particles} particles, "
                           f"order {order} 1/2, {interp} interpolation, {wl.nx}x{wl.ny}x{wl.nz} grid), "
                           f"serial C oracle, {dt:.1f} s, {host}"}
-    grid_only = _oracle_state(wl, None, None, order, interp)
+    grid_only = _oracle_state(wl, None, None, order, interp, xbc)
     t0 = time.perf_counter()
     grid_only.step(1)
     t_grid = time.perf_counter() - t0
@@ -430,7 +432,7 @@ def _oracle_sample_step(wl, sample_n, order, interp):
     e = picgen.electrons(small, n=sample_n)
     e.weight[:] = wl.weight
     ion = picgen.ions_like(wl, e)
-    st = _oracle_state(wl, e, ion, order, interp)
+    st = _oracle_state(wl, e, ion, order, interp, xbc)
     ns = sample_n * (2 if wl.ions_mobile else 1)
     t0 = time.perf_counter()
     st.step(1)
@@ -495,6 +497,8 @@ def main(argv=None):
     ap.add_argument("--interp", choices=["alternating", "conventional"], default="alternating",
                     help="field interpolation: the alternating-order form factor, or the conventional "
                          "uniform order of Eq. wrong1 (the comparison of Section 5; FP64, order 1)")
+    ap.add_argument("--xbc", choices=["periodic", "open"], default="periodic",
+                    help="x boundary: periodic, or open (Mur walls, particles absorbed near them)")
     ap.add_argument("--every", type=int, default=None,
                     help="checkpoint spacing of --adjoint (default: 20 for the differentiable 2D3V "
                          "workload, its stated spacing; otherwise a tape of every step when it fits "
@@ -563,7 +567,7 @@ def main(argv=None):
         print(f"# {wl.name} {p}: loading {wl.n_particles} particles, {args.warmup} + {args.steps} steps",
               file=sys.stderr, flush=True)
         results[p] = run_gpu(wl, p, args.steps, args.warmup, args.order, args.interp,
-                             sample=len(precs) == 2)
+                             sample=len(precs) == 2, xbc=args.xbc)
         r = results[p]
         print(f"# {p}: {r['ms_per_step']:.4f} ms/step, particle kernels "
               f"{r['phases']['particles'] / max(1, r['phases']['steps']):.4f} ms/step, "
@@ -591,6 +595,7 @@ def main(argv=None):
                    "particles_per_species": r["counts"], "ppc": wl.ppc,
                    "mobile_ions": wl.ions_mobile, "dt": wl.dt, "sort_every": wl.sort_every,
                    "precision": main_p, "order": f"{args.order} 1/2", "interp": args.interp,
+                   "xbc": args.xbc,
                    "parallelism": "none (1 GPU)"},
         "roofline": roofline(r, main_p, wl, copy_gbs, args.order, args.interp),
         "phases_ms_per_step": {k: round(v / max(1, r["phases"]["steps"]), 5)
@@ -614,7 +619,8 @@ def main(argv=None):
                                 "(FP64, order 1 1/2, 64^3 grid, 2 electrons per cell; Section 5); "
                                 "another machine, not a target"}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, order=args.order, interp=args.interp)
+        line["cpu_baseline"] = cpu_baseline(wl, order=args.order, interp=args.interp,
+                                            xbc=1 if args.xbc == "open" else 0)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -233,3 +233,53 @@ def test_open_x_rejects_periodic_only_operations():
     assert sim.lib.pic_adjoint_seed_field_energy(sim.ctx, ctypes.c_void_p(lam.data_ptr()), None) != 0
     sim.step(2)                                  # stepping itself works
     assert sim.diagnostics()["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_128cube_slab_laser_open_x_fullsize(precision):
+    """The full 128^3 slab workload (16,777,216 electrons in x in [32, 96),
+    immobile ions, the a0 = 1 laser of 20-cell wavelength from the plane
+    x = 8) with open x walls, 300 steps: the laser has crossed the slab and
+    reached the right wall.  Checked at full size:
+    - the walls follow Mur's update across one more step at every wall point,
+      B_wall^{n+1/2} = B_in^{n-1/2} + k (B_in^{n+1/2} - B_wall^{n-1/2});
+    - one step of 1500 sampled electrons against the oracle from the GPU's
+      own fields;
+    - the Gauss drift inside the box, and the empty outside layer.
+    The laser's E (about omega = 0.31) is some 300 times the slab's 4 pi rho,
+    so in FP64 the drift is set by the rounding of the E updates: each step
+    adds a few roundings of |E|-sized values to every E, and div_h E sums six
+    of them over dx, so the bar is steps * 16 eps max|E| / dx (absolute)."""
+    from test_gpu_parity import _sampled_step_check
+    wl = picgen.WORKLOADS["3d_128cube_slab"]
+    omega = 2 * math.pi / 20
+    src = (8, omega, omega, 20.0)
+    e = picgen.electrons(wl)
+    ion = picgen.ions_like(wl, e)
+    sim = _sim(nx=128, ny=128, nz=128, dt=wl.dt, dims=3, precision=precision,
+               sort_every=wl.sort_every, source=src, xbc="open")
+    s = sim.add_species(e.q, e.m, e.n)
+    sim.load(s, e.x, e.w, e.weight)
+    si = sim.add_species(ion.q, ion.m, 0, mobile=False)
+    sim.load(si, ion.x, ion.w, ion.weight)
+    del e, ion
+    print(f"128^3 slab, open x, {precision}: 299 steps", flush=True)
+    sim.step(299)
+    B0 = sim.fields_numpy()[3:6].copy()
+    g = oracle.Grid(128, 128, 128, wl.dt, xbc=1)
+    _sampled_step_check(sim, g, -1.0, 3, (128, 128, 128),
+                        1e-12 if precision == "fp64" else 2e-6, nsample=1500)
+    F = sim.fields_numpy()
+    k = (wl.dt - 1.0) / (wl.dt + 1.0)
+    for c in (1, 2):                       # B^y, B^z
+        for wall, inside in ((0, 1), (127, 126)):
+            want = B0[c][:, :, inside] + k * (F[3 + c][:, :, inside] - B0[c][:, :, wall])
+            assert np.max(np.abs(F[3 + c][:, :, wall] - want)) <= 1e-15 * max(1e-30, np.max(np.abs(want))) + 1e-300
+    assert np.max(np.abs(F[5][:, :, 120:127])) > 0.3 * omega      # the laser is at the right wall
+    assert np.all(F[1:4, :, :, 127] == 0.0)
+    d = sim.diagnostics()
+    if precision == "fp64":
+        assert d["gauss_abs"] <= 300 * 16 * np.finfo(np.float64).eps * np.max(np.abs(F[0:3])), d
+    else:
+        assert d["gauss_rel"] <= 1e-6, d
+    assert d["nonfinite"] == 0
