@@ -407,7 +407,7 @@ def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int 
     grid_only.step(1)
     t_grid = time.perf_counter() - t0
     del grid_only
-    t_step, ns = _oracle_sample_step(wl, sample_n, order, interp)
+    t_step, ns = _oracle_sample_step(wl, sample_n, order, interp, xbc)
     t_pp = max(t_step - t_grid, 1e-12) / ns
     t_full = t_grid + wl.n_particles * t_pp
     out = {"value": round(wl.n_particles / t_full, 1), "unit": "particle-steps/s", "cores": 1,
@@ -418,11 +418,11 @@ def cpu_baseline(wl, min_seconds: float = 10.0, max_steps: int = 12, order: int 
                      f"({wl.n_particles} particles) = N / (grid time + N x per-particle time), "
                      f"serial C oracle, order {order} 1/2, {interp} interpolation, {host}"}
     if all_cores:
-        out["all_cores"] = cpu_all_cores(wl, t_grid, sample_n, order, interp)
+        out["all_cores"] = cpu_all_cores(wl, t_grid, sample_n, order, interp, xbc=xbc)
     return out
 
 
-def _oracle_sample_step(wl, sample_n, order, interp):
+def _oracle_sample_step(wl, sample_n, order, interp, xbc=0):
     """One oracle step of the full grid with sample_n electrons (and as many
     ions when they move) drawn from the workload's distributions: (seconds,
     particles stepped)."""
@@ -439,7 +439,7 @@ def _oracle_sample_step(wl, sample_n, order, interp):
     return time.perf_counter() - t0, ns
 
 
-def cpu_all_cores(wl, t_grid, sample_n, order, interp, procs=None):
+def cpu_all_cores(wl, t_grid, sample_n, order, interp, procs=None, xbc=0):
     """The serial oracle on every host core at once: one child process per
     core (at most 16), each stepping its own sample as the serial leg does.
     The particles of a step are independent, so P copies stepping P samples
@@ -451,7 +451,7 @@ def cpu_all_cores(wl, t_grid, sample_n, order, interp, procs=None):
     procs = procs or max(1, min(16, os.cpu_count() or 1))
     code = (f"import json, sys; sys.path.insert(0, {ROOT!r}); import bench, picgen; "
             f"wl = picgen.WORKLOADS[{wl.name!r}]; "
-            f"t, ns = bench._oracle_sample_step(wl, {sample_n}, {order}, {interp!r}); "
+            f"t, ns = bench._oracle_sample_step(wl, {sample_n}, {order}, {interp!r}, {xbc}); "
             f"print(json.dumps({{'t': t, 'ns': ns}}))")
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
     t0 = time.perf_counter()
