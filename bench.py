@@ -497,8 +497,9 @@ def main(argv=None):
     ap.add_argument("--interp", choices=["alternating", "conventional"], default="alternating",
                     help="field interpolation: the alternating-order form factor, or the conventional "
                          "uniform order of Eq. wrong1 (the comparison of Section 5; FP64, order 1)")
-    ap.add_argument("--xbc", choices=["periodic", "open"], default="periodic",
-                    help="x boundary: periodic, or open (Mur walls, particles absorbed near them)")
+    ap.add_argument("--xbc", choices=["periodic", "open"], default=None,
+                    help="x boundary: periodic, or open (Mur walls, particles absorbed near them); "
+                         "default: the workload's own (open for the 128^3 slab with the laser)")
     ap.add_argument("--every", type=int, default=None,
                     help="checkpoint spacing of --adjoint (default: 20 for the differentiable 2D3V "
                          "workload, its stated spacing; otherwise a tape of every step when it fits "
@@ -557,6 +558,8 @@ def main(argv=None):
 
     import picgen
     wl = picgen.WORKLOADS[args.workload or DEFAULT_WORKLOAD]
+    if args.xbc is None:
+        args.xbc = wl.xbc
     head = HEADLINE_PRECISION.get(wl.name, "fp64")
     other = "fp64" if head == "fp32c" else "fp32c"
     precs = [head, other] if args.precision == "both" else [args.precision]

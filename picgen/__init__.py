@@ -43,6 +43,7 @@ class Workload:
     ion_mass: float = 100.0
     ion_w_th: float = 0.005
     source: tuple = None   # (plane, amplitude, omega, ramp time): +x E^y plane wave
+    xbc: str = "periodic"  # x boundary: "periodic", or "open" (absorbing walls)
     seed: int = BASE_SEED
 
     @property
@@ -83,7 +84,7 @@ WORKLOADS = {
     "3d_128cube_slab": Workload("3d_128cube_slab", 128, 128, 128, 3, 0.45, 16, (0.01,) * 3,
                                 0.1 * 2 * math.pi / 20.0, 200, sort_every=10, slab=(32, 96),
                                 source=(8, 2 * math.pi / 20.0, 2 * math.pi / 20.0, 20.0),
-                                seed=BASE_SEED + 3),
+                                xbc="open", seed=BASE_SEED + 3),
     "2d3v_256sq_beams": Workload("2d3v_256sq_beams", 256, 256, 1, 2, 0.5, 16, (0.02,) * 3, 0.02,
                                  200, drift=0.2, bext=(0.0, 0.0, 0.02), sort_every=20,
                                  seed=BASE_SEED + 4),

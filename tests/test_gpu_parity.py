@@ -786,7 +786,8 @@ def test_plane_wave_source_vacuum_matches_oracle():
 def test_slab_with_laser_parity(precision):
     """The slab workload at reduced size (48 x 16 x 16 cells, electrons at 8 per
     cell in x in [12, 36), cold, immobile ions) with the laser plane at x = 4:
-    40 steps against the oracle."""
+    40 steps against the oracle, in a periodic box (the open x form is in
+    test_gpu_open_x.py)."""
     wl = picgen.WORKLOADS["3d_128cube_slab"].scaled(nx=48, ny=16, nz=16, ppc=8, slab=(12, 36),
                                                    steps=40, sort_every=10)
     omega = 2 * math.pi / 20
@@ -812,7 +813,8 @@ def test_128cube_slab_laser_fullsize_sampled(precision):
     (16,777,216 electrons), w_th = 0.01 c, a0 = 1 laser of 20-cell wavelength
     from the plane x = 8 with a one-period sin^2 ramp.  After 60 steps the
     wave has entered the plasma; one more step is checked on a sample against
-    the oracle, and the Gauss drift over the grid."""
+    the oracle, and the Gauss drift over the grid.  The box is periodic here;
+    the workload's own open x walls are in test_gpu_open_x.py."""
     wl = picgen.WORKLOADS["3d_128cube_slab"]
     omega = 2 * math.pi / 20
     src = (8, omega, omega, 20.0)
