@@ -283,3 +283,37 @@ def test_128cube_slab_laser_open_x_fullsize(precision):
     else:
         assert d["gauss_rel"] <= 1e-6, d
     assert d["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_open_x_checkpoint_restore_continue(precision, tmp_path):
+    """Save an open-boundary run after 10 steps, restore it into a fresh
+    context and continue 10 steps: the same fields, particles and absorbed
+    set as 20 steps straight, up to the summation order of the atomics.
+    Electrons are absorbed before and after the checkpoint."""
+    import torch
+    from paper_1101_0809_amd import Sim
+    wl = _beams(24, 12, 12, 3, 4, 20, 6)
+    e = picgen.electrons(wl)
+    sim = _sim(nx=24, ny=12, nz=12, dt=wl.dt, dims=3, precision=precision, sort_every=6, xbc="open")
+    s = sim.add_species(e.q, e.m, e.n)
+    sim.load(s, e.x, e.w, e.weight)
+    sim.step(10)
+    n_half = np.count_nonzero(sim.particles(0)[2] == 0)
+    path = tmp_path / "ckpt.pt"
+    torch.save(sim.state_dict(), path)
+    sim.step(10)
+    ref_f = sim.fields_numpy()
+    ref_x, ref_w, ref_wt, _ = sim.particles(0)
+    sim2 = Sim.from_state_dict(torch.load(path, weights_only=True))
+    assert sim2.desc.xbc == 1
+    sim2.step(10)
+    f = sim2.fields_numpy()
+    x, w, wt, _ = sim2.particles(0)
+    assert 0 < n_half < np.count_nonzero(ref_wt == 0)
+    assert np.array_equal(wt == 0, ref_wt == 0)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for c in range(6):
+        assert _rel(f[c], ref_f[c]) < tol
+    assert np.max(np.abs(w - ref_w)) < tol * np.max(np.abs(ref_w))
+    assert np.max(np.abs(_wrapdiff(x, ref_x, np.array([[24], [12], [12]])))) < tol * 24
