@@ -18,13 +18,13 @@ def _sim(**kw):
     return Sim(**kw)
 
 
-def _loaded(nx, ny, nz, n, seed, precision):
+def _loaded(nx, ny, nz, n, seed, precision, xbc="periodic"):
     wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz, w_th=(0.3, 0.3, 0.3))
     rng = np.random.Generator(np.random.PCG64(seed))
     x = np.stack([rng.uniform(0, m, n) for m in (nx, ny, nz)])
     w = rng.normal(0.0, 0.3, (3, n))
     weight = np.full(n, wl.weight)
-    sim = _sim(nx=nx, ny=ny, nz=nz, dt=wl.dt, dims=3, precision=precision, sort_every=4)
+    sim = _sim(nx=nx, ny=ny, nz=nz, dt=wl.dt, dims=3, precision=precision, sort_every=4, xbc=xbc)
     s = sim.add_species(-1.0, 1.0, n)
     sim.load(s, x, w, weight)
     si = sim.add_species(1.0, 100.0, 0, mobile=False)
@@ -44,19 +44,21 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
-def test_static_diagnostics_match_workspace_diagnostics(precision):
+@pytest.mark.parametrize("xbc", ["periodic", "open"])
+def test_static_diagnostics_match_workspace_diagnostics(precision, xbc):
     """Two contexts in turn: 40x32x24 cells with 30,000 electrons, then
     12x10x9 with 1,500.  Each call of the static entry point equals
     pic_diagnostics on the same state; in the second context the static call
-    comes first, so it also captures the Gauss reference R^0."""
-    big = _loaded(40, 32, 24, 30000, 1, precision)
+    comes first, so it also captures the Gauss reference R^0.  With open x
+    walls both take the Gauss drift and div B over the same interior ranges."""
+    big = _loaded(40, 32, 24, 30000, 1, precision, xbc)
     big.step(5)
     ref = big.diagnostics()
     got = big.diagnostics_static()
     _same(got, ref)
     assert got["field_e"] > 0.0
     big.close()
-    small = _loaded(12, 10, 9, 1500, 2, precision)
+    small = _loaded(12, 10, 9, 1500, 2, precision, xbc)
     small.step(3)
     got = small.diagnostics_static()      # R^0 captured through the static scratch
     ref = small.diagnostics()
