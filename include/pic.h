@@ -125,7 +125,9 @@ typedef struct pic_grid_desc {
      * particle whose step ends within PIC_ABSORB cells of a wall
      * (x < PIC_ABSORB or x >= nx - 1 - PIC_ABSORB) is absorbed: its weight
      * becomes zero once its current of that step is deposited, and it
-     * moves on as a particle without charge.  With 1 the Gauss drift of
+     * moves on as a particle without charge (pic_get_particles returns it
+     * with weight 0; pic_load_particles takes weights > 0 only, so a caller
+     * moving particles to another context leaves such ones out).  With 1 the Gauss drift of
      * pic_diagnostics covers cells PIC_ABSORB + 1 .. nx - 3 - PIC_ABSORB along
      * x (those no absorbed charge reaches) and div B the nodes 1 .. nx - 2.
      * Needs nx >= 8, the alternating order 1 1/2 with B carried, and a source
