@@ -337,8 +337,9 @@ __device__ __forceinline__ void stage_fields3(const GridK& g, const int T0[3], c
 }
 
 // Flush the LDS current tile of a 3D tile into the grid's J: 16 lanes per
-// row of the tile, one x column each (the padding is never written); only
-// the non-zero entries take a global atomic.
+// row of the tile, one x column each (the padding is never written); the
+// columns of a row beyond 16 (FP32 mode's wider margin) follow, one (row,
+// column) pair per thread.  Only the non-zero entries take a global atomic.
 template <class R, int NT, class LJT>
 __device__ __forceinline__ void flush_current3(const GridK& g, const int T0[3], const LJT& sj,
                                                double* __restrict__ Jg, bool small)
@@ -349,23 +350,31 @@ __device__ __forceinline__ void flush_current3(const GridK& g, const int T0[3], 
     constexpr int NJ = TL::NJ;
     constexpr int RPP = NT / 16;
     constexpr int NROWS = 3 * LJY * LJY;  // (component, plane, row)
-    static_assert(LJX <= 16 && NT % 64 == 0, "a current-tile row fits 16 lanes");
+    constexpr int XT = LJX > 16 ? LJX - 16 : 0;  // columns beyond the 16-lane rows
+    static_assert(LJX <= 32 && NT % 64 == 0, "a current-tile row fits 16 lanes plus a tail");
     const int64_t N = g.ncell;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     auto wr = [&](int v, int n) { return small ? wrapi(v, n) : wrap1(v, n); };
-    const int lx = (int)threadIdx.x & 15;
-    const int gx = wr(T0[0] - 2 - MX + (lx < LJX ? lx : 0), nx);
-    for (int r = lx < LJX ? (int)threadIdx.x >> 4 : NROWS; r < NROWS; r += RPP) {
+    auto one = [&](int r, int lx, int gx) {
         const int comp = r / (LJY * LJY);
         const int rr = r - comp * (LJY * LJY);
         const int lz = rr / LJY;
         const int ly = rr - lz * LJY;
         const double v = sj.get(comp * NJ + lz * SJZ + ly * SJY + lx);
-        if (v == 0.0) continue;
+        if (v == 0.0) return;
         const int gy = wr(T0[1] - 2 - M + ly, ny);
         const int gz = wr(T0[2] - 2 - M + lz, nz);
         global_add(&Jg[comp * N + ((int64_t)gz * ny + gy) * nx + gx], v);
-    }
+    };
+    const int lx = (int)threadIdx.x & 15;
+    const int gx = wr(T0[0] - 2 - MX + (lx < LJX ? lx : 0), nx);
+    for (int r = lx < LJX ? (int)threadIdx.x >> 4 : NROWS; r < NROWS; r += RPP) one(r, lx, gx);
+    if (XT > 0)
+        for (int e = threadIdx.x; e < NROWS * XT; e += NT) {
+            const int r = e / (XT > 0 ? XT : 1);
+            const int cx = 16 + (e - r * XT);
+            one(r, cx, wr(T0[0] - 2 - MX + cx, nx));
+        }
 }
 
 // Position of cell i0 relative to the tile at T0, periodic-corrected; true if

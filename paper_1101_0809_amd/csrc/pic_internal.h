@@ -39,8 +39,8 @@ struct Tile3<double> {
 };
 template <>
 struct Tile3<float> {
-    static constexpr int MX = 2, M = 1;
-    static constexpr int FROW = 16, FPLANE = 200, JROW = 16, JPLANE = 232;
+    static constexpr int MX = 3, M = 1;
+    static constexpr int FROW = 18, FPLANE = 216, JROW = 18, JPLANE = 280;
 };
 template <class R>
 struct Tile3Dims : Tile3<R> {

@@ -227,9 +227,11 @@ def test_3d_ragged_tiles_parity(precision, tols):
                                              ("fp32c", (1e-3, 1e-5, 1e-6))])
 def test_3d_migrants_and_full_buckets_parity(precision, tols):
     """A beam at w_x = 1 (0.32 cells per step) that is sorted only when loaded:
-    most electrons leave their sorted tile's region (the immobile ions left
-    behind pull the beam back) and are advanced by the migrant pass of the
-    tile they moved into.  The species' capacity equals its
+    after 18 steps a large share of the electrons is beyond their sorted
+    tile's region (the immobile ions left behind pull the beam back; the
+    oracle's trajectories put 38% of the next 4 steps' updates there in FP32
+    mode, whose region is widest) and is advanced by the migrant pass of the
+    tile it moved into.  The species' capacity equals its
     count, so each of the 16 tiles' buckets holds a quarter of the particles,
     and the two tiles the beam (y < 8) enters overflow: their extra migrants
     take the global-memory path.  Against the oracle."""
@@ -248,9 +250,9 @@ def test_3d_migrants_and_full_buckets_parity(precision, tols):
     st = oracle.State(oracle.Grid(nx, ny, nz, 0.45),
                       [oracle.Species(x, w, weight, q=-1.0, m=1.0),
                        oracle.Species(x, np.zeros_like(w), weight, q=1.0, m=100.0, mobile=False)])
-    sim.step(14)
-    st.step(14)
-    sim.step(4)   # statistics of the last call: most of the beam is beyond its tiles' regions
+    sim.step(18)
+    st.step(18)
+    sim.step(4)   # statistics of the last call: much of the beam is beyond its tiles' regions
     st.step(4)
     mig, fb = sim.migrant_fraction(), sim.fallback_fraction()
     assert mig > 0.3 and fb > 0.0, (mig, fb)
@@ -261,14 +263,16 @@ def test_3d_migrants_and_full_buckets_parity(precision, tols):
 @pytest.mark.parametrize("precision,tols", [("fp64", (1e-12, 1e-12, 1e-12)),
                                              ("fp32c", (1e-3, 1e-5, 1e-6))])
 def test_3d_tile_margin_along_x(precision, tols):
-    """The tile region's margin along x: 2 cells in FP32 mode, 1 in FP64.  A
+    """The tile region's margin along x: 3 cells in FP32 mode, 1 in FP64.  A
     light beam (its own field negligible) starts in the last x cell of its
     tile (x in [7.15, 7.25)) at w_x = 1 (0.318 cells per step; a transverse
     spread of 0.01 makes every field component physical) and is sorted
     only when loaded.  Steps 7 and 8 start with every particle in cell 9, two
     cells past its tile: inside the FP32 region, so no particle is a migrant;
     outside the FP64 one, so every particle is (the capacity leaves room in
-    the one bucket they all enter).  Against the oracle."""
+    the one bucket they all enter).  Steps 11 and 12 start in cell 10, the
+    FP32 region's last; steps 14 and 15 in cell 11, past it, where every
+    particle is a migrant in both modes.  Against the oracle."""
     rng = np.random.Generator(np.random.PCG64(4343))
     nx, ny, nz, n = 32, 16, 16, 2000
     x = np.stack([7.15 + 0.1 * rng.random(n), 8.0 * rng.random(n), 8.0 * rng.random(n)])
@@ -294,6 +298,22 @@ def test_3d_tile_margin_along_x(precision, tols):
         assert mig == 0.0, mig
     else:
         assert mig > 0.99, mig
+    sim.step(2)   # steps 9 and 10: the beam enters cell 10
+    st.step(2)
+    assert np.all(np.floor(sim.particles(0)[0][0]) == 10.0)
+    sim.step(2)   # steps 11 and 12 start in cell 10
+    st.step(2)
+    mig = sim.migrant_fraction()
+    if precision == "fp32c":
+        assert mig == 0.0, mig
+    else:
+        assert mig > 0.99, mig
+    sim.step(1)   # step 13: the beam enters cell 11
+    st.step(1)
+    assert np.all(np.floor(sim.particles(0)[0][0]) == 11.0)
+    sim.step(2)   # steps 14 and 15 start in cell 11, past every region
+    st.step(2)
+    assert sim.migrant_fraction() > 0.99
     wl = picgen.WORKLOADS["3d_64cube_8ppc"].scaled(nx=nx, ny=ny, nz=nz)
     _compare(sim, st, wl, *tols)
 
@@ -529,7 +549,7 @@ def test_sort_order(dims, precision):
     of the loaded ones.  Inside a 3D tile of n_t particles, slot s holds a
     particle of lane class s mod C (C = 16 FP64, 32 FP32; the class of tile
     cell l is its field-tile base index mod C: ((lx+2) + 14 (ly+2) + 168 (lz+2))
-    in FP64, ((lx+3) + 16 (ly+2) + 200 (lz+2)) in FP32) in as many slots as the
+    in FP64, ((lx+4) + 18 (ly+2) + 216 (lz+2)) in FP32) in as many slots as the
     class counts allow -- sum over classes of min(count, rows of the column) --
     those slots form the first rows of each column, and down a column the
     cells follow their (lz, ly) row order.  Inside a 2D tile: rank levels in
@@ -558,7 +578,7 @@ def test_sort_order(dims, precision):
         if precision == "fp64":
             C, cls = 16, ((lx + 2) + 14 * (ly + 2) + 168 * (lz + 2)) % 16
         else:
-            C, cls = 32, ((lx + 3) + 16 * (ly + 2) + 200 * (lz + 2)) % 32
+            C, cls = 32, ((lx + 4) + 18 * (ly + 2) + 216 * (lz + 2)) % 32
         row_order = lz * T + ly
         for t in np.unique(tile):
             sel = np.flatnonzero(tile == t)
