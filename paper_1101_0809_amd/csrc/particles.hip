@@ -600,6 +600,8 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     const int T0[3] = {tx * T, ty * T, tz * T};
     const bool small = g.n[0] < LJX || g.n[1] < LJY || g.n[2] < LJY;
     const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int64_t begin = a.tile_start[tile], end = a.tile_start[tile + 1];
+    if (begin == end) return;  // no particle: nothing to stage, deposit or count (the whole workgroup)
 
     // 1. stage E^n and B^n (B^n from bfield) into LDS
     stage_fields3<R, NT>(g, T0, fields, bfield, sf, small);
@@ -617,7 +619,6 @@ __global__ __launch_bounds__(NT) void k_particle_step3(GridK g, StepArgs a, cons
     }
     __syncthreads();
 
-    const int64_t begin = a.tile_start[tile], end = a.tile_start[tile + 1];
     const int nt = (int)(end - begin);
     const unsigned capc = (unsigned)(nt / (4 * CJ));
     uint32_t* qmap = (uint32_t*)a.qmap + begin;
