@@ -28,8 +28,10 @@ constexpr int kTile2 = 16;
 // modulo 32, so the field base index and the current base index of a cell have
 // the same residue: the cell's lane class, shared by the sort (which places
 // particles by class) and the kernel.  FP32 mode stores its field tile in
-// FP32, which leaves room for a margin of 2 along x: fewer particles leave
-// their tile's region between sorts when they drift along x.
+// FP32, which leaves room for a margin of 3 along x: fewer particles leave
+// their tile's region between sorts when they drift along x.  Its rows of 18
+// and planes of 216 and 280 spread a tile's cells evenly over the 32 lane
+// classes and keep a gather stencil within one LDS base register's reach.
 template <class R>
 struct Tile3;
 template <>
