@@ -1,7 +1,7 @@
 """CPU checks of bench.py's oracle leg: the serial full-step form, the
 sampled form and its every-core variant all run, periodic and with the open
-x boundary, on a small named workload.  The timed GPU legs need a GPU and are
-covered by the round-end bench run."""
+x boundary, on a small named workload.  The timed GPU legs need a GPU and run
+only in bench.py itself."""
 import pytest
 
 import bench
